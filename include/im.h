@@ -1,0 +1,227 @@
+/*
+ * im.h -- C ABI of the MI355X influence-maximization hot path.
+ *
+ * Reverse influence sampling of random reverse-reachable (RRR) sets under the
+ * Independent Cascade (IC) and Linear Threshold (LT) models, and seed
+ * selection by maximum k-cover over them: standard greedy, the RandGreedi
+ * split into per-partition local greedy plus a streaming threshold-bucket
+ * cover with optional truncation, and the IMM driver around them.  The method
+ * is that of "GreediRIS: Scalable Influence Maximization using Distributed
+ * Streaming Maximum Cover" (Barik et al., arXiv 2408.10982); each entry point
+ * names the passage that defines its operation.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked [device] are HIP device memory owned by the caller;
+ *    pointers marked [host] are host memory owned by the caller.  The library
+ *    never frees caller memory.  It keeps private device scratch per
+ *    (device, stream) that grows on demand and is released by im_release().
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it; entry points that return a host-side value (sizes, counts)
+ *    synchronise that stream before returning, and say so.
+ *  - Errors are status codes; nothing is thrown across the ABI.  IM_EINVAL is
+ *    returned before any device work is enqueued or any output is written.
+ *  - Calls that share one stream run in order.  Calls on different streams
+ *    use different scratch and may overlap; they must not write the same
+ *    caller buffers.
+ *  - All arithmetic on the device is integer.  The only floating-point steps
+ *    (IMM sample-size bounds, streaming bucket thresholds) run on the host in
+ *    fp64 with a fixed operation order.
+ *
+ * Random numbers.  Every random quantity is one 32-bit word of Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed lo, seed hi) and counter
+ * (id >> 2, sample id, domain tag, stream tag), word id & 3.  Domain tags:
+ * root 0, IC edge 1, LT vertex 2, partition 3.  A draw depends only on its
+ * ids, so results do not depend on launch shape or on how samples are split
+ * (the property the paper's Leap-Frog generator provides, Sec. 3.2).
+ */
+#ifndef IM_H
+#define IM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IM_OK = 0,
+  IM_EINVAL = -1,  /* invalid argument; nothing was enqueued or written */
+  IM_ERANGE = -2,  /* output capacity too small; the needed size is returned */
+  IM_ENOMEM = -3,  /* device scratch allocation failed */
+  IM_EDEVICE = -4  /* a HIP call failed (the HIP error is in im_last_error()) */
+} im_status;
+
+typedef enum { IM_IC = 0, IM_LT = 1 } im_model;
+
+typedef enum { IM_SEL_GREEDY = 0, IM_SEL_GREEDIRIS = 1 } im_selector;
+
+/* A graph prepared for sampling.  The in-edge CSR lists, for every vertex v,
+ * the edges u -> v as in_src[in_off[v] .. in_off[v+1]); edge id e is the
+ * position in that array.  thr[e] comes from im_prepare_graph. */
+typedef struct {
+  int32_t n;               /* vertices, 1 <= n < 2^31 */
+  int64_t num_edges;       /* E, 0 <= E < 2^31 */
+  const int32_t* in_off;   /* [device] n+1, non-decreasing, in_off[0]=0, in_off[n]=E */
+  const int32_t* in_src;   /* [device] E, each in [0, n) */
+  const uint32_t* thr;     /* [device] round_up(E, 4) entries from im_prepare_graph */
+  int32_t model;           /* IM_IC or IM_LT, as given to im_prepare_graph */
+} im_graph;
+
+/* Sampling statistics of one im_sample_rrr call (exact, deterministic). */
+typedef struct {
+  int64_t total;           /* sum of set sizes */
+  int64_t examined;        /* IC: in-edges examined; LT: binary-search probes
+                              charged as ceil(log2(indeg+1)) per expanded vertex */
+  int64_t live;            /* IC: live in-edges found; LT: in-edges taken */
+  int64_t large_sets;      /* sets that took the large-set path (diagnostic) */
+} im_sample_stats;
+
+/* Library version string. */
+const char* im_version(void);
+/* Text of the last HIP error seen by the calling thread ("" if none). */
+const char* im_last_error(void);
+/* Releases the library's device scratch for every stream of the current
+ * device.  The caller must ensure no call is in flight. */
+int im_release(void);
+
+/*
+ * Graph ingest (Sec. 2: the IC and LT diffusion models).
+ * weight[e] is the IC probability p(u,v) in [0,1], or the LT weight w(u,v) >= 0
+ * (the model assumes the in-weights of a vertex sum to 1).  Writes thr:
+ *  IC: thr[e] = p >= 1 ? 0xFFFFFFFF : floor(p * 2^32); edge e of sample i is
+ *      live iff thr[e] == 0xFFFFFFFF or draw(edge, i, e) < thr[e].
+ *  LT: q_e = w >= 1 ? 2^32 : floor(w * 2^32); thr[e] = min(sum of q over the
+ *      in-edges of v up to and including e, 0xFFFFFFFF) (live-edge reading of
+ *      LT: v keeps in-edge e with probability w_e, none with 1 - sum w).
+ *  thr[E .. round_up(E,4)) is written 0.
+ * in_off [device] n+1; in_src [device] E; weight [device] E fp32;
+ * thr [device] round_up(E,4).  Synchronises `stream`; returns IM_EINVAL if
+ * in_off is not a valid CSR offset array (nothing else is then read), or if a
+ * source id is outside [0,n), or a weight is NaN, negative, infinite, or (IC)
+ * above 1 (thr is then partly written and must not be used).
+ */
+int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off, const int32_t* in_src,
+                     const float* weight, int32_t model, uint32_t* thr, void* stream);
+
+/*
+ * RRR sampling (Def. 2.3 and Sec. 2.1; Alg. 1 Sample, Alg. 3 sampling step).
+ * Generates the sets of sample ids [first, first+count) of (seed, stream_tag):
+ *  root_i = floor(draw(root, i) * n / 2^32) (uniform over V);
+ *  IC: R(i) = vertices with a path to root_i over edges live in sample i;
+ *  LT: R(i) = the chain root_i <- u1 <- u2 ... where each vertex keeps the
+ *      first in-edge e with draw(vertex, i, v) < thr[e] (or thr[e] saturated),
+ *      ending at a vertex that keeps none or at a repeated vertex.
+ * Output (sample-major CSR, canonical): off [device] count+1 int64 with
+ * off[0] = 0; mem [device] capacity int32, set j = sample first+j occupies
+ * mem[off[j] .. off[j+1]) with members strictly ascending.
+ * *total [host] receives the sum of set sizes.  If it exceeds capacity the
+ * call returns IM_ERANGE, off is written, mem is left undefined, and a repeat
+ * with capacity >= *total returns bit-identical output.  stats [host] may be
+ * NULL.  first + count <= 2^32.  Synchronises `stream`.
+ */
+int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t first,
+                  int64_t count, int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
+                  im_sample_stats* stats, void* stream);
+
+/*
+ * Covering subsets (Sec. 3.2; Alg. 3 per-vertex step): S(v) = {j : v in R(j)}
+ * for the count sets in (off, mem), j local indices in [0, count).
+ * inc_off [device] n+1 int64; inc_mem [device] off[count] int32.  The order of
+ * the ids inside one S(v) is unspecified (S(v) is a set).  Asynchronous.
+ */
+int im_build_incidence(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
+                       int64_t total, int64_t* inc_off, int32_t* inc_mem, void* stream);
+
+/*
+ * Standard greedy max-k-cover (Sec. 3.2): k times take the vertex v of largest
+ * marginal coverage |S(v) minus covered|, the lowest id on ties; stop early
+ * when the largest gain is 0.  Universe = the count samples.
+ * Inputs from im_sample_rrr / im_build_incidence (total = off[count]).
+ * seeds [device] k int32 (entries past nsel set to -1); gains [device] k int64
+ * (0 past nsel); nsel [device] 1 int32; coverage [device] 1 int64 = C(S).
+ * Asynchronous.
+ */
+int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
+                    int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,
+                    int32_t* seeds, int64_t* gains, int32_t* nsel, int64_t* coverage,
+                    void* stream);
+
+/*
+ * RandGreedi local step (Alg. 3 partition step; Alg. 4 lines 1-2; Sec. 3.4 S3).
+ * Partitions V uniformly at random into m parts, part(v) = floor(draw(part,
+ * v) * m / 2^32) with key part_seed, and runs the standard greedy above on
+ * every part p with candidates V_p and the full universe, all m in one
+ * launch, recording all k picks.  part [device] n uint8 (written);
+ * lseeds [device] m*k int32, row p = part p's picks in order, -1 past
+ * lcount[p]; lgains [device] m*k int64; lcount [device] m int32;
+ * lcover [device] m int64 = C(S_p).  1 <= m <= 256.  Asynchronous.
+ */
+int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
+                  int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,
+                  int32_t m, uint64_t part_seed, uint8_t* part, int32_t* lseeds, int64_t* lgains,
+                  int32_t* lcount, int64_t* lcover, void* stream);
+
+/*
+ * Streaming max-k-cover at the receiver (Alg. 5), truncation (Sec. 3.3.2) and
+ * the final choice of Alg. 4 (lines 5-6).
+ *  Stream: T = ceil(alpha*k) (clamped to [1,k]); for t < T, for p < m, the
+ *   item lseeds[p][t] if t < lcount[p], carrying the full S(x).
+ *  Buckets: l = max |S(x)| over the stream; B = max(1, ceil(ln k / ln(1+delta)));
+ *   thr_b = ceil(l * (1+delta)^b / (2k)); bucket b takes x iff it holds < k
+ *   seeds and |S(x) minus C_b| >= thr_b; b* = lowest bucket of largest |C_b|.
+ *  Final: S = S_b* if |C_b*| >= max_p lcover[p], else the lowest p of largest
+ *   lcover.
+ * seeds [device] k int32 (-1 past nsel); nsel [device] 1; coverage [device] 1
+ * int64; info [device] 4 int32 = {b*, B, global solution chosen (1/0), stream
+ * length}.  0 < delta < 1/2, 0 < alpha <= 1.  Asynchronous.
+ */
+int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off, const int32_t* inc_mem,
+                    int32_t k, int32_t m, const int32_t* lseeds, const int32_t* lcount,
+                    const int64_t* lcover, double delta, double alpha, int32_t* seeds,
+                    int32_t* nsel, int64_t* coverage, int32_t* info, void* stream);
+
+/* Options of im_solve. */
+typedef struct {
+  int32_t selector;      /* IM_SEL_GREEDY or IM_SEL_GREEDIRIS */
+  int32_t m;             /* partitions (GreediRIS), 1..256 */
+  double delta;          /* bucket spacing (GreediRIS), 0 < delta < 1/2 */
+  double alpha;          /* truncation fraction (GreediRIS), 0 < alpha <= 1 */
+  uint64_t seed;         /* sampling seed */
+  uint64_t part_seed;    /* partition seed (GreediRIS) */
+  int64_t theta;         /* > 0: use this many samples and skip the IMM bound */
+} im_solve_opts;
+
+/* Result of im_solve (host). */
+typedef struct {
+  int32_t nsel;
+  int64_t coverage;            /* C(S) over the final theta samples */
+  int64_t theta;               /* final sample count */
+  int32_t rounds;              /* martingale rounds run */
+  double lower_bound;          /* LB of Alg. 1 (1.0 if never certified) */
+  int64_t martingale_samples;  /* samples drawn in the martingale rounds */
+  int32_t bucket;              /* b* of the last GreediRIS selection, else -1 */
+  int32_t global_won;          /* 1 if the streamed solution won, 0 if local, -1 n/a */
+  int64_t final_total;         /* sum of set sizes of the final samples */
+} im_solve_result;
+
+/*
+ * IMM (Alg. 1), with the sample-size bounds of Tang, Shi and Xiao (2015):
+ * ell = 1 + ln2/ln n; eps' = sqrt(2) eps; lambda' = (2 + 2eps'/3)(ln C(n,k)
+ * + ell ln n + ln log2 n) n / eps'^2; round x = 1 .. floor(log2 n) - 1 uses
+ * theta_x = ceil(2 lambda'/n) * 2^(x-1) samples of stream 0 (earlier samples
+ * kept, Sec. 3.2), selects S_x, and stops with LB = n C(S_x) / (theta_x
+ * (1+eps')) once n C(S_x)/theta_x >= (1+eps') n / 2^x; then theta =
+ * ceil(lambda_star / LB), lambda_star = 2n((1-1/e) a + b)^2/eps^2, a = sqrt(ell ln n +
+ * ln 2), b = sqrt((1-1/e)(ln C(n,k) + ell ln n + ln 2)), and the final seeds
+ * are selected on theta fresh samples of stream 1.  The selector is the
+ * standard greedy or GreediRIS (im_randgreedi + im_stream_cover).
+ * seeds [host] k int32; res [host].  Synchronises `stream`.
+ */
+int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* opts,
+             int32_t* seeds, im_solve_result* res, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IM_H */

@@ -1,0 +1,14 @@
+"""MI355X-native hot path of GreediRIS-style influence maximization.
+
+RRR sampling under IC/LT and max-k-cover seed selection (standard greedy,
+RandGreedi local greedy, streaming bucket cover with truncation, IMM driver),
+as hand-written HIP kernels for gfx950 behind the C ABI in include/im.h.
+This package is the thin Python face of that library.
+"""
+from .binding import (IC, LT, SEL_GREEDIRIS, SEL_GREEDY, EXPORTS, Graph, ImError, RRR,
+                      build_incidence, greedy_cover, lib, prepare_graph, randgreedi, release,
+                      sample_rrr, solve, stream_cover, version)
+
+__all__ = ["IC", "LT", "SEL_GREEDY", "SEL_GREEDIRIS", "EXPORTS", "Graph", "ImError", "RRR",
+           "build_incidence", "greedy_cover", "lib", "prepare_graph", "randgreedi", "release",
+           "sample_rrr", "solve", "stream_cover", "version"]

@@ -1,0 +1,257 @@
+"""ctypes binding of libim.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; this module
+only turns torch tensors (device memory) and torch's current HIP stream into
+the plain pointers the C ABI takes, checks status codes, and sizes outputs.
+If libim.so is missing the import fails: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libim.so")
+
+IM_OK, IM_EINVAL, IM_ERANGE, IM_ENOMEM, IM_EDEVICE = 0, -1, -2, -3, -4
+IC, LT = 0, 1
+SEL_GREEDY, SEL_GREEDIRIS = 0, 1
+
+_STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM",
+           IM_EDEVICE: "IM_EDEVICE"}
+
+# every symbol the header declares
+EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
+           "im_build_incidence", "im_greedy_cover", "im_randgreedi", "im_stream_cover",
+           "im_solve")
+
+
+class ImError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__("%s returned %s%s" % (where, _STATUS.get(status, status),
+                                               (": " + detail) if detail else ""))
+
+
+class _Graph(C.Structure):
+    _fields_ = [("n", C.c_int32), ("num_edges", C.c_int64), ("in_off", C.c_void_p),
+                ("in_src", C.c_void_p), ("thr", C.c_void_p), ("model", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("total", C.c_int64), ("examined", C.c_int64), ("live", C.c_int64),
+                ("large_sets", C.c_int64)]
+
+
+class _SolveOpts(C.Structure):
+    _fields_ = [("selector", C.c_int32), ("m", C.c_int32), ("delta", C.c_double),
+                ("alpha", C.c_double), ("seed", C.c_uint64), ("part_seed", C.c_uint64),
+                ("theta", C.c_int64)]
+
+
+class _SolveResult(C.Structure):
+    _fields_ = [("nsel", C.c_int32), ("coverage", C.c_int64), ("theta", C.c_int64),
+                ("rounds", C.c_int32), ("lower_bound", C.c_double),
+                ("martingale_samples", C.c_int64), ("bucket", C.c_int32),
+                ("global_won", C.c_int32), ("final_total", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libim.so (raises if the HIP library has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libim.so not built: run paper_2408_10982_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, U32, U64, D = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64,
+                                    C.c_double)
+        L.im_version.restype = C.c_char_p
+        L.im_last_error.restype = C.c_char_p
+        L.im_release.argtypes = []
+        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P]
+        L.im_sample_rrr.argtypes = [C.POINTER(_Graph), U64, U32, I64, I64, P, P, I64,
+                                    C.POINTER(C.c_int64), C.POINTER(_Stats), P]
+        L.im_build_incidence.argtypes = [I32, I64, P, P, I64, P, P, P]
+        L.im_greedy_cover.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
+        L.im_randgreedi.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, U64, P, P, P, P, P, P]
+        L.im_stream_cover.argtypes = [I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P, P]
+        L.im_solve.argtypes = [C.POINTER(_Graph), I32, D, C.POINTER(_SolveOpts), P,
+                               C.POINTER(_SolveResult), P]
+        for f in EXPORTS[2:]:
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != IM_OK:
+        detail = lib().im_last_error().decode() if status == IM_EDEVICE else ""
+        raise ImError(status, where, detail)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("expected a contiguous %s device tensor" % dtype)
+    return t
+
+
+@dataclass
+class Graph:
+    """A graph prepared for sampling: in-edge CSR plus integer thresholds."""
+    n: int
+    num_edges: int
+    model: int
+    in_off: torch.Tensor   # int32 [n+1]
+    in_src: torch.Tensor   # int32 [E]
+    thr: torch.Tensor      # int32 storage of uint32 thresholds, [round_up(E, 4)]
+
+    def struct(self) -> _Graph:
+        return _Graph(self.n, self.num_edges, self.in_off.data_ptr(),
+                      self.in_src.data_ptr() if self.num_edges else None,
+                      self.thr.data_ptr(), self.model)
+
+    def hbm_bytes(self) -> int:
+        return 4 * (self.in_off.numel() + self.in_src.numel() + self.thr.numel())
+
+
+def prepare_graph(in_off, in_src, weight, model: int, device="cuda", stream=None) -> Graph:
+    """Uploads an in-edge CSR with fp32 weights and derives the thresholds."""
+    in_off = torch.as_tensor(in_off, dtype=torch.int32).to(device).contiguous()
+    in_src = torch.as_tensor(in_src, dtype=torch.int32).to(device).contiguous()
+    weight = torch.as_tensor(weight, dtype=torch.float32).to(device).contiguous()
+    n = in_off.numel() - 1
+    E = in_src.numel()
+    thr = torch.empty(max((E + 3) // 4 * 4, 4), dtype=torch.int32, device=device)
+    st = lib().im_prepare_graph(n, E, _ptr(in_off), _ptr(in_src) if E else None,
+                                _ptr(weight) if E else None, model, _ptr(thr), _stream(stream))
+    _check(st, "im_prepare_graph")
+    return Graph(n, E, model, in_off, in_src, thr)
+
+
+@dataclass
+class RRR:
+    off: torch.Tensor   # int64 [count+1]
+    mem: torch.Tensor   # int32 [total]
+    total: int
+    examined: int
+    live: int
+    large_sets: int
+
+    @property
+    def count(self) -> int:
+        return self.off.numel() - 1
+
+
+def sample_rrr(g: Graph, seed: int, stream_tag: int, first: int, count: int,
+               capacity: int | None = None, stream=None) -> RRR:
+    off = torch.empty(count + 1, dtype=torch.int64, device=g.in_off.device)
+    cap = int(capacity) if capacity is not None else max(4 * count, 1024)
+    gs = g.struct()
+    for _ in range(2):
+        mem = torch.empty(max(cap, 1), dtype=torch.int32, device=g.in_off.device)
+        total = C.c_int64()
+        stats = _Stats()
+        st = lib().im_sample_rrr(C.byref(gs), seed, stream_tag, first, count, _ptr(off),
+                                 _ptr(mem), cap, C.byref(total), C.byref(stats), _stream(stream))
+        if st == IM_ERANGE:
+            cap = int(total.value)
+            continue
+        _check(st, "im_sample_rrr")
+        return RRR(off, mem[:total.value], int(total.value), int(stats.examined),
+                   int(stats.live), int(stats.large_sets))
+    raise ImError(IM_ERANGE, "im_sample_rrr")
+
+
+def build_incidence(n: int, rrr: RRR, stream=None):
+    inc_off = torch.empty(n + 1, dtype=torch.int64, device=rrr.off.device)
+    inc_mem = torch.empty(max(rrr.total, 1), dtype=torch.int32, device=rrr.off.device)
+    st = lib().im_build_incidence(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
+                                  _ptr(inc_off), _ptr(inc_mem), _stream(stream))
+    _check(st, "im_build_incidence")
+    return inc_off, inc_mem[:rrr.total]
+
+
+def greedy_cover(n: int, rrr: RRR, inc_off, inc_mem, k: int, stream=None):
+    """Returns device tensors (seeds int32[k], gains int64[k], nsel int32[1], coverage int64[1])."""
+    dev = rrr.off.device
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    gains = torch.empty(k, dtype=torch.int64, device=dev)
+    nsel = torch.empty(1, dtype=torch.int32, device=dev)
+    cov = torch.empty(1, dtype=torch.int64, device=dev)
+    st = lib().im_greedy_cover(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
+                               _ptr(inc_off), _ptr(inc_mem), k, _ptr(seeds), _ptr(gains),
+                               _ptr(nsel), _ptr(cov), _stream(stream))
+    _check(st, "im_greedy_cover")
+    return seeds, gains, nsel, cov
+
+
+def randgreedi(n: int, rrr: RRR, inc_off, inc_mem, k: int, m: int, part_seed: int,
+               stream=None):
+    """Returns (part uint8[n], lseeds int32[m,k], lgains int64[m,k], lcount int32[m],
+    lcover int64[m]) on the device."""
+    dev = rrr.off.device
+    part = torch.empty(n, dtype=torch.uint8, device=dev)
+    ls = torch.empty((m, k), dtype=torch.int32, device=dev)
+    lg = torch.empty((m, k), dtype=torch.int64, device=dev)
+    lc = torch.empty(m, dtype=torch.int32, device=dev)
+    lv = torch.empty(m, dtype=torch.int64, device=dev)
+    st = lib().im_randgreedi(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
+                             _ptr(inc_off), _ptr(inc_mem), k, m, part_seed, _ptr(part), _ptr(ls),
+                             _ptr(lg), _ptr(lc), _ptr(lv), _stream(stream))
+    _check(st, "im_randgreedi")
+    return part, ls, lg, lc, lv
+
+
+def stream_cover(n: int, count: int, inc_off, inc_mem, lseeds, lcount, lcover, k: int,
+                 delta: float, alpha: float, stream=None):
+    """Returns device tensors (seeds int32[k], nsel int32[1], coverage int64[1],
+    info int32[4] = (best bucket, buckets, streamed solution chosen, stream length))."""
+    dev = inc_off.device
+    m = lcount.numel()
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    nsel = torch.empty(1, dtype=torch.int32, device=dev)
+    cov = torch.empty(1, dtype=torch.int64, device=dev)
+    info = torch.empty(4, dtype=torch.int32, device=dev)
+    st = lib().im_stream_cover(n, count, _ptr(inc_off), _ptr(inc_mem), k, m, _ptr(lseeds),
+                               _ptr(lcount), _ptr(lcover), delta, alpha, _ptr(seeds),
+                               _ptr(nsel), _ptr(cov), _ptr(info), _stream(stream))
+    _check(st, "im_stream_cover")
+    return seeds, nsel, cov, info
+
+
+def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,
+          delta: float = 0.077, alpha: float = 1.0, seed: int = 0, part_seed: int = 0,
+          theta: int = 0, stream=None) -> dict:
+    o = _SolveOpts(selector, m, delta, alpha, seed, part_seed, theta)
+    res = _SolveResult()
+    seeds = (C.c_int32 * k)()
+    gs = g.struct()
+    st = lib().im_solve(C.byref(gs), k, eps, C.byref(o), seeds, C.byref(res), _stream(stream))
+    _check(st, "im_solve")
+    out = {f: getattr(res, f) for f, _ in _SolveResult._fields_}
+    out["seeds"] = list(seeds)[:res.nsel]
+    return out
+
+
+def release():
+    _check(lib().im_release(), "im_release")
+
+
+def version() -> str:
+    return lib().im_version().decode()

@@ -1,0 +1,157 @@
+// common.h -- shared device helpers and host plumbing of the HIP library.
+//
+// gfx950 (CDNA4): 64-lane wavefronts, 160 KB LDS per CU, 256 CUs.  Nothing
+// here uses matrix cores: every operation on the path is integer graph or
+// set work.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/im.h"
+
+namespace im {
+
+constexpr int kWave = 64;
+
+// Random-number domains and counter layout (key = seed, counter =
+// (id >> 2, sample, tag, stream), word id & 3).
+constexpr uint32_t kTagRoot = 0, kTagEdge = 1, kTagVert = 2, kTagPart = 3;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi_a = __umulhi(0xD2511F53u, c.x), lo_a = 0xD2511F53u * c.x;
+    const uint32_t hi_b = __umulhi(0xCD9E8D57u, c.z), lo_b = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint32_t pick_word(uint4 v, uint32_t w) {
+  return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+}
+
+__device__ __forceinline__ uint32_t draw1(uint64_t seed, uint32_t tag, uint32_t stream,
+                                          uint32_t sample, uint32_t id) {
+  uint4 r = philox4x32_10(make_uint4(id >> 2, sample, tag, stream), (uint32_t)seed,
+                          (uint32_t)(seed >> 32));
+  return pick_word(r, id & 3u);
+}
+
+// floor(r * n / 2^32): maps a uniform word onto [0, n).
+__device__ __forceinline__ uint32_t scale_draw(uint32_t r, uint32_t n) {
+  return (uint32_t)(((uint64_t)r * (uint64_t)n) >> 32);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Orders LDS traffic of one wavefront (the wave's lanes run in lockstep; this
+// keeps the compiler from moving LDS accesses across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T y = __shfl_up(x, d, kWave);
+    if (l >= d) x += y;
+  }
+  return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    uint64_t y = __shfl_xor(x, d, kWave);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Argmax key: larger count first, then lower vertex id.
+__device__ __forceinline__ uint64_t argmax_key(uint32_t count, uint32_t v) {
+  return ((uint64_t)count << 32) | (uint64_t)(0xFFFFFFFFu - v);
+}
+__device__ __forceinline__ uint32_t key_vertex(uint64_t key) {
+  return 0xFFFFFFFFu - (uint32_t)key;
+}
+__device__ __forceinline__ uint32_t key_count(uint64_t key) { return (uint32_t)(key >> 32); }
+
+}  // namespace im
+
+// ----------------------------------------------------------------- host side
+namespace im {
+
+// Per-thread last HIP error text.
+void set_error(hipError_t e, const char* where);
+
+#define IM_HIP(call)                                   \
+  do {                                                 \
+    hipError_t _e = (call);                            \
+    if (_e != hipSuccess) {                            \
+      ::im::set_error(_e, #call);                      \
+      return IM_EDEVICE;                               \
+    }                                                  \
+  } while (0)
+
+#define IM_TRY(call)                 \
+  do {                               \
+    int _s = (call);                 \
+    if (_s != IM_OK) return _s;      \
+  } while (0)
+
+// Grow-only scratch buffers kept per (device, stream, slot).  Returns IM_OK
+// and sets *ptr; contents are undefined on return.
+int scratch(hipStream_t stream, int slot, size_t bytes, void** ptr);
+// Same, and reports whether the buffer was (re)allocated by this call.
+int scratch_fresh(hipStream_t stream, int slot, size_t bytes, void** ptr, bool* fresh);
+
+// Scratch slots (each caller of a slot owns it for the duration of its call).
+enum Slot {
+  kSlotSampleArena = 0,
+  kSlotSampleMeta,
+  kSlotSampleBig,
+  kSlotSampleLtLane,
+  kSlotScan,
+  kSlotIncidence,
+  kSlotGreedy,
+  kSlotLocal,
+  kSlotStream,
+  kSlotSolvePool,
+  kSlotSolveOff,
+  kSlotSolveInc,
+  kSlotSolveIncOff,
+  kSlotSolveOut,
+  kSlotSolveLocal,
+  kSlotCount
+};
+
+struct DeviceInfo {
+  int device;
+  int num_cus;
+};
+int device_info(DeviceInfo* out);
+
+// Exclusive scan of n int64/int32 values into int64 outputs (out[n] = total).
+int exclusive_scan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, hipStream_t s);
+int exclusive_scan_u32_to_i64(const uint32_t* in, int64_t n, int64_t* out, hipStream_t s);
+
+}  // namespace im

@@ -1,0 +1,762 @@
+// sample.hip -- RRR sampling under IC and LT (im_sample_rrr).
+//
+// Definition 2.3 and Sec. 2.1: a sample picks its root uniformly at random
+// and collects every vertex that reaches the root over the edges live in that
+// sample.  IC: every in-edge flips its own coin; the set is explored by a
+// reverse BFS.  LT: every vertex keeps at most one in-edge, so the set is the
+// backward chain from the root.  Draws are keyed by (seed, sample, edge or
+// vertex), so a set does not depend on who computes it or in which order.
+//
+// Work split (MI355X):
+//  * IC small path: one wavefront per sample, persistent over a work counter.
+//    Frontier vertices are expanded 64 at a time; their in-edge lists are cut
+//    into aligned groups of 4 edges (one 16-byte threshold load and one
+//    Philox call per group) and the groups are spread over the lanes.  The
+//    visited set is an open-addressing hash in LDS; the member list doubles
+//    as the BFS queue and is sorted in LDS before it is written.
+//  * A set that outgrows the LDS table is handed, by sample id, to the large
+//    path: one workgroup per sample with a private visited bitmap and queue in
+//    HBM; members come out sorted from the bitmap.
+//  * LT: one lane per walk (walks are sequential chains), lanes refill from
+//    the work counter independently; the visited check is a per-lane hash in
+//    HBM; the kept edge is found by binary search over the inclusive integer
+//    prefix of the in-weights.
+//  * Sets are first written to a staging arena (atomic cursor), then an
+//    exclusive scan of the sizes gives the canonical CSR offsets and a gather
+//    copies (and, for LT, sorts) each set into place.
+#include <algorithm>
+
+#include "common.h"
+
+namespace im {
+
+constexpr int kSmallBlock = 256;            // 4 waves, each its own sample
+constexpr int kSmallH = 512;                // LDS hash slots per wave
+constexpr int kSmallCap = 256;              // members before handing off
+constexpr int kBigBlock = 256;
+constexpr int kBigSortCap = 4096;           // large sets up to this size sort in LDS
+constexpr int kLtH = 2048;                  // per-lane HBM hash slots (LT)
+constexpr int kLtCap = 1024;                // per-lane walk length before handing off
+constexpr int kLtBlock = 256;
+constexpr int kGatherSortCap = kLtCap;      // LT sets sorted by the gather kernel
+constexpr int32_t kEmpty = -1;
+
+struct SampleArgs {
+  int32_t n;
+  const int32_t* __restrict__ in_off;
+  const int32_t* __restrict__ in_src;
+  const uint32_t* __restrict__ thr;
+  uint32_t seed_lo, seed_hi;
+  uint32_t stream;
+  uint32_t first;
+  uint32_t count;
+  int32_t* __restrict__ arena;
+  uint64_t arena_cap;
+  int64_t* __restrict__ start;   // per sample: arena position
+  int32_t* __restrict__ len;     // per sample: size (-1 while on the large path)
+  uint32_t* __restrict__ big_list;
+  unsigned long long* __restrict__ ctr;  // [0] work, [1] cursor, [2] big count,
+                                         // [3] examined, [4] live, [5] big work
+};
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t v, int bits) {
+  return ((uint32_t)v * 2654435761u) >> (32 - bits);
+}
+
+__device__ __forceinline__ uint32_t ceil_log2_plus1(int32_t d) {
+  // ceil(log2(d + 1)) for d >= 1
+  return 32u - (uint32_t)__clz((uint32_t)d);
+}
+
+// ------------------------------------------------------------------ IC small
+struct __align__(16) WaveLds {
+  int32_t hash[kSmallH];
+  int32_t queue[kSmallCap];
+  int32_t pre[kWave];    // inclusive prefix of 4-edge group counts
+  int32_t gbase[kWave];  // group id of a lane's first group minus its prefix start
+  int32_t ea[kWave];     // in-edge range of each frontier vertex
+  int32_t eb[kWave];
+  int32_t tail;
+  int32_t pad[3];
+};
+
+// Inserts u; returns true if it was new.  Gives up (sets *over) once the
+// member count reaches kSmallCap: the hash then holds at most kSmallCap + 63
+// keys, so probing always finds a free slot.
+__device__ __forceinline__ void lds_insert(WaveLds& L, int32_t u, bool* over) {
+  uint32_t h = hash_slot(u, 9);
+  for (;;) {
+    int32_t cur = L.hash[h];
+    if (cur == u) return;
+    if (cur == kEmpty) {
+      if (__atomic_load_n(&L.tail, __ATOMIC_RELAXED) >= kSmallCap) {
+        *over = true;
+        return;
+      }
+      int32_t old = atomicCAS(&L.hash[h], kEmpty, u);
+      if (old == kEmpty) {
+        int32_t pos = atomicAdd(&L.tail, 1);
+        if (pos < kSmallCap)
+          L.queue[pos] = u;
+        else
+          *over = true;
+        return;
+      }
+      if (old == u) return;
+    }
+    h = (h + 1) & (kSmallH - 1);
+  }
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
+  __shared__ WaveLds lds_all[kSmallBlock / kWave];
+  WaveLds& L = lds_all[threadIdx.x / kWave];
+  const int lane = lane_id();
+  unsigned long long w_ex = 0, w_lv = 0;  // per-lane sums of finished sets
+  for (;;) {
+    uint32_t il = 0;
+    if (lane == 0) il = (uint32_t)atomicAdd(&A.ctr[0], 1ull);
+    il = __shfl(il, 0, kWave);
+    if (il >= A.count) break;
+    const uint32_t i = A.first + il;
+    const int32_t root =
+        (int32_t)scale_draw(draw1(((uint64_t)A.seed_hi << 32) | A.seed_lo, kTagRoot, A.stream,
+                                  0u, i),
+                            (uint32_t)A.n);
+    for (int j = lane; j < kSmallH; j += kWave) L.hash[j] = kEmpty;
+    wave_sync();
+    if (lane == 0) {
+      L.hash[hash_slot(root, 9)] = root;
+      L.queue[0] = root;
+      L.tail = 1;
+    }
+    wave_sync();
+    int32_t head = 0, tail = 1;
+    bool over = false;
+    unsigned long long s_ex = 0, s_lv = 0;
+    while (head < tail) {
+      const int32_t nf = min(tail - head, kWave);
+      int32_t a = 0, b = 0, ng = 0;
+      if (lane < nf) {
+        const int32_t v = L.queue[head + lane];
+        a = A.in_off[v];
+        b = A.in_off[v + 1];
+        if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
+        s_ex += (unsigned long long)(b - a);
+      }
+      const int32_t inc = wave_inclusive_scan(ng);
+      const int32_t total = __shfl(inc, kWave - 1, kWave);
+      L.pre[lane] = inc;
+      L.gbase[lane] = (a >> 2) - (inc - ng);
+      L.ea[lane] = a;
+      L.eb[lane] = b;
+      head += nf;
+      wave_sync();
+      for (int32_t base = 0; base < total; base += kWave) {
+        const int32_t gi = base + lane;
+        if (gi < total) {
+          int lo = 0, hi = kWave - 1;  // owner: first lane whose prefix exceeds gi
+          while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (L.pre[mid] > gi)
+              hi = mid;
+            else
+              lo = mid + 1;
+          }
+          const uint32_t g = (uint32_t)(L.gbase[lo] + gi);
+          const int32_t ea = L.ea[lo], eb = L.eb[lo];
+          const uint4 q = reinterpret_cast<const uint4*>(A.thr)[g];
+          const uint4 r = philox4x32_10(make_uint4(g, i, kTagEdge, A.stream), A.seed_lo,
+                                        A.seed_hi);
+          const int32_t e0 = (int32_t)(g << 2);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int32_t e = e0 + w;
+            const uint32_t qw = pick_word(q, w), rw = pick_word(r, w);
+            if (e >= ea && e < eb && (qw == 0xFFFFFFFFu || rw < qw)) {
+              ++s_lv;
+              lds_insert(L, A.in_src[e], &over);
+            }
+          }
+        }
+        wave_sync();
+        if (__any(over)) break;
+      }
+      wave_sync();
+      tail = L.tail;
+      if (__any(over) || tail > kSmallCap) {
+        over = true;
+        break;
+      }
+    }
+    if (over) {
+      if (lane == 0) {
+        uint32_t slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
+        A.big_list[slot] = il;
+        A.len[il] = -1;
+      }
+      continue;
+    }
+    // sort queue[0, tail) ascending (bitonic over the next power of two)
+    int32_t P = 1;
+    while (P < tail) P <<= 1;
+    for (int j = tail + lane; j < P; j += kWave) L.queue[j] = 0x7FFFFFFF;
+    wave_sync();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = lane; t < (P >> 1); t += kWave) {
+          const int i1 = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+          const int i2 = i1 | j;
+          const bool asc = (i1 & k) == 0;
+          const int32_t x = L.queue[i1], y = L.queue[i2];
+          if ((x > y) == asc) {
+            L.queue[i1] = y;
+            L.queue[i2] = x;
+          }
+        }
+        wave_sync();
+      }
+    }
+    unsigned long long pos = 0;
+    if (lane == 0) pos = atomicAdd(&A.ctr[1], (unsigned long long)tail);
+    pos = __shfl(pos, 0, kWave);
+    if (pos + (unsigned long long)tail <= A.arena_cap)
+      for (int j = lane; j < tail; j += kWave) A.arena[pos + j] = L.queue[j];
+    if (lane == 0) {
+      A.start[il] = (int64_t)pos;
+      A.len[il] = tail;
+    }
+    w_ex += s_ex;
+    w_lv += s_lv;
+    wave_sync();
+  }
+  w_ex = wave_sum(w_ex);
+  w_lv = wave_sum(w_lv);
+  if (lane == 0) {
+    if (w_ex) atomicAdd(&A.ctr[3], w_ex);
+    if (w_lv) atomicAdd(&A.ctr[4], w_lv);
+  }
+}
+
+// ------------------------------------------------------------------ large sets
+struct BigArgs {
+  int32_t model;
+  uint32_t nwords;                  // ceil(n / 32)
+  uint32_t* __restrict__ bitmaps;   // per worker, nwords words, all zero between uses
+  int32_t* __restrict__ queues;     // per worker, n entries
+};
+
+__device__ __forceinline__ int64_t block_exclusive_scan64(int64_t x, int64_t* lds,
+                                                          int64_t* total) {
+  // lds: kBigBlock / kWave + 1 entries; every thread of the block must call
+  const int t = threadIdx.x, l = lane_id(), w = t / kWave;
+  int64_t inc = wave_inclusive_scan(x);
+  if (l == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int64_t v = l < kBigBlock / kWave ? lds[l] : 0;
+    int64_t vi = wave_inclusive_scan(v);
+    if (l < kBigBlock / kWave) lds[l] = vi - v;
+    if (l == kWave - 1) lds[kBigBlock / kWave] = vi;
+  }
+  __syncthreads();
+  int64_t r = lds[w] + inc - x;
+  *total = lds[kBigBlock / kWave];
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per large set: visited bitmap and queue in HBM (private to
+// the worker), members written in ascending order.
+__global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs Bg) {
+  __shared__ int32_t pre[kBigBlock];
+  __shared__ int32_t gbase[kBigBlock];
+  __shared__ int32_t ea[kBigBlock];
+  __shared__ int32_t eb[kBigBlock];
+  __shared__ int64_t scan_lds[kBigBlock / kWave + 1];
+  __shared__ int32_t sorted[kBigSortCap];
+  __shared__ int32_t s_tail;
+  __shared__ uint32_t s_item;
+  __shared__ unsigned long long s_pos;
+  uint32_t* bm = Bg.bitmaps + (size_t)blockIdx.x * Bg.nwords;
+  int32_t* queue = Bg.queues + (size_t)blockIdx.x * (size_t)A.n;
+  const int t = threadIdx.x;
+  const uint64_t seed = ((uint64_t)A.seed_hi << 32) | A.seed_lo;
+  const uint32_t nbig = (uint32_t)A.ctr[2];
+  unsigned long long t_ex = 0, t_lv = 0;
+  for (;;) {
+    if (t == 0) s_item = (uint32_t)atomicAdd(&A.ctr[5], 1ull);
+    __syncthreads();
+    const uint32_t item = s_item;
+    __syncthreads();
+    if (item >= nbig) break;
+    const uint32_t il = A.big_list[item];
+    const uint32_t i = A.first + il;
+    const int32_t root =
+        (int32_t)scale_draw(draw1(seed, kTagRoot, A.stream, 0u, i), (uint32_t)A.n);
+    unsigned long long s_ex = 0, s_lv = 0;
+    if (Bg.model == IM_IC) {
+      if (t == 0) {
+        bm[root >> 5] = 1u << (root & 31);
+        queue[0] = root;
+        s_tail = 1;
+      }
+      __syncthreads();
+      int32_t head = 0, tail = 1;
+      while (head < tail) {
+        const int32_t nf = min(tail - head, kBigBlock);
+        int32_t a = 0, b = 0, ng = 0;
+        if (t < nf) {
+          const int32_t v = queue[head + t];
+          a = A.in_off[v];
+          b = A.in_off[v + 1];
+          if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
+          s_ex += (unsigned long long)(b - a);
+        }
+        int64_t tot64;
+        const int32_t ex = (int32_t)block_exclusive_scan64(ng, scan_lds, &tot64);
+        const int32_t total = (int32_t)tot64;
+        pre[t] = ex + ng;
+        gbase[t] = (a >> 2) - ex;
+        ea[t] = a;
+        eb[t] = b;
+        head += nf;
+        __syncthreads();
+        for (int32_t base = 0; base < total; base += kBigBlock) {
+          const int32_t gi = base + t;
+          if (gi < total) {
+            int lo = 0, hi = kBigBlock - 1;
+            while (lo < hi) {
+              int mid = (lo + hi) >> 1;
+              if (pre[mid] > gi)
+                hi = mid;
+              else
+                lo = mid + 1;
+            }
+            const uint32_t g = (uint32_t)(gbase[lo] + gi);
+            const int32_t e_a = ea[lo], e_b = eb[lo];
+            const uint4 q = reinterpret_cast<const uint4*>(A.thr)[g];
+            const uint4 r =
+                philox4x32_10(make_uint4(g, i, kTagEdge, A.stream), A.seed_lo, A.seed_hi);
+            const int32_t e0 = (int32_t)(g << 2);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              const int32_t e = e0 + w;
+              const uint32_t qw = pick_word(q, w), rw = pick_word(r, w);
+              if (e >= e_a && e < e_b && (qw == 0xFFFFFFFFu || rw < qw)) {
+                ++s_lv;
+                const int32_t u = A.in_src[e];
+                const uint32_t bit = 1u << (u & 31);
+                const uint32_t old = atomicOr(&bm[u >> 5], bit);
+                if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = u;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        tail = s_tail;
+        __syncthreads();
+      }
+    } else if (t == 0) {  // LT: the chain is sequential; one thread walks it
+      int32_t v = root, len = 0;
+      bm[v >> 5] |= 1u << (v & 31);
+      queue[len++] = v;
+      for (;;) {
+        const int32_t a = A.in_off[v], b = A.in_off[v + 1];
+        if (a == b) break;
+        s_ex += ceil_log2_plus1(b - a);
+        const uint32_t r = draw1(seed, kTagVert, A.stream, i, (uint32_t)v);
+        int32_t lo = a, hi = b;
+        while (lo < hi) {
+          const int32_t mid = lo + ((hi - lo) >> 1);
+          const uint32_t c = A.thr[mid];
+          if (c > r || c == 0xFFFFFFFFu)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        if (lo == b) break;
+        ++s_lv;
+        const int32_t u = A.in_src[lo];
+        const uint32_t bit = 1u << (u & 31);
+        if (bm[u >> 5] & bit) break;
+        bm[u >> 5] |= bit;
+        queue[len++] = u;
+        v = u;
+      }
+      s_tail = len;
+    }
+    __syncthreads();
+    const int32_t tail = s_tail;
+    if (t == 0) s_pos = atomicAdd(&A.ctr[1], (unsigned long long)tail);
+    __syncthreads();
+    const unsigned long long pos = s_pos;
+    const bool fits = pos + (unsigned long long)tail <= A.arena_cap;
+    if (tail <= kBigSortCap) {
+      int32_t P = 1;
+      while (P < tail) P <<= 1;
+      for (int j = t; j < P; j += kBigBlock) sorted[j] = j < tail ? queue[j] : 0x7FFFFFFF;
+      __syncthreads();
+      for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int u = t; u < (P >> 1); u += kBigBlock) {
+            const int i1 = ((u & ~(j - 1)) << 1) | (u & (j - 1));
+            const int i2 = i1 | j;
+            const bool asc = (i1 & k) == 0;
+            const int32_t x = sorted[i1], y = sorted[i2];
+            if ((x > y) == asc) {
+              sorted[i1] = y;
+              sorted[i2] = x;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      if (fits)
+        for (int j = t; j < tail; j += kBigBlock) A.arena[pos + j] = sorted[j];
+    } else {
+      // members in ascending order straight from the bitmap
+      const uint32_t per = (Bg.nwords + kBigBlock - 1) / kBigBlock;
+      const uint32_t w0 = min((uint32_t)t * per, Bg.nwords);
+      const uint32_t w1 = min(w0 + per, Bg.nwords);
+      int64_t cnt = 0;
+      for (uint32_t w = w0; w < w1; ++w) cnt += __popc(bm[w]);
+      int64_t tot;
+      int64_t o = block_exclusive_scan64(cnt, scan_lds, &tot);
+      if (fits) {
+        for (uint32_t w = w0; w < w1; ++w) {
+          uint32_t x = bm[w];
+          while (x) {
+            const int b = __ffs(x) - 1;
+            x &= x - 1;
+            A.arena[pos + o++] = (int32_t)((w << 5) + b);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = t; j < tail; j += kBigBlock) bm[queue[j] >> 5] = 0u;
+    if (t == 0) {
+      A.start[il] = (int64_t)pos;
+      A.len[il] = tail;
+    }
+    t_ex += s_ex;
+    t_lv += s_lv;
+    __syncthreads();
+  }
+  int64_t tot;
+  (void)block_exclusive_scan64((int64_t)t_ex, scan_lds, &tot);
+  if (t == 0 && tot) atomicAdd(&A.ctr[3], (unsigned long long)tot);
+  (void)block_exclusive_scan64((int64_t)t_lv, scan_lds, &tot);
+  if (t == 0 && tot) atomicAdd(&A.ctr[4], (unsigned long long)tot);
+}
+
+// ------------------------------------------------------------------ LT walks
+__device__ __forceinline__ bool lt_contains(const int32_t* H, int32_t u) {
+  uint32_t h = hash_slot(u, 11);
+  for (;;) {
+    const int32_t c = H[h];
+    if (c == u) return true;
+    if (c == kEmpty) return false;
+    h = (h + 1) & (kLtH - 1);
+  }
+}
+__device__ __forceinline__ void lt_insert(int32_t* H, int32_t u) {
+  uint32_t h = hash_slot(u, 11);
+  while (H[h] != kEmpty) h = (h + 1) & (kLtH - 1);
+  H[h] = u;
+}
+// Removal in reverse insertion order restores the table exactly.
+__device__ __forceinline__ void lt_erase(int32_t* H, int32_t u) {
+  uint32_t h = hash_slot(u, 11);
+  while (H[h] != u) h = (h + 1) & (kLtH - 1);
+  H[h] = kEmpty;
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
+  const uint32_t lo = __shfl((uint32_t)x, src, kWave);
+  const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// One lane per walk.  Lanes take new samples as their walks end (aggregated
+// per wave), so a long walk does not hold up the other 63 lanes.  The per-lane
+// hash (kLtH slots) is empty between walks.
+__global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* lane_hash,
+                                                        int32_t* lane_list) {
+  const size_t gl = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t* H = lane_hash + gl * kLtH;
+  int32_t* Ls = lane_list + gl * kLtCap;
+  const int lane = lane_id();
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint64_t seed = ((uint64_t)A.seed_hi << 32) | A.seed_lo;
+  bool have = false, done = false;
+  uint32_t il = 0, i = 0;
+  int32_t v = 0, len = 0;
+  unsigned long long ex = 0, lv = 0, s_ex = 0, s_lv = 0;
+  for (;;) {
+    const uint64_t need = __ballot(!have && !done);
+    if (need) {
+      const int leader = __ffsll((unsigned long long)need) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(&A.ctr[0], (unsigned long long)__popcll(need));
+      base = shfl_u64(base, leader);
+      if (!have && !done) {
+        const unsigned long long mine = base + (unsigned long long)__popcll(need & below);
+        if (mine >= A.count) {
+          done = true;
+        } else {
+          il = (uint32_t)mine;
+          i = A.first + il;
+          v = (int32_t)scale_draw(draw1(seed, kTagRoot, A.stream, 0u, i), (uint32_t)A.n);
+          lt_insert(H, v);
+          Ls[0] = v;
+          len = 1;
+          s_ex = s_lv = 0;
+          have = true;
+        }
+      }
+    }
+    if (!__any(have)) break;
+    bool fin = false, over = false;
+    if (have) {
+      const int32_t a = A.in_off[v], b = A.in_off[v + 1];
+      if (a == b) {
+        fin = true;
+      } else {
+        s_ex += ceil_log2_plus1(b - a);
+        const uint32_t r = draw1(seed, kTagVert, A.stream, i, (uint32_t)v);
+        int32_t lo = a, hi = b;
+        while (lo < hi) {
+          const int32_t mid = lo + ((hi - lo) >> 1);
+          const uint32_t c = A.thr[mid];
+          if (c > r || c == 0xFFFFFFFFu)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        if (lo == b) {
+          fin = true;
+        } else {
+          ++s_lv;
+          const int32_t u = A.in_src[lo];
+          if (lt_contains(H, u)) {
+            fin = true;
+          } else if (len == kLtCap) {
+            fin = true;
+            over = true;
+          } else {
+            lt_insert(H, u);
+            Ls[len++] = u;
+            v = u;
+          }
+        }
+      }
+    }
+    const bool emit = fin && !over;
+    const int32_t mylen = emit ? len : 0;
+    const int32_t inc = wave_inclusive_scan(mylen);
+    const int32_t tot = __shfl(inc, kWave - 1, kWave);
+    unsigned long long pos = 0;
+    if (tot > 0) {
+      const uint64_t em = __ballot(emit);
+      const int leader = __ffsll((unsigned long long)em) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(&A.ctr[1], (unsigned long long)tot);
+      pos = shfl_u64(base, leader) + (unsigned long long)(inc - mylen);
+    }
+    if (fin) {
+      if (over) {
+        const uint32_t slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
+        A.big_list[slot] = il;
+        A.len[il] = -1;
+      } else {
+        if (pos + (unsigned long long)len <= A.arena_cap)
+          for (int32_t j = 0; j < len; ++j) A.arena[pos + j] = Ls[j];
+        A.start[il] = (int64_t)pos;
+        A.len[il] = len;
+        ex += s_ex;
+        lv += s_lv;
+      }
+      for (int32_t j = len - 1; j >= 0; --j) lt_erase(H, Ls[j]);
+      have = false;
+    }
+  }
+  ex = wave_sum(ex);
+  lv = wave_sum(lv);
+  if (lane == 0) {
+    if (ex) atomicAdd(&A.ctr[3], ex);
+    if (lv) atomicAdd(&A.ctr[4], lv);
+  }
+}
+
+// ------------------------------------------------------------------ gather
+constexpr int kGatherBlock = 256;
+
+// One wavefront per set: copies it from the arena to its canonical place,
+// sorting it on the way when it was written unsorted (LT walks).
+__global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
+                                                         const int64_t* __restrict__ start,
+                                                         const int32_t* __restrict__ len,
+                                                         const int64_t* __restrict__ off,
+                                                         const int32_t* __restrict__ arena,
+                                                         int32_t* __restrict__ mem,
+                                                         int sort_small) {
+  __shared__ int32_t buf_all[kGatherBlock / kWave][kGatherSortCap];
+  int32_t* buf = buf_all[threadIdx.x / kWave];
+  const int lane = lane_id();
+  const uint32_t wid = (blockIdx.x * kGatherBlock + threadIdx.x) / kWave;
+  const uint32_t nw = gridDim.x * (kGatherBlock / kWave);
+  for (uint32_t s = wid; s < count; s += nw) {
+    const int32_t L = len[s];
+    const int32_t* src = arena + start[s];
+    int32_t* dst = mem + off[s];
+    if (sort_small && L > 1 && L <= kGatherSortCap) {
+      int32_t P = 1;
+      while (P < L) P <<= 1;
+      for (int j = lane; j < P; j += kWave) buf[j] = j < L ? src[j] : 0x7FFFFFFF;
+      wave_sync();
+      for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int t = lane; t < (P >> 1); t += kWave) {
+            const int i1 = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+            const int i2 = i1 | j;
+            const bool asc = (i1 & k) == 0;
+            const int32_t x = buf[i1], y = buf[i2];
+            if ((x > y) == asc) {
+              buf[i1] = y;
+              buf[i2] = x;
+            }
+          }
+          wave_sync();
+        }
+      }
+      for (int j = lane; j < L; j += kWave) dst[j] = buf[j];
+      wave_sync();
+    } else {
+      for (int j = lane; j < L; j += kWave) dst[j] = src[j];
+    }
+  }
+}
+
+}  // namespace im
+
+// ------------------------------------------------------------------ entry
+extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag,
+                             int64_t first, int64_t count, int64_t* off, int32_t* mem,
+                             int64_t capacity, int64_t* total, im_sample_stats* stats,
+                             void* stream) {
+  using namespace im;
+  if (!g || !off || !total || first < 0 || count < 0 || capacity < 0 ||
+      first + count > (int64_t)1 << 32 || (capacity > 0 && !mem))
+    return IM_EINVAL;
+  if (g->n <= 0 || g->num_edges < 0 || g->num_edges >= (int64_t)0x7FFFFFFF || !g->in_off ||
+      (g->num_edges > 0 && (!g->in_src || !g->thr)) ||
+      (g->model != IM_IC && g->model != IM_LT) || ((uintptr_t)g->thr & 15u))
+    return IM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  if (count == 0) {
+    IM_HIP(hipMemsetAsync(off, 0, sizeof(int64_t), s));
+    IM_HIP(hipStreamSynchronize(s));
+    *total = 0;
+    if (stats) *stats = im_sample_stats{0, 0, 0, 0};
+    return IM_OK;
+  }
+  const uint32_t cnt = (uint32_t)count;
+  // per-sample metadata: start (i64), len (i32), big list (u32), counters
+  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 64 + 256;
+  void* mp = nullptr;
+  IM_TRY(scratch(s, kSlotSampleMeta, meta_bytes, &mp));
+  unsigned long long* ctr = (unsigned long long*)mp;
+  int64_t* start = (int64_t*)((char*)mp + 64);
+  int32_t* lens = (int32_t*)(start + cnt);
+  uint32_t* big_list = (uint32_t*)(lens + cnt);
+
+  static thread_local int64_t last_total = 0;
+  uint64_t arena_cap = (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total),
+                                                   (int64_t)cnt * 2);
+  unsigned long long hc[6] = {0, 0, 0, 0, 0, 0};
+  const bool lt = g->model == IM_LT;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    void* ap = nullptr;
+    IM_TRY(scratch(s, kSlotSampleArena, arena_cap * sizeof(int32_t), &ap));
+    SampleArgs A;
+    A.n = g->n;
+    A.in_off = g->in_off;
+    A.in_src = g->in_src;
+    A.thr = g->thr;
+    A.seed_lo = (uint32_t)seed;
+    A.seed_hi = (uint32_t)(seed >> 32);
+    A.stream = stream_tag;
+    A.first = (uint32_t)first;
+    A.count = cnt;
+    A.arena = (int32_t*)ap;
+    A.arena_cap = arena_cap;
+    A.start = start;
+    A.len = lens;
+    A.big_list = big_list;
+    A.ctr = ctr;
+    IM_HIP(hipMemsetAsync(ctr, 0, 64, s));
+    if (!lt) {
+      const int blocks = di.num_cus * 8;
+      k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(A);
+    } else {
+      const int blocks = di.num_cus * 2;
+      const size_t lanes = (size_t)blocks * kLtBlock;
+      bool fresh = false;
+      void* hp = nullptr;
+      IM_TRY(scratch_fresh(s, kSlotSampleLtLane, lanes * (kLtH + kLtCap) * sizeof(int32_t), &hp,
+                           &fresh));
+      if (fresh) IM_HIP(hipMemsetAsync(hp, 0xFF, lanes * kLtH * sizeof(int32_t), s));
+      int32_t* lane_hash = (int32_t*)hp;
+      int32_t* lane_list = lane_hash + lanes * kLtH;
+      k_sample_lt<<<dim3(blocks), dim3(kLtBlock), 0, s>>>(A, lane_hash, lane_list);
+    }
+    IM_HIP(hipGetLastError());
+    IM_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+    IM_HIP(hipStreamSynchronize(s));
+    if (hc[2] > 0) {
+      const uint32_t nbig = (uint32_t)hc[2];
+      const uint32_t nwords = (uint32_t)(((int64_t)g->n + 31) / 32);
+      // workers each hold an n-bit bitmap and an n-entry queue
+      const size_t per_worker = (size_t)nwords * 4 + (size_t)g->n * 4;
+      uint32_t workers = std::min<uint32_t>(nbig, (uint32_t)di.num_cus * 2);
+      const size_t budget = (size_t)8 << 30;
+      while (workers > 1 && (size_t)workers * per_worker > budget) workers >>= 1;
+      void* bp = nullptr;
+      IM_TRY(scratch(s, kSlotSampleBig, (size_t)workers * per_worker, &bp));
+      BigArgs Bg;
+      Bg.model = g->model;
+      Bg.nwords = nwords;
+      Bg.bitmaps = (uint32_t*)bp;
+      Bg.queues = (int32_t*)((char*)bp + (size_t)workers * nwords * 4);
+      IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)workers * nwords * 4, s));
+      k_sample_big<<<dim3(workers), dim3(kBigBlock), 0, s>>>(A, Bg);
+      IM_HIP(hipGetLastError());
+      IM_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
+      IM_HIP(hipStreamSynchronize(s));
+    }
+    if (hc[1] <= arena_cap) break;
+    arena_cap = hc[1];  // deterministic: the retry produces the same sets
+    if (attempt == 2) return IM_ENOMEM;
+  }
+  const int64_t tot = (int64_t)hc[1];
+  last_total = tot;
+  IM_TRY(exclusive_scan_i32_to_i64(lens, (int64_t)cnt, off, s));
+  *total = tot;
+  if (stats) *stats = im_sample_stats{tot, (int64_t)hc[3], (int64_t)hc[4], (int64_t)hc[2]};
+  if (tot > capacity) {
+    IM_HIP(hipStreamSynchronize(s));
+    return IM_ERANGE;
+  }
+  void* ap = nullptr;
+  IM_TRY(scratch(s, kSlotSampleArena, arena_cap * sizeof(int32_t), &ap));
+  const int gblocks = std::min<int64_t>(((int64_t)cnt + 3) / 4, (int64_t)di.num_cus * 16);
+  k_gather<<<dim3(std::max(gblocks, 1)), dim3(kGatherBlock), 0, s>>>(
+      cnt, start, lens, off, (const int32_t*)ap, mem, lt ? 1 : 0);
+  IM_HIP(hipGetLastError());
+  IM_HIP(hipStreamSynchronize(s));
+  return IM_OK;
+}

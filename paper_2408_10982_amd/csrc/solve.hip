@@ -1,0 +1,222 @@
+// solve.hip -- the IMM driver (im_solve; Alg. 1 with the GreediRIS selector of
+// Alg. 3/4/5 or the standard greedy).
+//
+// Host logic only: it grows a device-resident pool of RRR sets by sample-id
+// range (earlier samples are kept across martingale rounds, Sec. 3.2),
+// rebuilds the covering subsets, runs the selector on the device and reads
+// back the coverage for the lower-bound test.  The fp64 bounds follow IMM
+// (Tang, Shi and Xiao 2015); the final seeds come from theta fresh samples
+// of a second stream (the Sample(G, theta) line of Alg. 1).
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace im {
+
+__global__ void k_add_base(int64_t* __restrict__ off, int64_t n, int64_t base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) off[i] += base;
+}
+
+// A growable device pool of RRR sets owned by one im_solve call.
+struct Pool {
+  int64_t count = 0, total = 0;
+  int64_t cap_sets = 0, cap_mem = 0;
+  int64_t* off = nullptr;
+  int32_t* mem = nullptr;
+  ~Pool() {
+    if (off) (void)hipFree(off);
+    if (mem) (void)hipFree(mem);
+  }
+};
+
+static int grow(void** p, size_t old_bytes, size_t new_bytes, hipStream_t s) {
+  void* q = nullptr;
+  if (hipMalloc(&q, new_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return IM_ENOMEM;
+  }
+  if (*p) {
+    if (old_bytes) IM_HIP(hipMemcpyAsync(q, *p, old_bytes, hipMemcpyDeviceToDevice, s));
+    IM_HIP(hipStreamSynchronize(s));
+    IM_HIP(hipFree(*p));
+  }
+  *p = q;
+  return IM_OK;
+}
+
+static int pool_extend(Pool& P, const im_graph* g, uint64_t seed, uint32_t tag, int64_t want,
+                       hipStream_t s) {
+  if (want <= P.count) return IM_OK;
+  if (want + 1 > P.cap_sets) {
+    int64_t nc = std::max<int64_t>(want + 1, P.cap_sets * 2);
+    IM_TRY(grow((void**)&P.off, (size_t)(P.count + 1) * 8, (size_t)nc * 8, s));
+    P.cap_sets = nc;
+  }
+  if (P.count == 0) IM_HIP(hipMemsetAsync(P.off, 0, 8, s));
+  const int64_t add = want - P.count;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (P.cap_mem - P.total < add * 4) {
+      int64_t nc = std::max<int64_t>(P.total + add * 8, P.cap_mem * 2);
+      IM_TRY(grow((void**)&P.mem, (size_t)P.total * 4, (size_t)nc * 4, s));
+      P.cap_mem = nc;
+    }
+    int64_t tot = 0;
+    int st = im_sample_rrr(g, seed, tag, P.count, add, P.off + P.count, P.mem + P.total,
+                           P.cap_mem - P.total, &tot, nullptr, s);
+    if (st == IM_ERANGE) {
+      int64_t nc = std::max<int64_t>(P.total + tot + tot / 4, P.cap_mem * 2);
+      IM_TRY(grow((void**)&P.mem, (size_t)P.total * 4, (size_t)nc * 4, s));
+      P.cap_mem = nc;
+      continue;
+    }
+    IM_TRY(st);
+    if (P.total > 0) {
+      k_add_base<<<dim3((unsigned)((add + 1 + 255) / 256)), dim3(256), 0, s>>>(P.off + P.count,
+                                                                             add + 1, P.total);
+      IM_HIP(hipGetLastError());
+    }
+    P.total += tot;
+    P.count = want;
+    return IM_OK;
+  }
+  return IM_ENOMEM;
+}
+
+struct Selection {
+  std::vector<int32_t> seeds;
+  int32_t nsel = 0;
+  int64_t coverage = 0;
+  int32_t bucket = -1;
+  int32_t global_won = -1;
+};
+
+static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o,
+                     Selection* out, hipStream_t s) {
+  void *pio = nullptr, *pim = nullptr, *pout = nullptr;
+  IM_TRY(scratch(s, kSlotSolveIncOff, (size_t)(n + 1) * 8, &pio));
+  IM_TRY(scratch(s, kSlotSolveInc, (size_t)std::max<int64_t>(P.total, 1) * 4, &pim));
+  int64_t* inc_off = (int64_t*)pio;
+  int32_t* inc_mem = (int32_t*)pim;
+  IM_TRY(im_build_incidence(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, s));
+  // outputs: seeds k, gains k, nsel, coverage, info 4
+  IM_TRY(scratch(s, kSlotSolveOut, (size_t)k * 12 + 64, &pout));
+  int32_t* d_seeds = (int32_t*)pout;
+  int64_t* d_cov = (int64_t*)((char*)pout + ((size_t)k * 4 + 7) / 8 * 8);
+  int32_t* d_nsel = (int32_t*)(d_cov + 1);
+  int32_t* d_info = d_nsel + 2;
+  out->seeds.assign(k, -1);
+  if (o->selector == IM_SEL_GREEDY) {
+    void* pg = nullptr;
+    IM_TRY(scratch(s, kSlotSolveLocal, (size_t)k * 8, &pg));
+    IM_TRY(im_greedy_cover(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, d_seeds,
+                           (int64_t*)pg, d_nsel, d_cov, s));
+  } else {
+    const int32_t m = o->m;
+    void* pl = nullptr;
+    const size_t lbytes = (size_t)n + 64 + (size_t)m * k * 12 + (size_t)m * 12 + 64;
+    IM_TRY(scratch(s, kSlotSolveLocal, lbytes, &pl));
+    int64_t* lgains = (int64_t*)pl;
+    int64_t* lcover = lgains + (size_t)m * k;
+    int32_t* lseeds = (int32_t*)(lcover + m);
+    int32_t* lcount = lseeds + (size_t)m * k;
+    uint8_t* part = (uint8_t*)(lcount + m);
+    IM_TRY(im_randgreedi(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, m, o->part_seed,
+                         part, lseeds, lgains, lcount, lcover, s));
+    IM_TRY(im_stream_cover(n, P.count, inc_off, inc_mem, k, m, lseeds, lcount, lcover, o->delta,
+                           o->alpha, d_seeds, d_nsel, d_cov, d_info, s));
+  }
+  int32_t h_nsel = 0, h_info[4] = {-1, 0, -1, 0};
+  int64_t h_cov = 0;
+  IM_HIP(hipMemcpyAsync(out->seeds.data(), d_seeds, (size_t)k * 4, hipMemcpyDeviceToHost, s));
+  IM_HIP(hipMemcpyAsync(&h_nsel, d_nsel, 4, hipMemcpyDeviceToHost, s));
+  IM_HIP(hipMemcpyAsync(&h_cov, d_cov, 8, hipMemcpyDeviceToHost, s));
+  if (o->selector != IM_SEL_GREEDY)
+    IM_HIP(hipMemcpyAsync(h_info, d_info, 16, hipMemcpyDeviceToHost, s));
+  IM_HIP(hipStreamSynchronize(s));
+  out->nsel = h_nsel;
+  out->coverage = h_cov;
+  if (o->selector != IM_SEL_GREEDY) {
+    out->bucket = h_info[0];
+    out->global_won = h_info[2];
+  }
+  return IM_OK;
+}
+
+}  // namespace im
+
+extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* o,
+                        int32_t* seeds, im_solve_result* res, void* stream) {
+  using namespace im;
+  if (!g || !o || !seeds || !res || k <= 0 || g->n <= 0 || k > g->n || !(eps > 0.0 && eps < 1.0) ||
+      (o->selector != IM_SEL_GREEDY && o->selector != IM_SEL_GREEDIRIS) || o->theta < 0)
+    return IM_EINVAL;
+  if (o->selector == IM_SEL_GREEDIRIS &&
+      (o->m < 1 || o->m > 256 || !(o->delta > 0.0 && o->delta < 0.5) ||
+       !(o->alpha > 0.0 && o->alpha <= 1.0)))
+    return IM_EINVAL;
+  if (g->model != IM_IC && g->model != IM_LT) return IM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t n = g->n;
+  const double nd = (double)n;
+  // IMM bounds (fp64, fixed order)
+  const double ln_n = log(nd);
+  const double ell = 1.0 * (1.0 + log(2.0) / ln_n);
+  const double eps_p = sqrt(2.0) * eps;
+  double lbin = 0.0;
+  for (int32_t i = 0; i < k; ++i) lbin += log(nd - (double)i);
+  for (int32_t i = 1; i <= k; ++i) lbin -= log((double)i);
+  const double lambda_p =
+      (2.0 + 2.0 * eps_p / 3.0) * (lbin + ell * ln_n + log(log2(nd))) * nd / (eps_p * eps_p);
+  const double e1 = 1.0 - exp(-1.0);
+  const double a_i = sqrt(ell * ln_n + log(2.0));
+  const double b_i = sqrt(e1 * (lbin + ell * ln_n + log(2.0)));
+  const double sm = e1 * a_i + b_i;
+  const double lambda_s = 2.0 * nd * sm * sm / (eps * eps);
+  int32_t lg = 0;
+  while (((int64_t)1 << (lg + 1)) <= (int64_t)n) ++lg;
+  const int32_t rounds = lg - 1;
+
+  *res = im_solve_result{};
+  res->bucket = -1;
+  res->global_won = -1;
+  double lb = 1.0;
+  int64_t theta;
+  Selection sel;
+  if (o->theta > 0) {
+    theta = o->theta;
+  } else {
+    Pool P;
+    int64_t th = (int64_t)ceil(lambda_p / (nd / 2.0));
+    for (int32_t i = 1; i <= rounds; ++i) {
+      if (i > 1) th *= 2;
+      if (th >= ((int64_t)1 << 31)) return IM_ERANGE;
+      IM_TRY(pool_extend(P, g, o->seed, 0u, th, s));
+      IM_TRY(select_on(P, n, k, o, &sel, s));
+      res->rounds = i;
+      const double x = nd / ldexp(1.0, i);
+      if (nd * (double)sel.coverage / (double)th >= (1.0 + eps_p) * x) {
+        lb = nd * (double)sel.coverage / ((double)th * (1.0 + eps_p));
+        break;
+      }
+    }
+    res->martingale_samples = P.count;
+    theta = (int64_t)ceil(lambda_s / lb);
+  }
+  if (theta >= ((int64_t)1 << 31)) return IM_ERANGE;
+  Pool F;
+  IM_TRY(pool_extend(F, g, o->seed, 1u, theta, s));
+  IM_TRY(select_on(F, n, k, o, &sel, s));
+  for (int32_t j = 0; j < k; ++j) seeds[j] = sel.seeds[j];
+  res->nsel = sel.nsel;
+  res->coverage = sel.coverage;
+  res->theta = theta;
+  res->lower_bound = lb;
+  res->bucket = sel.bucket;
+  res->global_won = sel.global_won;
+  res->final_total = F.total;
+  return IM_OK;
+}

@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every symbol its header declares
+(no compute calls: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "im.h")
+LIB = os.path.join(ROOT, "paper_2408_10982_amd", "libim.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(im_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for f in ("im_sample_rrr", "im_greedy_cover", "im_randgreedi", "im_stream_cover",
+              "im_solve", "im_build_incidence", "im_prepare_graph"):
+        assert f in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    for name in _declared():
+        assert hasattr(L, name), name
+    L.im_version.restype = ctypes.c_char_p
+    assert b"gfx950" in L.im_version()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_binding_exports_match_header():
+    import paper_2408_10982_amd as im
+    assert sorted(im.EXPORTS) == _declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_invalid_arguments_rejected_before_device_work():
+    """IM_EINVAL comes back before any HIP call, so this runs without a GPU."""
+    L = ctypes.CDLL(LIB)
+    L.im_greedy_cover.restype = ctypes.c_int
+    # k = 0 is invalid
+    st = L.im_greedy_cover(ctypes.c_int32(10), ctypes.c_int64(5), None, None, ctypes.c_int64(0),
+                           None, None, ctypes.c_int32(0), None, None, None, None, None)
+    assert st == -1
+    L.im_stream_cover.restype = ctypes.c_int
+    st = L.im_stream_cover(ctypes.c_int32(10), ctypes.c_int64(5), None, None, ctypes.c_int32(3),
+                           ctypes.c_int32(2), None, None, None, ctypes.c_double(0.7),
+                           ctypes.c_double(1.0), None, None, None, None, None)
+    assert st == -1
+    L.im_sample_rrr.restype = ctypes.c_int
+    st = L.im_sample_rrr(None, ctypes.c_uint64(0), ctypes.c_uint32(0), ctypes.c_int64(0),
+                         ctypes.c_int64(1), None, None, ctypes.c_int64(0), None, None, None)
+    assert st == -1

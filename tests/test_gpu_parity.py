@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every comparison is exact: thresholds, RRR sets (canonical sorted CSR),
+sampling counters, covering subsets (as sets), seeds, gains, coverage,
+partitions, local solutions, streamed solutions and IMM sample counts.
+Both sides run on the same seeded synthetic inputs; neither sees the other's
+outputs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def im():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2408_10982_amd as im
+    im.lib()
+    return im
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _prep(im, g):
+    return im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
+
+
+def _oracle_thr(g):
+    return O.thresholds(g.model, g.in_off, g.weight)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+GRAPHS = {
+    "ic_sparse": lambda: W.random_small_graph(500, 2000, seed=1, p_hi=0.1),
+    "ic_dense": lambda: W.random_small_graph(300, 3000, seed=2, p_hi=0.5),
+    "ic_p1": lambda: W.tiny_graph(400, [(int(a), int(b)) for a, b in
+                                        np.random.default_rng(3).integers(0, 400, (1600, 2))],
+                                  np.ones(1600, np.float32)),
+    "lt_small": lambda: W.random_small_graph(500, 2500, seed=4, model=W.LT),
+    "lt_chain": lambda: W.tiny_graph(3000, [(v, v + 1) for v in range(2999)],
+                                     np.ones(2999, np.float32), model=W.LT),
+    "rmat12": lambda: W.config(1).graph,
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+def test_thresholds(im, name):
+    _say("thresholds", name)
+    g = GRAPHS[name]()
+    G = _prep(im, g)
+    got = _np(G.thr).view(np.uint32)[:g.num_edges]
+    assert np.array_equal(got, _oracle_thr(g))
+    assert np.all(_np(G.thr)[g.num_edges:] == 0)
+
+
+@pytest.mark.parametrize("name,first,count", [
+    ("ic_sparse", 0, 3000), ("ic_dense", 17, 2001), ("ic_p1", 5, 700), ("lt_small", 0, 4000),
+    ("lt_chain", 3, 600), ("rmat12", 0, 16384), ("rmat12", 100000, 999)])
+def test_sample_rrr(im, name, first, count):
+    _say("sample", name, first, count)
+    g = GRAPHS[name]()
+    G = _prep(im, g)
+    r = im.sample_rrr(G, seed=3001, stream_tag=0, first=first, count=count)
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), 3001, 0, first, count)
+    assert np.array_equal(_np(r.off), o.off)
+    assert np.array_equal(_np(r.mem), o.mem)
+    assert (r.examined, r.live) == (o.examined, o.live)
+
+
+def test_sample_edge_cases(im):
+    _say("sample edge cases")
+    g = GRAPHS["ic_sparse"]()
+    G = _prep(im, g)
+    r = im.sample_rrr(G, 1, 0, 0, 0)
+    assert r.total == 0 and _np(r.off).tolist() == [0]
+    # capacity too small: IM_ERANGE first, identical result after the retry
+    r1 = im.sample_rrr(G, 7, 2, 0, 500, capacity=10)
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), 7, 2, 0, 500)
+    assert np.array_equal(_np(r1.mem), o.mem)
+    # an isolated vertex graph: every set is its root
+    iso = W.tiny_graph(64, [], np.zeros(0, np.float32))
+    Gi = _prep(im, iso)
+    ri = im.sample_rrr(Gi, 5, 0, 0, 300)
+    oi = O.sample(O.IC, iso.in_off, iso.in_src, np.zeros(0, np.uint32), 5, 0, 0, 300)
+    assert np.array_equal(_np(ri.mem), oi.mem)
+
+
+def test_invalid_arguments(im):
+    _say("invalid arguments")
+    g = GRAPHS["ic_sparse"]()
+    bad = g.weight.copy()
+    bad[3] = np.nan
+    with pytest.raises(im.ImError):
+        im.prepare_graph(g.in_off, g.in_src, bad, W.IC)
+    bad2 = g.weight.copy()
+    bad2[0] = 1.5
+    with pytest.raises(im.ImError):
+        im.prepare_graph(g.in_off, g.in_src, bad2, W.IC)
+    off = g.in_off.copy()
+    off[-1] += 1
+    with pytest.raises(im.ImError):
+        im.prepare_graph(off, g.in_src, g.weight, W.IC)
+
+
+def _incidence_sets(inc_off, inc_mem):
+    io = np.asarray(inc_off)
+    im_ = np.asarray(inc_mem).copy()
+    for v in range(io.shape[0] - 1):
+        im_[io[v]:io[v + 1]].sort()
+    return io, im_
+
+
+@pytest.mark.parametrize("name,count", [("ic_dense", 3000), ("lt_small", 5000), ("rmat12", 16384)])
+def test_incidence(im, name, count):
+    _say("incidence", name, count)
+    g = GRAPHS[name]()
+    G = _prep(im, g)
+    r = im.sample_rrr(G, 11, 0, 0, count)
+    io, imem = im.build_incidence(g.n, r)
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), 11, 0, 0, count)
+    oio, oim = O.incidence(g.n, o)
+    gio, gim = _incidence_sets(_np(io), _np(imem))
+    assert np.array_equal(gio, oio)
+    assert np.array_equal(gim, oim)
+
+
+def _pipeline(im, g, count, seed):
+    G = _prep(im, g)
+    r = im.sample_rrr(G, seed, 0, 0, count)
+    io, imem = im.build_incidence(g.n, r)
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), seed, 0, 0, count)
+    oio, oim = O.incidence(g.n, o)
+    return G, r, io, imem, o, oio, oim
+
+
+@pytest.mark.parametrize("name,count,k", [("ic_sparse", 3000, 10), ("ic_dense", 2000, 25),
+                                          ("lt_small", 6000, 40), ("rmat12", 16384, 16),
+                                          ("ic_p1", 500, 8)])
+def test_greedy(im, name, count, k):
+    _say("greedy", name, count, k)
+    g = GRAPHS[name]()
+    G, r, io, imem, o, oio, oim = _pipeline(im, g, count, 21)
+    seeds, gains, nsel, cov = im.greedy_cover(g.n, r, io, imem, k)
+    os_, og, oc = O.greedy(g.n, count, oio, oim, k)
+    ns = int(_np(nsel)[0])
+    assert ns == len(os_)
+    assert np.array_equal(_np(seeds)[:ns], os_)
+    assert np.array_equal(_np(gains)[:ns], og)
+    assert np.all(_np(seeds)[ns:] == -1)
+    assert int(_np(cov)[0]) == oc
+
+
+@pytest.mark.parametrize("name,count,k,m", [("ic_dense", 2000, 10, 4), ("lt_small", 6000, 20, 8),
+                                            ("rmat12", 16384, 16, 64), ("ic_sparse", 3000, 5, 1)])
+def test_randgreedi(im, name, count, k, m):
+    _say("randgreedi", name, count, k, m)
+    g = GRAPHS[name]()
+    G, r, io, imem, o, oio, oim = _pipeline(im, g, count, 31)
+    part, ls, lg, lc, lv = im.randgreedi(g.n, r, io, imem, k, m, part_seed=4003)
+    opart = O.partition(g.n, m, 4003)
+    assert np.array_equal(_np(part), opart)
+    ols, olg, olc, olv = O.local_greedy(g.n, count, oio, oim, opart, m, k)
+    assert np.array_equal(_np(lc), olc)
+    assert np.array_equal(_np(lv), olv)
+    assert np.array_equal(_np(ls), ols)
+    assert np.array_equal(_np(lg), olg)
+
+
+@pytest.mark.parametrize("name,count,k,m,delta,alpha", [
+    ("ic_dense", 2000, 10, 4, 0.077, 1.0), ("lt_small", 6000, 20, 8, 0.1, 0.25),
+    ("rmat12", 16384, 16, 64, 0.077, 1.0), ("rmat12", 16384, 16, 64, 0.077, 0.125),
+    ("ic_sparse", 3000, 1, 3, 0.2, 1.0)])
+def test_stream_cover(im, name, count, k, m, delta, alpha):
+    _say("stream", name, count, k, m, delta, alpha)
+    g = GRAPHS[name]()
+    G, r, io, imem, o, oio, oim = _pipeline(im, g, count, 41)
+    part, ls, lg, lc, lv = im.randgreedi(g.n, r, io, imem, k, m, part_seed=77)
+    seeds, nsel, cov, info = im.stream_cover(g.n, count, io, imem, ls, lc, lv, k, delta, alpha)
+    opart = O.partition(g.n, m, 77)
+    ols, olg, olc, olv = O.local_greedy(g.n, count, oio, oim, opart, m, k)
+    gs, gc, gb, gnb = O.stream_cover(g.n, count, oio, oim, ols, olg, olc, k, delta, alpha)
+    fs, fc, won = O.final_select(ols, olc, olv, gs, gc)
+    ns = int(_np(nsel)[0])
+    inf = _np(info)
+    assert (inf[0], inf[1], inf[2]) == (gb, gnb, int(won))
+    assert ns == len(fs) and np.array_equal(_np(seeds)[:ns], fs)
+    assert int(_np(cov)[0]) == fc
+
+
+@pytest.mark.parametrize("name,k,eps,selector", [
+    ("ic_sparse", 5, 0.5, O.SEL_GREEDY), ("lt_small", 8, 0.4, O.SEL_GREEDIRIS),
+    ("rmat12", 16, 0.5, O.SEL_GREEDY), ("rmat12", 16, 0.5, O.SEL_GREEDIRIS)])
+def test_solve_imm(im, name, k, eps, selector):
+    _say("imm", name, k, eps, selector)
+    g = GRAPHS[name]()
+    G = _prep(im, g)
+    kw = dict(selector=selector, m=8, delta=0.077, alpha=0.5, seed=3003, part_seed=4003)
+    got = im.solve(G, k, eps, **kw)
+    exp = O.imm(g.model, g.in_off, g.in_src, _oracle_thr(g), k, eps, **kw)
+    assert got["theta"] == exp["theta"]
+    assert got["rounds"] == exp["rounds_run"]
+    assert got["martingale_samples"] == exp["martingale_samples"]
+    assert got["lower_bound"] == exp["lb"]
+    assert got["seeds"] == exp["seeds"].tolist()
+    assert got["coverage"] == exp["coverage"]
