@@ -68,13 +68,21 @@ typedef struct {
   int32_t model;           /* IM_IC or IM_LT, as given to im_prepare_graph */
 } im_graph;
 
-/* Sampling statistics of one im_sample_rrr call (exact, deterministic). */
+/* Sampling statistics of one im_sample_rrr call.  The counts are exact and
+ * deterministic; the times are device times of the three launches, taken
+ * with HIP events on `stream` (only when statistics are requested). */
 typedef struct {
   int64_t total;           /* sum of set sizes */
   int64_t examined;        /* IC: in-edges examined; LT: binary-search probes
                               charged as ceil(log2(indeg+1)) per expanded vertex */
   int64_t live;            /* IC: live in-edges found; LT: in-edges taken */
-  int64_t large_sets;      /* sets that took the large-set path (diagnostic) */
+  int64_t large_sets;      /* sets finished by the large-set path */
+  int64_t large_total;     /* ... their summed sizes */
+  int64_t large_examined;  /* ... their examined count */
+  int64_t large_live;      /* ... their live count */
+  double ms_main;          /* main sampling launch (small IC sets, or LT walks) */
+  double ms_large;         /* large-set launch (0 if none) */
+  double ms_canon;         /* size scan + gather into the canonical CSR */
 } im_sample_stats;
 
 /* Library version string. */

@@ -43,7 +43,9 @@ class _Graph(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("total", C.c_int64), ("examined", C.c_int64), ("live", C.c_int64),
-                ("large_sets", C.c_int64)]
+                ("large_sets", C.c_int64), ("large_total", C.c_int64),
+                ("large_examined", C.c_int64), ("large_live", C.c_int64),
+                ("ms_main", C.c_double), ("ms_large", C.c_double), ("ms_canon", C.c_double)]
 
 
 class _SolveOpts(C.Structure):
@@ -152,6 +154,7 @@ class RRR:
     examined: int
     live: int
     large_sets: int
+    stats: dict | None = None
 
     @property
     def count(self) -> int:
@@ -173,8 +176,9 @@ def sample_rrr(g: Graph, seed: int, stream_tag: int, first: int, count: int,
             cap = int(total.value)
             continue
         _check(st, "im_sample_rrr")
+        sd = {f: getattr(stats, f) for f, _ in _Stats._fields_}
         return RRR(off, mem[:total.value], int(total.value), int(stats.examined),
-                   int(stats.live), int(stats.large_sets))
+                   int(stats.live), int(stats.large_sets), sd)
     raise ImError(IM_ERANGE, "im_sample_rrr")
 
 

@@ -56,7 +56,8 @@ struct SampleArgs {
   int32_t* __restrict__ len;     // per sample: size (-1 while on the large path)
   uint32_t* __restrict__ big_list;
   unsigned long long* __restrict__ ctr;  // [0] work, [1] cursor, [2] big count,
-                                         // [3] examined, [4] live, [5] big work
+                                         // [3] examined, [4] live, [5] big work,
+                                         // [6] big examined, [7] big live, [8] big total
 };
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t v, int bits) {
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs 
   const int t = threadIdx.x;
   const uint64_t seed = ((uint64_t)A.seed_hi << 32) | A.seed_lo;
   const uint32_t nbig = (uint32_t)A.ctr[2];
-  unsigned long long t_ex = 0, t_lv = 0;
+  unsigned long long t_ex = 0, t_lv = 0, t_tot = 0;
   for (;;) {
     if (t == 0) s_item = (uint32_t)atomicAdd(&A.ctr[5], 1ull);
     __syncthreads();
@@ -442,13 +443,16 @@ __global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs 
     }
     t_ex += s_ex;
     t_lv += s_lv;
+    if (t == 0) t_tot += (unsigned long long)tail;
     __syncthreads();
   }
   int64_t tot;
   (void)block_exclusive_scan64((int64_t)t_ex, scan_lds, &tot);
-  if (t == 0 && tot) atomicAdd(&A.ctr[3], (unsigned long long)tot);
+  if (t == 0 && tot) atomicAdd(&A.ctr[6], (unsigned long long)tot);
   (void)block_exclusive_scan64((int64_t)t_lv, scan_lds, &tot);
-  if (t == 0 && tot) atomicAdd(&A.ctr[4], (unsigned long long)tot);
+  if (t == 0 && tot) atomicAdd(&A.ctr[7], (unsigned long long)tot);
+  (void)block_exclusive_scan64((int64_t)t_tot, scan_lds, &tot);
+  if (t == 0 && tot) atomicAdd(&A.ctr[8], (unsigned long long)tot);
 }
 
 // ------------------------------------------------------------------ LT walks
@@ -661,23 +665,37 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     IM_HIP(hipMemsetAsync(off, 0, sizeof(int64_t), s));
     IM_HIP(hipStreamSynchronize(s));
     *total = 0;
-    if (stats) *stats = im_sample_stats{0, 0, 0, 0};
+    if (stats) *stats = im_sample_stats{};
     return IM_OK;
   }
   const uint32_t cnt = (uint32_t)count;
   // per-sample metadata: start (i64), len (i32), big list (u32), counters
-  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 64 + 256;
+  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 128 + 256;
   void* mp = nullptr;
   IM_TRY(scratch(s, kSlotSampleMeta, meta_bytes, &mp));
   unsigned long long* ctr = (unsigned long long*)mp;
-  int64_t* start = (int64_t*)((char*)mp + 64);
+  int64_t* start = (int64_t*)((char*)mp + 128);
   int32_t* lens = (int32_t*)(start + cnt);
   uint32_t* big_list = (uint32_t*)(lens + cnt);
 
   static thread_local int64_t last_total = 0;
   uint64_t arena_cap = (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total),
                                                    (int64_t)cnt * 2);
-  unsigned long long hc[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long hc[16] = {0};
+  // device times of the launches, only when statistics are requested
+  hipEvent_t ev[6] = {};
+  const bool timed = stats != nullptr;
+  if (timed)
+    for (auto& e : ev) IM_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    bool on;
+    ~EvGuard() {
+      if (on)
+        for (int j = 0; j < 6; ++j) (void)hipEventDestroy(e[j]);
+    }
+  } ev_guard{ev, timed};
+  float ms_main = 0.f, ms_large = 0.f, ms_canon = 0.f;
   const bool lt = g->model == IM_LT;
   for (int attempt = 0; attempt < 3; ++attempt) {
     void* ap = nullptr;
@@ -698,7 +716,8 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     A.len = lens;
     A.big_list = big_list;
     A.ctr = ctr;
-    IM_HIP(hipMemsetAsync(ctr, 0, 64, s));
+    IM_HIP(hipMemsetAsync(ctr, 0, 128, s));
+    if (timed) IM_HIP(hipEventRecord(ev[0], s));
     if (!lt) {
       const int blocks = di.num_cus * 8;
       k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(A);
@@ -715,8 +734,11 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       k_sample_lt<<<dim3(blocks), dim3(kLtBlock), 0, s>>>(A, lane_hash, lane_list);
     }
     IM_HIP(hipGetLastError());
+    if (timed) IM_HIP(hipEventRecord(ev[1], s));
     IM_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
     IM_HIP(hipStreamSynchronize(s));
+    if (timed) IM_HIP(hipEventElapsedTime(&ms_main, ev[0], ev[1]));
+    ms_large = 0.f;
     if (hc[2] > 0) {
       const uint32_t nbig = (uint32_t)hc[2];
       const uint32_t nwords = (uint32_t)(((int64_t)g->n + 31) / 32);
@@ -733,10 +755,13 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       Bg.bitmaps = (uint32_t*)bp;
       Bg.queues = (int32_t*)((char*)bp + (size_t)workers * nwords * 4);
       IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)workers * nwords * 4, s));
+      if (timed) IM_HIP(hipEventRecord(ev[2], s));
       k_sample_big<<<dim3(workers), dim3(kBigBlock), 0, s>>>(A, Bg);
       IM_HIP(hipGetLastError());
+      if (timed) IM_HIP(hipEventRecord(ev[3], s));
       IM_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
       IM_HIP(hipStreamSynchronize(s));
+      if (timed) IM_HIP(hipEventElapsedTime(&ms_large, ev[2], ev[3]));
     }
     if (hc[1] <= arena_cap) break;
     arena_cap = hc[1];  // deterministic: the retry produces the same sets
@@ -744,11 +769,25 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
   }
   const int64_t tot = (int64_t)hc[1];
   last_total = tot;
+  if (timed) IM_HIP(hipEventRecord(ev[4], s));
   IM_TRY(exclusive_scan_i32_to_i64(lens, (int64_t)cnt, off, s));
   *total = tot;
-  if (stats) *stats = im_sample_stats{tot, (int64_t)hc[3], (int64_t)hc[4], (int64_t)hc[2]};
+  auto fill_stats = [&]() {
+    if (!stats) return;
+    stats->total = tot;
+    stats->examined = (int64_t)(hc[3] + hc[6]);
+    stats->live = (int64_t)(hc[4] + hc[7]);
+    stats->large_sets = (int64_t)hc[2];
+    stats->large_total = (int64_t)hc[8];
+    stats->large_examined = (int64_t)hc[6];
+    stats->large_live = (int64_t)hc[7];
+    stats->ms_main = ms_main;
+    stats->ms_large = ms_large;
+    stats->ms_canon = ms_canon;
+  };
   if (tot > capacity) {
     IM_HIP(hipStreamSynchronize(s));
+    fill_stats();
     return IM_ERANGE;
   }
   void* ap = nullptr;
@@ -757,6 +796,9 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
   k_gather<<<dim3(std::max(gblocks, 1)), dim3(kGatherBlock), 0, s>>>(
       cnt, start, lens, off, (const int32_t*)ap, mem, lt ? 1 : 0);
   IM_HIP(hipGetLastError());
+  if (timed) IM_HIP(hipEventRecord(ev[5], s));
   IM_HIP(hipStreamSynchronize(s));
+  if (timed) IM_HIP(hipEventElapsedTime(&ms_canon, ev[4], ev[5]));
+  fill_stats();
   return IM_OK;
 }
