@@ -4,30 +4,28 @@
 // Sec. 3.2: k times, take the vertex of largest marginal coverage (lowest id
 // on ties).  The marginal coverage of every vertex is kept exactly as a count
 // of its still-uncovered samples: when a sample becomes covered, every member
-// of that sample loses one.  Both steps run in one persistent cooperative
-// launch with two grid barriers per pick:
-//   A. every workgroup reduces the per-tile maxima (redundantly, no barrier
-//      needed) to the argmax key (count << 32 | ~v);
-//   B. the samples of S(v*) are spread over the grid; newly covered samples
-//      decrement their members' counts and mark the members' tiles dirty;
-//   C. dirty tiles recompute their maxima.
-// The RandGreedi form runs all m partitions in the same launch: vertices are
-// laid out partition by partition, tiles never straddle partitions, and a
-// covered sample only decrements members of the partition that covered it
-// (Alg. 4 lines 1-2 with the full universe of samples, Sec. 3.4 S3).
-#include <hip/hip_cooperative_groups.h>
-
+// of that sample loses one.  Two launches per pick:
+//   A. every workgroup scans a tile of the counts for the argmax key
+//      (count << 32 | ~v) and folds it into a global atomic max;
+//   B. the samples of S(v*) are spread over the wavefronts; each newly
+//      covered sample is walked by a whole wavefront, decrementing counts.
+// A device-wide barrier inside one persistent kernel would need agent-scope
+// fences, which on this multi-die part write back and invalidate the L2 of
+// every wavefront's die; a kernel boundary does that once.
+// The RandGreedi form runs all m partitions in the same launch: counts are
+// laid out partition by partition, each partition keeps its own covered flags
+// over the full universe of samples, and a covered sample only decrements the
+// members of the partition that covered it (Alg. 4 lines 1-2, Sec. 3.4 S3).
 #include <algorithm>
 #include <vector>
 
 #include "common.h"
 
-namespace cg = cooperative_groups;
-
 namespace im {
 
-constexpr int kGBlock = 256;
-constexpr int kTile = 1024;  // vertices per tile (4 per thread)
+constexpr int kGBlock = 1024;
+constexpr int kArgTile = kGBlock * 8;  // positions per workgroup in the argmax pass
+constexpr int kApplyBlock = 256;
 constexpr int kMaxParts = 256;
 
 struct CoverArgs {
@@ -39,115 +37,133 @@ struct CoverArgs {
   const int32_t* __restrict__ mem;
   const int64_t* __restrict__ inc_off;
   const int32_t* __restrict__ inc_mem;
-  const uint8_t* __restrict__ part;      // n (nullptr when m == 1)
-  const int32_t* __restrict__ order;     // n: vertices partition by partition (nullptr: identity)
-  const int32_t* __restrict__ tile_of;   // n: tile of each vertex (nullptr: v / kTile)
-  const int32_t* __restrict__ tile_lo;   // ntiles: first position in `order`
-  const int32_t* __restrict__ tile_hi;   // ntiles: end position
-  const int32_t* __restrict__ part_tile; // m+1: tiles of partition p
-  int32_t ntiles;
-  uint32_t* __restrict__ cnt;            // n
+  const int32_t* __restrict__ order;     // n: vertex at each position (nullptr: identity)
+  const int32_t* __restrict__ pos_of;    // n: position of each vertex (nullptr: identity)
+  const int64_t* __restrict__ pbase;     // m+1: positions of partition p (nullptr: [0, n))
+  uint32_t* __restrict__ cnt;            // n, by position: uncovered samples of the vertex
   uint8_t* __restrict__ covered;         // m * count
-  uint64_t* __restrict__ tile_max;       // ntiles
-  uint32_t* __restrict__ dirty;          // ntiles
-  int64_t* __restrict__ slice_pre;       // m+1 (scratch for the flattened slices)
+  unsigned long long* __restrict__ gmax; // k * m argmax keys, one row per pick
+  int32_t* __restrict__ done;            // set once no partition can gain
   int32_t* __restrict__ seeds;           // m*k
   int64_t* __restrict__ gains;           // m*k
   int32_t* __restrict__ nsel;            // m
   int64_t* __restrict__ cover;           // m
 };
 
-__device__ __forceinline__ uint64_t block_max_u64(uint64_t x, uint64_t* lds) {
+__device__ __forceinline__ int64_t part_lo(const CoverArgs& A, int p) {
+  return A.pbase ? A.pbase[p] : 0;
+}
+__device__ __forceinline__ int64_t part_hi(const CoverArgs& A, int p) {
+  return A.pbase ? A.pbase[p + 1] : (int64_t)A.n;
+}
+
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x,
+                                                            unsigned long long* lds) {
   x = wave_max_u64(x);
   const int w = threadIdx.x / kWave;
   if (lane_id() == 0) lds[w] = x;
   __syncthreads();
-  uint64_t r = 0;
-  for (int j = 0; j < kGBlock / kWave; ++j) r = lds[j] > r ? lds[j] : r;
+  unsigned long long r = 0;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r = lds[j] > r ? lds[j] : r;
   __syncthreads();
   return r;
 }
 
-__device__ __forceinline__ uint64_t tile_reduce(const CoverArgs& A, int tile, uint64_t* lds) {
-  const int32_t lo = A.tile_lo ? A.tile_lo[tile] : tile * kTile;
-  const int32_t hi = A.tile_hi ? A.tile_hi[tile] : min((tile + 1) * kTile, A.n);
-  uint64_t best = 0;
-  for (int32_t pos = lo + threadIdx.x; pos < hi; pos += kGBlock) {
-    const int32_t v = A.order ? A.order[pos] : pos;
-    const uint64_t key = argmax_key(A.cnt[v], (uint32_t)v);
-    best = key > best ? key : best;
+// Counts start at |S(v)|; nothing is covered; no argmax yet.
+__global__ __launch_bounds__(kGBlock) void k_cover_init(CoverArgs A) {
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t pos = gtid; pos < A.n; pos += gthreads) {
+    const int32_t v = A.order ? A.order[pos] : (int32_t)pos;
+    A.cnt[pos] = (uint32_t)(A.inc_off[v + 1] - A.inc_off[v]);
   }
-  return block_max_u64(best, lds);
+  for (int64_t j = gtid; j < (int64_t)A.m * A.count; j += gthreads) A.covered[j] = 0;
+  for (int64_t j = gtid; j < (int64_t)A.m * A.k; j += gthreads) A.gmax[j] = 0ull;
+  if (gtid == 0) *A.done = 0;
 }
 
-__global__ __launch_bounds__(kGBlock) void k_cover(CoverArgs A) {
-  cg::grid_group grid = cg::this_grid();
-  __shared__ uint64_t red[kGBlock / kWave];
-  __shared__ uint64_t pbest[kMaxParts];
-  __shared__ int64_t pre[kMaxParts + 1];
-  const int64_t gtid = (int64_t)blockIdx.x * kGBlock + threadIdx.x;
-  const int64_t gthreads = (int64_t)gridDim.x * kGBlock;
+// Pick `it`, step 1: every workgroup reduces one tile of positions to the
+// argmax key (count << 32 | ~v) of each partition it overlaps.
+__global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
+  __shared__ unsigned long long red[kGBlock / kWave];
+  if (*A.done) return;
+  const int64_t b0 = (int64_t)blockIdx.x * kArgTile;
+  const int64_t b1 = min((int64_t)A.n, b0 + kArgTile);
+  int p = 0;
+  if (A.m > 1) {  // first partition overlapping the tile
+    int lo = 0, hi = A.m - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (A.pbase[mid] <= b0)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    p = lo;
+  }
+  for (; p < A.m; ++p) {
+    const int64_t lo = max(b0, part_lo(A, p)), hi = min(b1, part_hi(A, p));
+    if (lo >= b1) break;
+    unsigned long long best = 0ull;
+    for (int64_t pos = lo + threadIdx.x; pos < hi; pos += kGBlock) {
+      const int32_t v = A.order ? A.order[pos] : (int32_t)pos;
+      const unsigned long long key = argmax_key(A.cnt[pos], (uint32_t)v);
+      best = key > best ? key : best;
+    }
+    best = block_max_u64(best, red);
+    if (threadIdx.x == 0 && best) atomicMax(&A.gmax[(int64_t)it * A.m + p], best);
+  }
+}
 
-  // init: counts = |S(v)|, nothing covered, all tiles fresh
-  for (int64_t v = gtid; v < A.n; v += gthreads)
-    A.cnt[v] = (uint32_t)(A.inc_off[v + 1] - A.inc_off[v]);
-  for (int64_t j = gtid; j < (int64_t)A.m * A.count; j += gthreads) A.covered[j] = 0;
-  grid.sync();
-  for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
-    const uint64_t b = tile_reduce(A, t, red);
-    if (threadIdx.x == 0) {
-      A.tile_max[t] = b;
-      A.dirty[t] = 0;
+// Pick `it`, step 2: record the picks, cover their covering subsets, and
+// decrement the counts of the members of every newly covered sample.  Each
+// wavefront takes 64 consecutive entries of the picks' subsets; a newly
+// covered sample is then walked by the whole wavefront.
+__global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it) {
+  __shared__ unsigned long long pbest[kMaxParts];
+  __shared__ int64_t pre[kMaxParts + 1];
+  if (*A.done) return;
+  const int tid = threadIdx.x, lane = lane_id();
+  const int m = A.m;
+  const unsigned long long* gm = A.gmax + (int64_t)it * m;
+  if (tid == 0) {
+    int64_t acc = 0;
+    for (int p = 0; p < m; ++p) {
+      const unsigned long long b = gm[p];
+      pbest[p] = b;
+      pre[p] = acc;
+      if (key_count(b) > 0) {
+        const uint32_t v = key_vertex(b);
+        acc += A.inc_off[v + 1] - A.inc_off[v];
+      }
+    }
+    pre[m] = acc;
+  }
+  __syncthreads();
+  const int64_t tot = pre[m];
+  if (tot == 0) {  // no partition has anything left to gain
+    if (blockIdx.x == 0 && tid == 0) *A.done = 1;
+    return;
+  }
+  if (blockIdx.x == 0) {
+    for (int p = tid; p < m; p += kApplyBlock) {
+      const unsigned long long b = pbest[p];
+      if (key_count(b) > 0) {
+        A.seeds[(int64_t)p * A.k + it] = (int32_t)key_vertex(b);
+        A.gains[(int64_t)p * A.k + it] = (int64_t)key_count(b);
+      }
     }
   }
-  grid.sync();
-
-  int32_t picks = 0;
-  for (int it = 0; it < A.k; ++it) {
-    // A: per-partition argmax over tile maxima (every block, same result)
-    for (int p = threadIdx.x; p < A.m; p += kGBlock) pbest[p] = 0;
-    __syncthreads();
-    for (int p = 0; p < A.m; ++p) {
-      const int t0 = A.part_tile ? A.part_tile[p] : 0;
-      const int t1 = A.part_tile ? A.part_tile[p + 1] : A.ntiles;
-      uint64_t b = 0;
-      for (int t = t0 + threadIdx.x; t < t1; t += kGBlock) {
-        const uint64_t x = A.tile_max[t];
-        b = x > b ? x : b;
-      }
-      b = block_max_u64(b, red);
-      if (threadIdx.x == 0) pbest[p] = b;
-    }
-    __syncthreads();
-    // flattened slices of the picks with a positive gain
-    if (threadIdx.x == 0) {
-      int64_t acc = 0;
-      for (int p = 0; p < A.m; ++p) {
-        pre[p] = acc;
-        const uint64_t b = pbest[p];
-        if (key_count(b) > 0) {
-          const uint32_t v = key_vertex(b);
-          acc += A.inc_off[v + 1] - A.inc_off[v];
-        }
-      }
-      pre[A.m] = acc;
-    }
-    __syncthreads();
-    if (pre[A.m] == 0) break;  // no partition has anything left to gain
-    if (blockIdx.x == 0) {
-      for (int p = threadIdx.x; p < A.m; p += kGBlock) {
-        const uint64_t b = pbest[p];
-        if (key_count(b) > 0) {
-          A.seeds[(int64_t)p * A.k + it] = (int32_t)key_vertex(b);
-          A.gains[(int64_t)p * A.k + it] = (int64_t)key_count(b);
-        }
-      }
-    }
-    ++picks;
-    // B: cover S(v*_p) for every partition
-    const int64_t tot = pre[A.m];
-    for (int64_t f = gtid; f < tot; f += gthreads) {
-      int lo = 0, hi = A.m - 1;  // partition owning flat index f
+  const int64_t gtid = (int64_t)blockIdx.x * kApplyBlock + tid;
+  const int64_t nchunks = (tot + kWave - 1) / kWave;
+  const int64_t wid = gtid / kWave, nw = (int64_t)gridDim.x * kApplyBlock / kWave;
+  for (int64_t c = wid; c < nchunks; c += nw) {
+    const int64_t f = c * kWave + lane;
+    int p = 0;
+    int32_t smp = -1;
+    bool fresh = false;
+    if (f < tot) {
+      int lo = 0, hi = m - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (pre[mid] <= f)
@@ -155,51 +171,50 @@ __global__ __launch_bounds__(kGBlock) void k_cover(CoverArgs A) {
         else
           hi = mid - 1;
       }
-      const int p = lo;
+      p = lo;
       const uint32_t v = key_vertex(pbest[p]);
-      const int32_t smp = A.inc_mem[A.inc_off[v] + (f - pre[p])];
+      smp = A.inc_mem[A.inc_off[v] + (f - pre[p])];
       uint8_t* cov = A.covered + (int64_t)p * A.count;
-      if (cov[smp]) continue;
-      cov[smp] = 1;
-      for (int64_t t = A.off[smp]; t < A.off[smp + 1]; ++t) {
+      if (!cov[smp]) {  // each sample occurs once in S(v), so no race
+        cov[smp] = 1;
+        fresh = true;
+      }
+    }
+    unsigned long long todo = __ballot(fresh);
+    while (todo) {
+      const int src = __ffsll(todo) - 1;
+      todo &= todo - 1;
+      const int32_t s_smp = __shfl(smp, src, kWave);
+      const int s_p = __shfl(p, src, kWave);
+      const int64_t lo_p = part_lo(A, s_p), hi_p = part_hi(A, s_p);
+      const int64_t a = A.off[s_smp], b = A.off[s_smp + 1];
+      for (int64_t t = a + lane; t < b; t += kWave) {
         const int32_t u = A.mem[t];
-        if (A.part && A.part[u] != (uint8_t)p) continue;
-        atomicSub(&A.cnt[u], 1u);
-        const int32_t tile = A.tile_of ? A.tile_of[u] : u / kTile;
-        if (!A.dirty[tile]) A.dirty[tile] = 1;
+        const int64_t pos = A.pos_of ? A.pos_of[u] : u;
+        if (pos >= lo_p && pos < hi_p) atomicSub(&A.cnt[pos], 1u);
       }
-    }
-    grid.sync();
-    // C: refresh dirty tiles
-    for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
-      if (!A.dirty[t]) continue;  // uniform per block
-      const uint64_t b = tile_reduce(A, t, red);
-      if (threadIdx.x == 0) {
-        A.tile_max[t] = b;
-        A.dirty[t] = 0;
-      }
-    }
-    grid.sync();
-  }
-  // outputs: per partition, picks with positive gain
-  if (blockIdx.x == 0) {
-    for (int p = threadIdx.x; p < A.m; p += kGBlock) {
-      int32_t c = 0;
-      int64_t s = 0;
-      for (int it = 0; it < picks; ++it) {
-        const int64_t g = A.gains[(int64_t)p * A.k + it];
-        if (g <= 0) break;
-        ++c;
-        s += g;
-      }
-      for (int it = c; it < A.k; ++it) {
-        A.seeds[(int64_t)p * A.k + it] = -1;
-        A.gains[(int64_t)p * A.k + it] = 0;
-      }
-      A.nsel[p] = c;
-      A.cover[p] = s;
     }
   }
+}
+
+// Per partition: the picks with a positive gain, their count and coverage.
+__global__ void k_cover_finish(CoverArgs A) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= A.m) return;
+  int32_t c = 0;
+  int64_t s = 0;
+  for (int it = 0; it < A.k; ++it) {
+    const int64_t g = A.gains[(int64_t)p * A.k + it];
+    if (g <= 0) break;
+    ++c;
+    s += g;
+  }
+  for (int it = c; it < A.k; ++it) {
+    A.seeds[(int64_t)p * A.k + it] = -1;
+    A.gains[(int64_t)p * A.k + it] = 0;
+  }
+  A.nsel[p] = c;
+  A.cover[p] = s;
 }
 
 // Partition draw: part(v) = floor(draw(part_seed, PART, 0, 0, v) * m / 2^32).
@@ -245,27 +260,29 @@ __global__ __launch_bounds__(kGBlock) void k_part_order(int32_t n, const uint8_t
   }
 }
 
-__global__ void k_tile_of(int32_t n, const int32_t* __restrict__ order,
-                          const uint8_t* __restrict__ part, const int64_t* __restrict__ pbase,
-                          const int32_t* __restrict__ part_tile, int32_t* __restrict__ tile_of) {
+__global__ void k_pos_of(int32_t n, const int32_t* __restrict__ order,
+                         int32_t* __restrict__ pos_of) {
   const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= n) return;
-  const int32_t v = order[pos];
-  const int q = part[v];
-  tile_of[v] = part_tile[q] + (int32_t)((pos - pbase[q]) / kTile);
+  if (pos < n) pos_of[order[pos]] = (int32_t)pos;
 }
 
+// k picks = 2k small launches; kernel boundaries make each pass's writes
+// visible device-wide (one cache flush per launch rather than per wave).
 static int launch_cover(CoverArgs& A, hipStream_t s) {
   DeviceInfo di;
   IM_TRY(device_info(&di));
-  int per_cu = 0;
-  IM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_cover, kGBlock, 0));
-  if (per_cu < 1) per_cu = 1;
-  int64_t want = std::max<int64_t>(A.ntiles, 1);
-  int64_t blocks = std::min<int64_t>((int64_t)per_cu * di.num_cus, std::max<int64_t>(want, di.num_cus));
-  void* args[] = {&A};
-  IM_HIP(hipLaunchCooperativeKernel((const void*)k_cover, dim3((unsigned)blocks), dim3(kGBlock),
-                                    args, 0, s));
+  const int64_t init_blocks = std::min<int64_t>(
+      std::max<int64_t>(((int64_t)A.n + kGBlock - 1) / kGBlock, 1), (int64_t)di.num_cus * 4);
+  k_cover_init<<<dim3((unsigned)init_blocks), dim3(kGBlock), 0, s>>>(A);
+  IM_HIP(hipGetLastError());
+  const unsigned arg_blocks = (unsigned)std::max<int64_t>(((int64_t)A.n + kArgTile - 1) / kArgTile, 1);
+  const unsigned apply_blocks = (unsigned)di.num_cus * 4;
+  for (int it = 0; it < A.k; ++it) {
+    k_cover_argmax<<<dim3(arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
+    k_cover_apply<<<dim3(apply_blocks), dim3(kApplyBlock), 0, s>>>(A, it);
+  }
+  k_cover_finish<<<dim3((unsigned)((A.m + 255) / 256)), dim3(256), 0, s>>>(A);
+  IM_HIP(hipGetLastError());
   return IM_OK;
 }
 
@@ -281,10 +298,9 @@ extern "C" int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, con
       !inc_off || !seeds || !gains || !nsel || !coverage || (total > 0 && (!mem || !inc_mem)))
     return IM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  const int32_t ntiles = (int32_t)(((int64_t)n + kTile - 1) / kTile);
-  const size_t bytes = (size_t)n * 4 + (size_t)count + 16 + (size_t)ntiles * 12 + 64;
+  const size_t bytes = 64 + (size_t)k * 8 + 64 + (size_t)n * 4 + (size_t)count + 64;
   void* p = nullptr;
-  IM_TRY(scratch(s, kSlotGreedy, bytes + 64, &p));
+  IM_TRY(scratch(s, kSlotGreedy, bytes, &p));
   char* c = (char*)p;
   CoverArgs A{};
   A.n = n;
@@ -295,14 +311,12 @@ extern "C" int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, con
   A.mem = mem;
   A.inc_off = inc_off;
   A.inc_mem = inc_mem;
-  A.ntiles = ntiles;
-  A.tile_max = (uint64_t*)c;
-  c += (size_t)ntiles * 8;
+  A.done = (int32_t*)c;
+  c += 64;
+  A.gmax = (unsigned long long*)c;
+  c += ((size_t)k * 8 + 63) / 64 * 64;
   A.cnt = (uint32_t*)c;
   c += (size_t)n * 4;
-  A.dirty = (uint32_t*)c;
-  c += (size_t)ntiles * 4;
-  A.slice_pre = nullptr;
   A.covered = (uint8_t*)c;
   A.seeds = seeds;
   A.gains = gains;
@@ -322,38 +336,29 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
       (total > 0 && (!mem || !inc_mem)))
     return IM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  // partition, then lay vertices out partition by partition
   k_partition<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
       n, m, (uint32_t)part_seed, (uint32_t)(part_seed >> 32), part);
   IM_HIP(hipGetLastError());
-  // scratch: hist(m u32) pbase(m+1 i64) order(n) tile_of(n) cnt(n) tiles... covered(m*count)
-  const int64_t max_tiles = ((int64_t)n + kTile - 1) / kTile + m;
-  const size_t bytes = (size_t)m * 4 + (size_t)(m + 1) * 8 + (size_t)n * 12 +
-                       (size_t)max_tiles * (8 + 4 + 4 + 4) + (size_t)(m + 1) * 4 +
-                       (size_t)m * (size_t)count + 256;
+  // scratch: gmax(k*m) | done | pbase(m+1) | hist(m) | order(n) | pos_of(n) | cnt(n) | covered(m*count)
+  const size_t bytes = (size_t)m * k * 8 + 64 + 64 + (size_t)(m + 1) * 8 + (size_t)m * 4 + 64 +
+                       (size_t)n * 12 + (size_t)m * (size_t)count + 256;
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotLocal, bytes, &p));
   char* c = (char*)p;
-  uint64_t* tile_max = (uint64_t*)c;
-  c += (size_t)max_tiles * 8;
+  unsigned long long* gmax = (unsigned long long*)c;
+  c += ((size_t)m * k * 8 + 63) / 64 * 64;
+  int32_t* done = (int32_t*)c;
+  c += 64;
   int64_t* pbase = (int64_t*)c;
   c += (size_t)(m + 1) * 8;
   uint32_t* hist = (uint32_t*)c;
-  c += (size_t)m * 4;
+  c += ((size_t)m * 4 + 63) / 64 * 64;
   int32_t* order = (int32_t*)c;
   c += (size_t)n * 4;
-  int32_t* tile_of = (int32_t*)c;
+  int32_t* pos_of = (int32_t*)c;
   c += (size_t)n * 4;
   uint32_t* cnt = (uint32_t*)c;
   c += (size_t)n * 4;
-  int32_t* tile_lo = (int32_t*)c;
-  c += (size_t)max_tiles * 4;
-  int32_t* tile_hi = (int32_t*)c;
-  c += (size_t)max_tiles * 4;
-  uint32_t* dirty = (uint32_t*)c;
-  c += (size_t)max_tiles * 4;
-  int32_t* part_tile = (int32_t*)c;
-  c += (size_t)(m + 1) * 4;
   uint8_t* covered = (uint8_t*)c;
   IM_HIP(hipMemsetAsync(hist, 0, (size_t)m * 4, s));
   k_part_hist<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, part, hist);
@@ -362,29 +367,12 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   IM_HIP(hipMemcpyAsync(hh.data(), hist, (size_t)m * 4, hipMemcpyDeviceToHost, s));
   IM_HIP(hipStreamSynchronize(s));
   std::vector<int64_t> hb(m + 1);
-  std::vector<int32_t> hpt(m + 1), htlo, hthi;
   hb[0] = 0;
   for (int q = 0; q < m; ++q) hb[q + 1] = hb[q] + hh[q];
-  int32_t nt = 0;
-  for (int q = 0; q < m; ++q) {
-    hpt[q] = nt;
-    for (int64_t lo = hb[q]; lo < hb[q + 1]; lo += kTile) {
-      htlo.push_back((int32_t)lo);
-      hthi.push_back((int32_t)std::min<int64_t>(lo + kTile, hb[q + 1]));
-      ++nt;
-    }
-  }
-  hpt[m] = nt;
   IM_HIP(hipMemcpyAsync(pbase, hb.data(), (size_t)(m + 1) * 8, hipMemcpyHostToDevice, s));
-  IM_HIP(hipMemcpyAsync(part_tile, hpt.data(), (size_t)(m + 1) * 4, hipMemcpyHostToDevice, s));
-  if (nt > 0) {
-    IM_HIP(hipMemcpyAsync(tile_lo, htlo.data(), (size_t)nt * 4, hipMemcpyHostToDevice, s));
-    IM_HIP(hipMemcpyAsync(tile_hi, hthi.data(), (size_t)nt * 4, hipMemcpyHostToDevice, s));
-  }
   k_part_order<<<dim3(m), dim3(kGBlock), 0, s>>>(n, part, pbase, order);
   IM_HIP(hipGetLastError());
-  k_tile_of<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, order, part, pbase,
-                                                                   part_tile, tile_of);
+  k_pos_of<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, order, pos_of);
   IM_HIP(hipGetLastError());
   CoverArgs A{};
   A.n = n;
@@ -395,21 +383,21 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   A.mem = mem;
   A.inc_off = inc_off;
   A.inc_mem = inc_mem;
-  A.part = part;
   A.order = order;
-  A.tile_of = tile_of;
-  A.tile_lo = tile_lo;
-  A.tile_hi = tile_hi;
-  A.part_tile = part_tile;
-  A.ntiles = nt;
+  A.pos_of = pos_of;
+  A.pbase = pbase;
   A.cnt = cnt;
   A.covered = covered;
-  A.tile_max = tile_max;
-  A.dirty = dirty;
+  A.gmax = gmax;
+  A.done = done;
   A.seeds = lseeds;
   A.gains = lgains;
   A.nsel = lcount;
   A.cover = lcover;
   IM_HIP(hipMemsetAsync(lgains, 0, (size_t)m * k * 8, s));
-  return launch_cover(A, s);
+  int st = launch_cover(A, s);
+  if (st != IM_OK) return st;
+  // the host copy of hb must outlive the async copy
+  IM_HIP(hipStreamSynchronize(s));
+  return IM_OK;
 }

@@ -25,6 +25,9 @@
 //    exclusive scan of the sizes gives the canonical CSR offsets and a gather
 //    copies (and, for LT, sorts) each set into place.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "common.h"
 
@@ -34,7 +37,8 @@ constexpr int kSmallBlock = 256;            // 4 waves, each its own sample
 constexpr int kSmallH = 512;                // LDS hash slots per wave
 constexpr int kSmallCap = 256;              // members before handing off
 constexpr int kBigBlock = 256;
-constexpr int kBigSortCap = 4096;           // large sets up to this size sort in LDS
+constexpr int kBigSortCap = 2048;           // large sets up to this size sort in LDS
+constexpr uint32_t kMaxHandoff = 1u << 16;  // large sets that resume from a snapshot
 constexpr int kLtH = 2048;                  // per-lane HBM hash slots (LT)
 constexpr int kLtCap = 1024;                // per-lane walk length before handing off
 constexpr int kLtBlock = 256;
@@ -55,6 +59,7 @@ struct SampleArgs {
   int64_t* __restrict__ start;   // per sample: arena position
   int32_t* __restrict__ len;     // per sample: size (-1 while on the large path)
   uint32_t* __restrict__ big_list;
+  struct Handoff* __restrict__ handoff;  // kMaxHandoff snapshots (IC)
   unsigned long long* __restrict__ ctr;  // [0] work, [1] cursor, [2] big count,
                                          // [3] examined, [4] live, [5] big work,
                                          // [6] big examined, [7] big live, [8] big total
@@ -68,6 +73,15 @@ __device__ __forceinline__ uint32_t ceil_log2_plus1(int32_t d) {
   // ceil(log2(d + 1)) for d >= 1
   return 32u - (uint32_t)__clz((uint32_t)d);
 }
+
+// A set handed from the small to the large path resumes from the state it had
+// at the start of the round that overflowed: members [0, tail), of which
+// [0, head) are expanded, and the exact counters of those expansions.
+struct Handoff {
+  int32_t mem[kSmallCap];
+  int32_t head, tail;
+  unsigned long long ex, lv;
+};
 
 // ------------------------------------------------------------------ IC small
 struct __align__(16) WaveLds {
@@ -135,7 +149,13 @@ __global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
     int32_t head = 0, tail = 1;
     bool over = false;
     unsigned long long s_ex = 0, s_lv = 0;
+    int32_t head0 = 0, tail0 = 1;
+    unsigned long long ex0 = 0, lv0 = 0;
     while (head < tail) {
+      head0 = head;  // snapshot for a hand-off
+      tail0 = tail;
+      ex0 = s_ex;
+      lv0 = s_lv;
       const int32_t nf = min(tail - head, kWave);
       int32_t a = 0, b = 0, ng = 0;
       if (lane < nf) {
@@ -191,11 +211,25 @@ __global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
       }
     }
     if (over) {
+      const unsigned long long hex = wave_sum(ex0), hlv = wave_sum(lv0);
+      uint32_t slot = 0;
+      if (lane == 0) slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
+      slot = __shfl(slot, 0, kWave);
+      if (slot < kMaxHandoff) {
+        Handoff& H = A.handoff[slot];
+        for (int j = lane; j < tail0; j += kWave) H.mem[j] = L.queue[j];
+        if (lane == 0) {
+          H.head = head0;
+          H.tail = tail0;
+          H.ex = hex;
+          H.lv = hlv;
+        }
+      }
       if (lane == 0) {
-        uint32_t slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
         A.big_list[slot] = il;
         A.len[il] = -1;
       }
+      wave_sync();
       continue;
     }
     // sort queue[0, tail) ascending (bitonic over the next power of two)
@@ -297,13 +331,27 @@ __global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs 
         (int32_t)scale_draw(draw1(seed, kTagRoot, A.stream, 0u, i), (uint32_t)A.n);
     unsigned long long s_ex = 0, s_lv = 0;
     if (Bg.model == IM_IC) {
-      if (t == 0) {
+      int32_t head = 0, tail = 1;
+      if (item < kMaxHandoff) {  // resume from the small path's snapshot
+        const Handoff& H = A.handoff[item];
+        head = H.head;
+        tail = H.tail;
+        for (int j = t; j < tail; j += kBigBlock) {
+          const int32_t u = H.mem[j];
+          queue[j] = u;
+          atomicOr(&bm[u >> 5], 1u << (u & 31));
+        }
+        if (t == 0) {
+          s_tail = tail;
+          s_ex = H.ex;
+          s_lv = H.lv;
+        }
+      } else if (t == 0) {
         bm[root >> 5] = 1u << (root & 31);
         queue[0] = root;
         s_tail = 1;
       }
       __syncthreads();
-      int32_t head = 0, tail = 1;
       while (head < tail) {
         const int32_t nf = min(tail - head, kBigBlock);
         int32_t a = 0, b = 0, ng = 0;
@@ -670,13 +718,16 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
   }
   const uint32_t cnt = (uint32_t)count;
   // per-sample metadata: start (i64), len (i32), big list (u32), counters
-  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 128 + 256;
+  const uint32_t nhand = std::min<uint32_t>(cnt, kMaxHandoff);
+  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 128 + 256 +
+                            (size_t)nhand * sizeof(Handoff) + 64;
   void* mp = nullptr;
   IM_TRY(scratch(s, kSlotSampleMeta, meta_bytes, &mp));
   unsigned long long* ctr = (unsigned long long*)mp;
   int64_t* start = (int64_t*)((char*)mp + 128);
   int32_t* lens = (int32_t*)(start + cnt);
   uint32_t* big_list = (uint32_t*)(lens + cnt);
+  Handoff* handoff = (Handoff*)(((uintptr_t)(big_list + cnt) + 63) & ~(uintptr_t)63);
 
   static thread_local int64_t last_total = 0;
   uint64_t arena_cap = (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total),
@@ -715,6 +766,7 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     A.start = start;
     A.len = lens;
     A.big_list = big_list;
+    A.handoff = handoff;
     A.ctr = ctr;
     IM_HIP(hipMemsetAsync(ctr, 0, 128, s));
     if (timed) IM_HIP(hipEventRecord(ev[0], s));
@@ -744,17 +796,36 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       const uint32_t nwords = (uint32_t)(((int64_t)g->n + 31) / 32);
       // workers each hold an n-bit bitmap and an n-entry queue
       const size_t per_worker = (size_t)nwords * 4 + (size_t)g->n * 4;
-      uint32_t workers = std::min<uint32_t>(nbig, (uint32_t)di.num_cus * 2);
-      const size_t budget = (size_t)8 << 30;
-      while (workers > 1 && (size_t)workers * per_worker > budget) workers >>= 1;
+      // up to 8 workers per CU, within a 16 GiB budget; the bitmaps are zero
+      // between uses (each set clears its own bits), so only a new buffer
+      // needs clearing
+      const uint32_t max_workers = (uint32_t)di.num_cus * 8;
+      uint32_t cap_workers = max_workers;
+      const size_t budget = (size_t)16 << 30;
+      while (cap_workers > 1 && (size_t)cap_workers * per_worker > budget) cap_workers >>= 1;
+      const uint32_t workers = std::min<uint32_t>(nbig, cap_workers);
       void* bp = nullptr;
-      IM_TRY(scratch(s, kSlotSampleBig, (size_t)workers * per_worker, &bp));
+      bool bfresh = false;
+      IM_TRY(scratch_fresh(s, kSlotSampleBig, (size_t)cap_workers * per_worker, &bp, &bfresh));
       BigArgs Bg;
       Bg.model = g->model;
       Bg.nwords = nwords;
       Bg.bitmaps = (uint32_t*)bp;
-      Bg.queues = (int32_t*)((char*)bp + (size_t)workers * nwords * 4);
-      IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)workers * nwords * 4, s));
+      Bg.queues = (int32_t*)((char*)bp + (size_t)cap_workers * nwords * 4);
+      // the zero invariant only holds for the layout that last used the buffer
+      static std::mutex layout_mu;
+      static std::map<std::pair<void*, uintptr_t>, std::pair<uint32_t, uint32_t>> layouts;
+      bool same_layout = false;
+      {
+        std::lock_guard<std::mutex> lk(layout_mu);
+        auto key = std::make_pair(bp, (uintptr_t)s);
+        auto it = layouts.find(key);
+        same_layout = !bfresh && it != layouts.end() && it->second.first == nwords &&
+                      it->second.second == cap_workers;
+        layouts[key] = std::make_pair(nwords, cap_workers);
+      }
+      if (!same_layout)
+        IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)cap_workers * nwords * 4, s));
       if (timed) IM_HIP(hipEventRecord(ev[2], s));
       k_sample_big<<<dim3(workers), dim3(kBigBlock), 0, s>>>(A, Bg);
       IM_HIP(hipGetLastError());

@@ -66,7 +66,8 @@ def test_thresholds(im, name):
 
 @pytest.mark.parametrize("name,first,count", [
     ("ic_sparse", 0, 3000), ("ic_dense", 17, 2001), ("ic_p1", 5, 700), ("lt_small", 0, 4000),
-    ("lt_chain", 3, 600), ("rmat12", 0, 16384), ("rmat12", 100000, 999)])
+    ("lt_chain", 3, 600), ("rmat12", 0, 16384), ("rmat12", 100000, 999),
+    ("ic_p1", 0, 70000)])
 def test_sample_rrr(im, name, first, count):
     _say("sample", name, first, count)
     g = GRAPHS[name]()
