@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.125)
     ap.add_argument("--cpu-sample", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -78,6 +80,17 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "copies": 3}), flush=True)
+        return
     t0 = time.time()
     w = W.config(args.config)
     g = w.graph
@@ -179,6 +192,7 @@ def main():
                          "incidence": round(ms_inc, 3), "greedy": round(ms_greedy, 3)},
         "counts": {"sum_rrr": st["total"], "examined_edges": st["examined"],
                    "live_edges": st["live"], "large_sets": st["large_sets"],
+                   "redo_examined": st["redo_examined"],
                    "coverage": cov0, "seeds_head": seeds0[:8]},
         "roofline": roofline,
     }

@@ -80,6 +80,8 @@ typedef struct {
   int64_t large_total;     /* ... their summed sizes */
   int64_t large_examined;  /* ... their examined count */
   int64_t large_live;      /* ... their live count */
+  int64_t redo_examined;   /* in-edges the main launch examined in rounds it
+                              abandoned when handing a set to the large path */
   double ms_main;          /* main sampling launch (small IC sets, or LT walks) */
   double ms_large;         /* large-set launch (0 if none) */
   double ms_canon;         /* size scan + gather into the canonical CSR */

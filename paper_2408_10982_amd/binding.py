@@ -45,7 +45,7 @@ class _Stats(C.Structure):
     _fields_ = [("total", C.c_int64), ("examined", C.c_int64), ("live", C.c_int64),
                 ("large_sets", C.c_int64), ("large_total", C.c_int64),
                 ("large_examined", C.c_int64), ("large_live", C.c_int64),
-                ("ms_main", C.c_double), ("ms_large", C.c_double), ("ms_canon", C.c_double)]
+                ("redo_examined", C.c_int64), ("ms_main", C.c_double), ("ms_large", C.c_double), ("ms_canon", C.c_double)]
 
 
 class _SolveOpts(C.Structure):

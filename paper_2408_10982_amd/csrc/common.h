@@ -19,7 +19,9 @@ constexpr int kWave = 64;
 // (id >> 2, sample, tag, stream), word id & 3).
 constexpr uint32_t kTagRoot = 0, kTagEdge = 1, kTagVert = 2, kTagPart = 3;
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each 32x32 product is
+// formed as one 64-bit product (a single v_mad_u64_u32 on gfx950) rather than
+// separate high and low multiplies.
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -27,9 +29,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t hi_a = __umulhi(0xD2511F53u, c.x), lo_a = 0xD2511F53u * c.x;
-    const uint32_t hi_b = __umulhi(0xCD9E8D57u, c.z), lo_b = 0xCD9E8D57u * c.z;
-    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+    const uint64_t pa = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * c.z;
+    c = make_uint4((uint32_t)(pb >> 32) ^ c.y ^ k0, (uint32_t)pb, (uint32_t)(pa >> 32) ^ c.w ^ k1,
+                   (uint32_t)pa);
   }
   return c;
 }

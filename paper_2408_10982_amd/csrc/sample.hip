@@ -62,11 +62,54 @@ struct SampleArgs {
   struct Handoff* __restrict__ handoff;  // kMaxHandoff snapshots (IC)
   unsigned long long* __restrict__ ctr;  // [0] work, [1] cursor, [2] big count,
                                          // [3] examined, [4] live, [5] big work,
-                                         // [6] big examined, [7] big live, [8] big total
+                                         // [6] big examined, [7] big live, [8] big total,
+                                         // [9] examined in abandoned rounds,
+                                         // [10] sum of set sizes
 };
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t v, int bits) {
   return ((uint32_t)v * 2654435761u) >> (32 - bits);
+}
+
+// Index of the frontier slot owning flat group gi: the first slot whose
+// inclusive group prefix exceeds gi (pre has NF entries, non-decreasing).
+template <int NF>
+__device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
+  int lo = 0, hi = NF - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] > gi)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+// Tuning knobs (compile-time): groups per lane per iteration, and an
+// occupancy hint for the two IC kernels.
+// Measured on MI355X (R-MAT 2^20, IC weighted cascade, 2^20 sets): two groups
+// per lane at 8 waves per SIMD beat four groups at 4 waves per SIMD by 22%.
+#ifndef IM_UNROLL
+#define IM_UNROLL 2
+#endif
+#ifndef IM_IC_WAVES_PER_EU
+#define IM_IC_WAVES_PER_EU 8
+#endif
+#define IM_IC_ATTR __attribute__((amdgpu_waves_per_eu(IM_IC_WAVES_PER_EU)))
+constexpr int kUnroll = IM_UNROLL;  // 4-edge groups per lane per iteration
+
+// Same-address atomics serialise at one coherence point, so work and arena
+// space are claimed in batches: kGrab sample ids (kLtGrab for LT) and kChunk
+// arena entries per atomic.
+constexpr uint32_t kGrab = 16;
+constexpr uint32_t kLtGrab = 256;
+constexpr unsigned long long kChunk = 1024;
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
+  const uint32_t lo = __shfl((uint32_t)x, src, kWave);
+  const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ uint32_t ceil_log2_plus1(int32_t d) {
@@ -123,16 +166,25 @@ __device__ __forceinline__ void lds_insert(WaveLds& L, int32_t u, bool* over) {
   }
 }
 
-__global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
+__global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(SampleArgs A) {
   __shared__ WaveLds lds_all[kSmallBlock / kWave];
   WaveLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
   unsigned long long w_ex = 0, w_lv = 0;  // per-lane sums of finished sets
+  unsigned long long w_tot = 0;            // members written by this wave
+  unsigned long long next = 0, end = 0;    // claimed sample ids
+  unsigned long long cpos = 0, cend = 0;   // reserved arena chunk
   for (;;) {
-    uint32_t il = 0;
-    if (lane == 0) il = (uint32_t)atomicAdd(&A.ctr[0], 1ull);
-    il = __shfl(il, 0, kWave);
-    if (il >= A.count) break;
+    wave_sync();
+    if (next == end) {
+      unsigned long long b = 0;
+      if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kGrab);
+      b = shfl_u64(b, 0);
+      if (b >= A.count) break;
+      next = b;
+      end = min(b + kGrab, (unsigned long long)A.count);
+    }
+    const uint32_t il = (uint32_t)next++;
     const uint32_t i = A.first + il;
     const int32_t root =
         (int32_t)scale_draw(draw1(((uint64_t)A.seed_hi << 32) | A.seed_lo, kTagRoot, A.stream,
@@ -173,30 +225,40 @@ __global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
       L.eb[lane] = b;
       head += nf;
       wave_sync();
-      for (int32_t base = 0; base < total; base += kWave) {
-        const int32_t gi = base + lane;
-        if (gi < total) {
-          int lo = 0, hi = kWave - 1;  // owner: first lane whose prefix exceeds gi
-          while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (L.pre[mid] > gi)
-              hi = mid;
-            else
-              lo = mid + 1;
-          }
-          const uint32_t g = (uint32_t)(L.gbase[lo] + gi);
-          const int32_t ea = L.ea[lo], eb = L.eb[lo];
-          const uint4 q = reinterpret_cast<const uint4*>(A.thr)[g];
-          const uint4 r = philox4x32_10(make_uint4(g, i, kTagEdge, A.stream), A.seed_lo,
-                                        A.seed_hi);
-          const int32_t e0 = (int32_t)(g << 2);
+      for (int32_t base = 0; base < total; base += kWave * kUnroll) {
+        // one owner for the whole chunk (a large in-edge list) skips the search
+        const int o_b = owner_of<kWave>(L.pre, base);
+        const bool uni = L.pre[o_b] >= min(total, base + kWave * kUnroll);
+        uint4 q[kUnroll];
+        uint32_t g[kUnroll];
+        int32_t ea[kUnroll], eb[kUnroll];
 #pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const int32_t e = e0 + w;
-            const uint32_t qw = pick_word(q, w), rw = pick_word(r, w);
-            if (e >= ea && e < eb && (qw == 0xFFFFFFFFu || rw < qw)) {
-              ++s_lv;
-              lds_insert(L, A.in_src[e], &over);
+        for (int u = 0; u < kUnroll; ++u) {
+          const int32_t gi = base + u * kWave + lane;
+          ea[u] = eb[u] = 0;
+          g[u] = 0;
+          if (gi < total) {
+            const int o = uni ? o_b : owner_of<kWave>(L.pre, gi);
+            g[u] = (uint32_t)(L.gbase[o] + gi);
+            ea[u] = L.ea[o];
+            eb[u] = L.eb[o];
+            q[u] = reinterpret_cast<const uint4*>(A.thr)[g[u]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (ea[u] < eb[u]) {
+            const uint4 r = philox4x32_10(make_uint4(g[u], i, kTagEdge, A.stream), A.seed_lo,
+                                          A.seed_hi);
+            const int32_t e0 = (int32_t)(g[u] << 2);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              const int32_t e = e0 + w;
+              const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
+              if (e >= ea[u] && e < eb[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
+                ++s_lv;
+                lds_insert(L, A.in_src[e], &over);
+              }
             }
           }
         }
@@ -212,6 +274,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
     }
     if (over) {
       const unsigned long long hex = wave_sum(ex0), hlv = wave_sum(lv0);
+      const unsigned long long redo = wave_sum(s_ex - ex0);
+      if (lane == 0 && redo) atomicAdd(&A.ctr[9], redo);
       uint32_t slot = 0;
       if (lane == 0) slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
       slot = __shfl(slot, 0, kWave);
@@ -252,9 +316,16 @@ __global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
         wave_sync();
       }
     }
-    unsigned long long pos = 0;
-    if (lane == 0) pos = atomicAdd(&A.ctr[1], (unsigned long long)tail);
-    pos = __shfl(pos, 0, kWave);
+    if (cpos + (unsigned long long)tail > cend) {
+      const unsigned long long want = max((unsigned long long)tail, kChunk);
+      unsigned long long b = 0;
+      if (lane == 0) b = atomicAdd(&A.ctr[1], want);
+      cpos = shfl_u64(b, 0);
+      cend = cpos + want;
+    }
+    const unsigned long long pos = cpos;
+    cpos += (unsigned long long)tail;
+    w_tot += (unsigned long long)tail;
     if (pos + (unsigned long long)tail <= A.arena_cap)
       for (int j = lane; j < tail; j += kWave) A.arena[pos + j] = L.queue[j];
     if (lane == 0) {
@@ -270,6 +341,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_sample_ic_small(SampleArgs A) {
   if (lane == 0) {
     if (w_ex) atomicAdd(&A.ctr[3], w_ex);
     if (w_lv) atomicAdd(&A.ctr[4], w_lv);
+    if (w_tot) atomicAdd(&A.ctr[10], w_tot);
   }
 }
 
@@ -303,7 +375,7 @@ __device__ __forceinline__ int64_t block_exclusive_scan64(int64_t x, int64_t* ld
 
 // One workgroup per large set: visited bitmap and queue in HBM (private to
 // the worker), members written in ascending order.
-__global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs Bg) {
+__global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
   __shared__ int32_t pre[kBigBlock];
   __shared__ int32_t gbase[kBigBlock];
   __shared__ int32_t ea[kBigBlock];
@@ -371,33 +443,42 @@ __global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs 
         eb[t] = b;
         head += nf;
         __syncthreads();
-        for (int32_t base = 0; base < total; base += kBigBlock) {
-          const int32_t gi = base + t;
-          if (gi < total) {
-            int lo = 0, hi = kBigBlock - 1;
-            while (lo < hi) {
-              int mid = (lo + hi) >> 1;
-              if (pre[mid] > gi)
-                hi = mid;
-              else
-                lo = mid + 1;
-            }
-            const uint32_t g = (uint32_t)(gbase[lo] + gi);
-            const int32_t e_a = ea[lo], e_b = eb[lo];
-            const uint4 q = reinterpret_cast<const uint4*>(A.thr)[g];
-            const uint4 r =
-                philox4x32_10(make_uint4(g, i, kTagEdge, A.stream), A.seed_lo, A.seed_hi);
-            const int32_t e0 = (int32_t)(g << 2);
+        for (int32_t base = 0; base < total; base += kBigBlock * kUnroll) {
+          const int o_b = owner_of<kBigBlock>(pre, base);
+          const bool uni = pre[o_b] >= min(total, base + kBigBlock * kUnroll);
+          uint4 q[kUnroll];
+          uint32_t g[kUnroll];
+          int32_t e_a[kUnroll], e_b[kUnroll];
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-              const int32_t e = e0 + w;
-              const uint32_t qw = pick_word(q, w), rw = pick_word(r, w);
-              if (e >= e_a && e < e_b && (qw == 0xFFFFFFFFu || rw < qw)) {
-                ++s_lv;
-                const int32_t u = A.in_src[e];
-                const uint32_t bit = 1u << (u & 31);
-                const uint32_t old = atomicOr(&bm[u >> 5], bit);
-                if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = u;
+          for (int u = 0; u < kUnroll; ++u) {
+            const int32_t gi = base + u * kBigBlock + t;
+            e_a[u] = e_b[u] = 0;
+            g[u] = 0;
+            if (gi < total) {
+              const int o = uni ? o_b : owner_of<kBigBlock>(pre, gi);
+              g[u] = (uint32_t)(gbase[o] + gi);
+              e_a[u] = ea[o];
+              e_b[u] = eb[o];
+              q[u] = reinterpret_cast<const uint4*>(A.thr)[g[u]];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            if (e_a[u] < e_b[u]) {
+              const uint4 r =
+                  philox4x32_10(make_uint4(g[u], i, kTagEdge, A.stream), A.seed_lo, A.seed_hi);
+              const int32_t e0 = (int32_t)(g[u] << 2);
+#pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                const int32_t e = e0 + w;
+                const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
+                if (e >= e_a[u] && e < e_b[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
+                  ++s_lv;
+                  const int32_t v2 = A.in_src[e];
+                  const uint32_t bit = 1u << (v2 & 31);
+                  const uint32_t old = atomicOr(&bm[v2 >> 5], bit);
+                  if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = v2;
+                }
               }
             }
           }
@@ -500,7 +581,10 @@ __global__ __launch_bounds__(kBigBlock) void k_sample_big(SampleArgs A, BigArgs 
   (void)block_exclusive_scan64((int64_t)t_lv, scan_lds, &tot);
   if (t == 0 && tot) atomicAdd(&A.ctr[7], (unsigned long long)tot);
   (void)block_exclusive_scan64((int64_t)t_tot, scan_lds, &tot);
-  if (t == 0 && tot) atomicAdd(&A.ctr[8], (unsigned long long)tot);
+  if (t == 0 && tot) {
+    atomicAdd(&A.ctr[8], (unsigned long long)tot);
+    atomicAdd(&A.ctr[10], (unsigned long long)tot);
+  }
 }
 
 // ------------------------------------------------------------------ LT walks
@@ -525,12 +609,6 @@ __device__ __forceinline__ void lt_erase(int32_t* H, int32_t u) {
   H[h] = kEmpty;
 }
 
-__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
-  const uint32_t lo = __shfl((uint32_t)x, src, kWave);
-  const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
 // One lane per walk.  Lanes take new samples as their walks end (aggregated
 // per wave), so a long walk does not hold up the other 63 lanes.  The per-lane
 // hash (kLtH slots) is empty between walks.
@@ -545,20 +623,29 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
   bool have = false, done = false;
   uint32_t il = 0, i = 0;
   int32_t v = 0, len = 0;
-  unsigned long long ex = 0, lv = 0, s_ex = 0, s_lv = 0;
+  unsigned long long ex = 0, lv = 0, s_ex = 0, s_lv = 0, w_tot = 0;
+  unsigned long long pnext = 0, pend = 0;  // this wave's pool of sample ids
+  bool dry = false;                        // no ids left anywhere
+  unsigned long long cpos = 0, cend = 0;   // reserved arena chunk
   for (;;) {
     const uint64_t need = __ballot(!have && !done);
     if (need) {
-      const int leader = __ffsll((unsigned long long)need) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(&A.ctr[0], (unsigned long long)__popcll(need));
-      base = shfl_u64(base, leader);
-      if (!have && !done) {
-        const unsigned long long mine = base + (unsigned long long)__popcll(need & below);
-        if (mine >= A.count) {
-          done = true;
+      if (pnext == pend && !dry) {
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kLtGrab);
+        b = shfl_u64(b, 0);
+        if (b >= A.count) {
+          dry = true;
         } else {
-          il = (uint32_t)mine;
+          pnext = b;
+          pend = min(b + kLtGrab, (unsigned long long)A.count);
+        }
+      }
+      const unsigned long long avail = pend - pnext;
+      const unsigned long long rank = (unsigned long long)__popcll(need & below);
+      if (!have && !done) {
+        if (rank < avail) {
+          il = (uint32_t)(pnext + rank);
           i = A.first + il;
           v = (int32_t)scale_draw(draw1(seed, kTagRoot, A.stream, 0u, i), (uint32_t)A.n);
           lt_insert(H, v);
@@ -566,8 +653,11 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
           len = 1;
           s_ex = s_lv = 0;
           have = true;
+        } else if (dry) {
+          done = true;
         }
       }
+      pnext += min(avail, (unsigned long long)__popcll(need));
     }
     if (!__any(have)) break;
     bool fin = false, over = false;
@@ -611,11 +701,16 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
     const int32_t tot = __shfl(inc, kWave - 1, kWave);
     unsigned long long pos = 0;
     if (tot > 0) {
-      const uint64_t em = __ballot(emit);
-      const int leader = __ffsll((unsigned long long)em) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(&A.ctr[1], (unsigned long long)tot);
-      pos = shfl_u64(base, leader) + (unsigned long long)(inc - mylen);
+      if (cpos + (unsigned long long)tot > cend) {
+        const unsigned long long want = max((unsigned long long)tot, 4 * kChunk);
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd(&A.ctr[1], want);
+        cpos = shfl_u64(b, 0);
+        cend = cpos + want;
+      }
+      pos = cpos + (unsigned long long)(inc - mylen);
+      cpos += (unsigned long long)tot;
+      w_tot += (unsigned long long)tot;
     }
     if (fin) {
       if (over) {
@@ -639,6 +734,7 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
   if (lane == 0) {
     if (ex) atomicAdd(&A.ctr[3], ex);
     if (lv) atomicAdd(&A.ctr[4], lv);
+    if (w_tot) atomicAdd(&A.ctr[10], w_tot);
   }
 }
 
@@ -730,8 +826,11 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
   Handoff* handoff = (Handoff*)(((uintptr_t)(big_list + cnt) + 63) & ~(uintptr_t)63);
 
   static thread_local int64_t last_total = 0;
-  uint64_t arena_cap = (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total),
-                                                   (int64_t)cnt * 2);
+  // room for the sets plus the unfilled tails of the per-wave arena chunks
+  const uint64_t slack = (uint64_t)di.num_cus * 32 * 4 * kChunk;
+  uint64_t arena_cap =
+      (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total), (int64_t)cnt * 2) +
+      slack;
   unsigned long long hc[16] = {0};
   // device times of the launches, only when statistics are requested
   hipEvent_t ev[6] = {};
@@ -835,10 +934,11 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       if (timed) IM_HIP(hipEventElapsedTime(&ms_large, ev[2], ev[3]));
     }
     if (hc[1] <= arena_cap) break;
-    arena_cap = hc[1];  // deterministic: the retry produces the same sets
+    // the sets are deterministic, the chunk slack is not: leave room for it
+    arena_cap = hc[1] + hc[1] / 8 + (uint64_t)di.num_cus * 64 * 4 * kChunk;
     if (attempt == 2) return IM_ENOMEM;
   }
-  const int64_t tot = (int64_t)hc[1];
+  const int64_t tot = (int64_t)hc[10];
   last_total = tot;
   if (timed) IM_HIP(hipEventRecord(ev[4], s));
   IM_TRY(exclusive_scan_i32_to_i64(lens, (int64_t)cnt, off, s));
@@ -852,6 +952,7 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     stats->large_total = (int64_t)hc[8];
     stats->large_examined = (int64_t)hc[6];
     stats->large_live = (int64_t)hc[7];
+    stats->redo_examined = (int64_t)hc[9];
     stats->ms_main = ms_main;
     stats->ms_large = ms_large;
     stats->ms_canon = ms_canon;

@@ -1,0 +1,85 @@
+"""Writes the full-size expected values used by tests/test_gpu_fullsize.py.
+
+Calls only the CPU oracle (oracle/) on the seeded synthetic workloads
+(workloads/); nothing here reads an output of the HIP path.  Run from the
+repository root:  python tests/golden/make_golden.py [2] [3]
+Config 2 takes about five minutes of single-core CPU time, config 3 a few.
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+def digest(off: np.ndarray, mem: np.ndarray) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(off, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(mem, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
+def config2():
+    w = W.config(2)
+    g = w.graph
+    thr = O.thresholds(g.model, g.in_off, g.weight)
+    t0 = time.time()
+    r = O.sample(g.model, g.in_off, g.in_src, thr, w.seed, 0, 0, w.theta)
+    io, im_ = O.incidence(g.n, r)
+    seeds, gains, cov = O.greedy(g.n, w.theta, io, im_, w.k, lazy=True)
+    pick = [0, 1, 2, 3, 1000, 65535, 65536, 500000, w.theta - 1]
+    return {
+        "workload": w.name, "theta": w.theta, "k": w.k, "seed": w.seed,
+        "total": r.total, "examined": r.examined, "live": r.live,
+        "rrr_sha256": digest(r.off, r.mem),
+        "sets": {str(i): r.set(i).tolist() for i in pick},
+        "seeds": seeds.tolist(), "gains": gains.tolist(), "coverage": cov,
+        "oracle_seconds": round(time.time() - t0, 1),
+    }
+
+
+def config3():
+    w = W.config(3)
+    g = w.graph
+    thr = O.thresholds(g.model, g.in_off, g.weight)
+    out = {"workload": w.name, "k": w.k, "eps": w.eps, "m": w.m, "delta": w.delta,
+           "seed": w.seed, "part_seed": w.part_seed, "runs": {}}
+    for alpha in w.alphas:
+        t0 = time.time()
+        res = O.imm(g.model, g.in_off, g.in_src, thr, w.k, w.eps, seed=w.seed,
+                    selector=O.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha,
+                    part_seed=w.part_seed, lazy=True)
+        res["seeds"] = res["seeds"].tolist()
+        res["oracle_seconds"] = round(time.time() - t0, 1)
+        out["runs"][repr(alpha)] = res
+    # the final-stream sets themselves, for a sampled parity check
+    theta = out["runs"][repr(w.alphas[0])]["theta"]
+    r = O.sample(g.model, g.in_off, g.in_src, thr, w.seed, 1, 0, theta)
+    out["final_theta"] = theta
+    out["final_total"] = r.total
+    out["final_rrr_sha256"] = digest(r.off, r.mem)
+    return out
+
+
+def main():
+    which = sys.argv[1:] or ["2", "3"]
+    for c in which:
+        fn = {"2": config2, "3": config3}[c]
+        t0 = time.time()
+        res = fn()
+        path = os.path.join(HERE, "config%s_expected.json" % c)
+        with open(path, "w") as f:
+            json.dump(res, f, indent=1, sort_keys=True)
+        print("wrote %s in %.0fs" % (path, time.time() - t0), flush=True)
+
+
+if __name__ == "__main__":
+    main()
