@@ -1,0 +1,93 @@
+"""Full-size parity: the HIP path at the benchmark sizes against expected
+values the CPU oracle wrote (tests/golden/make_golden.py, oracle calls only).
+
+Config 2: R-MAT scale 20, 2^24 edges, IC weighted cascade, 2^20 RRR sets,
+greedy k = 100 -- the whole RRR collection (SHA-256 of the canonical CSR),
+its counters, sampled sets, and the seeds, gains and coverage.
+Config 3: R-MAT scale 22, 2^26 edges, LT, IMM with eps = 0.13, k = 100,
+GreediRIS (m = 64, delta = 0.077) with and without truncation (alpha 0.125)
+-- the IMM sample counts, lower bound, seeds, coverage, winning bucket, and
+the final-stream RRR collection.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(c):
+    with open(os.path.join(HERE, "golden", "config%d_expected.json" % c)) as f:
+        return json.load(f)
+
+
+def _digest(off, mem):
+    h = hashlib.sha256()
+    h.update(off.cpu().numpy().astype("<i8").tobytes())
+    h.update(mem.cpu().numpy().astype("<i4").tobytes())
+    return h.hexdigest()
+
+
+@pytest.fixture(scope="module")
+def im():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2408_10982_amd as im
+    im.lib()
+    return im
+
+
+def test_config2_sampling_and_greedy(im):
+    print("[case] config 2 full size", flush=True)
+    exp = _golden(2)
+    w = W.config(2)
+    g = w.graph
+    G = im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
+    r = im.sample_rrr(G, w.seed, 0, 0, w.theta, capacity=exp["total"])
+    assert (r.total, r.examined, r.live) == (exp["total"], exp["examined"], exp["live"])
+    off = r.off.cpu().numpy()
+    mem = r.mem.cpu().numpy()
+    for i, s in exp["sets"].items():
+        i = int(i)
+        assert mem[off[i]:off[i + 1]].tolist() == s
+    assert _digest(r.off, r.mem) == exp["rrr_sha256"]
+    io, imem = im.build_incidence(g.n, r)
+    seeds, gains, nsel, cov = im.greedy_cover(g.n, r, io, imem, w.k)
+    n = int(nsel.item())
+    assert seeds[:n].cpu().tolist() == exp["seeds"]
+    assert gains[:n].cpu().tolist() == exp["gains"]
+    assert int(cov.item()) == exp["coverage"]
+    # properties that hold at any size
+    gl = gains[:n].cpu().numpy()
+    assert np.all(np.diff(gl) <= 0) and gl.sum() == int(cov.item())
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.125])
+def test_config3_imm_greediris(im, alpha):
+    print("[case] config 3 full size alpha=%s" % alpha, flush=True)
+    exp = _golden(3)
+    run = exp["runs"][repr(alpha)]
+    w = W.config(3)
+    g = w.graph
+    G = im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
+    got = im.solve(G, w.k, w.eps, selector=im.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha,
+                   seed=w.seed, part_seed=w.part_seed)
+    assert got["theta"] == run["theta"]
+    assert got["rounds"] == run["rounds_run"]
+    assert got["martingale_samples"] == run["martingale_samples"]
+    assert got["lower_bound"] == run["lb"]
+    assert got["seeds"] == run["seeds"]
+    assert got["coverage"] == run["coverage"]
+    assert got["bucket"] == run["bucket"]
+    assert got["global_won"] == run["global_won"]
+    if alpha == 1.0:
+        r = im.sample_rrr(G, w.seed, 1, 0, exp["final_theta"], capacity=exp["final_total"])
+        assert r.total == exp["final_total"] == got["final_total"]
+        assert _digest(r.off, r.mem) == exp["final_rrr_sha256"]
