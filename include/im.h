@@ -231,6 +231,37 @@ typedef struct {
 int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* opts,
              int32_t* seeds, im_solve_result* res, void* stream);
 
+/* One task of a batch: theta samples [0, theta) of (seed, stream_tag) on a
+ * prepared graph, then the standard greedy with k picks. */
+typedef struct {
+  im_graph graph;
+  uint64_t seed;
+  uint32_t stream_tag;
+  int32_t k;
+  int64_t theta;
+} im_task;
+
+/* Batch statistics (sums over the tasks; device times from HIP events). */
+typedef struct {
+  int64_t sets, total, examined, live;
+  double ms_sample, ms_incidence, ms_cover;
+} im_batch_stats;
+
+/*
+ * Batched sampling and greedy cover over many independent tasks (the same
+ * operations as im_sample_rrr, im_build_incidence and im_greedy_cover of
+ * Sec. 2.1 and 3.2, per task): all IC tasks share one sampling launch, all LT
+ * tasks another, covering subsets of every task are built together, and the
+ * greedy picks of every task run in the same launches.  Task t's results are
+ * bit-identical to those three calls on task t alone.
+ * tasks [host] ntasks; seeds [device] and gains [device] hold sum_t k_t
+ * entries, task t's at offset sum_{u<t} k_u (-1 / 0 past its nsel);
+ * nsel [device] ntasks int32; coverage [device] ntasks int64; stats [host]
+ * may be NULL.  Tasks are processed 256 at a time.  Synchronises `stream`.
+ */
+int im_solve_batch(const im_task* tasks, int32_t ntasks, int32_t* seeds, int64_t* gains,
+                   int32_t* nsel, int64_t* coverage, im_batch_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

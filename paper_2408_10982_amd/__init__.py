@@ -7,8 +7,8 @@ This package is the thin Python face of that library.
 """
 from .binding import (IC, LT, SEL_GREEDIRIS, SEL_GREEDY, EXPORTS, Graph, ImError, RRR,
                       build_incidence, greedy_cover, lib, prepare_graph, randgreedi, release,
-                      sample_rrr, solve, stream_cover, version)
+                      sample_rrr, solve, solve_batch, stream_cover, version)
 
 __all__ = ["IC", "LT", "SEL_GREEDY", "SEL_GREEDIRIS", "EXPORTS", "Graph", "ImError", "RRR",
            "build_incidence", "greedy_cover", "lib", "prepare_graph", "randgreedi", "release",
-           "sample_rrr", "solve", "stream_cover", "version"]
+           "sample_rrr", "solve", "solve_batch", "stream_cover", "version"]

@@ -26,7 +26,7 @@ _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM
 # every symbol the header declares
 EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
            "im_build_incidence", "im_greedy_cover", "im_randgreedi", "im_stream_cover",
-           "im_solve")
+           "im_solve", "im_solve_batch")
 
 
 class ImError(RuntimeError):
@@ -61,6 +61,17 @@ class _SolveResult(C.Structure):
                 ("global_won", C.c_int32), ("final_total", C.c_int64)]
 
 
+class _Task(C.Structure):
+    _fields_ = [("graph", _Graph), ("seed", C.c_uint64), ("stream_tag", C.c_uint32),
+                ("k", C.c_int32), ("theta", C.c_int64)]
+
+
+class _BatchStats(C.Structure):
+    _fields_ = [("sets", C.c_int64), ("total", C.c_int64), ("examined", C.c_int64),
+                ("live", C.c_int64), ("ms_sample", C.c_double), ("ms_incidence", C.c_double),
+                ("ms_cover", C.c_double)]
+
+
 _lib = None
 
 
@@ -86,6 +97,8 @@ def lib():
         L.im_stream_cover.argtypes = [I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P, P]
         L.im_solve.argtypes = [C.POINTER(_Graph), I32, D, C.POINTER(_SolveOpts), P,
                                C.POINTER(_SolveResult), P]
+        L.im_solve_batch.argtypes = [C.POINTER(_Task), I32, P, P, P, P, C.POINTER(_BatchStats),
+                                     P]
         for f in EXPORTS[2:]:
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -251,6 +264,35 @@ def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,
     out = {f: getattr(res, f) for f, _ in _SolveResult._fields_}
     out["seeds"] = list(seeds)[:res.nsel]
     return out
+
+
+def solve_batch(tasks, stream=None):
+    """tasks: list of (Graph, seed, stream_tag, k, theta).  Returns a list of
+    per-task dicts (seeds, gains, coverage) and the batch statistics."""
+    nt = len(tasks)
+    arr = (_Task * nt)()
+    ks = []
+    for j, (g, seed, tag, k, theta) in enumerate(tasks):
+        arr[j] = _Task(g.struct(), seed, tag, k, theta)
+        ks.append(k)
+    dev = tasks[0][0].in_off.device
+    K = sum(ks)
+    seeds = torch.empty(K, dtype=torch.int32, device=dev)
+    gains = torch.empty(K, dtype=torch.int64, device=dev)
+    nsel = torch.empty(nt, dtype=torch.int32, device=dev)
+    cov = torch.empty(nt, dtype=torch.int64, device=dev)
+    st = _BatchStats()
+    rc = lib().im_solve_batch(arr, nt, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov),
+                              C.byref(st), _stream(stream))
+    _check(rc, "im_solve_batch")
+    s_h, g_h, n_h, c_h = (seeds.cpu().tolist(), gains.cpu().tolist(), nsel.cpu().tolist(),
+                          cov.cpu().tolist())
+    out, o = [], 0
+    for j, k in enumerate(ks):
+        n = n_h[j]
+        out.append({"seeds": s_h[o:o + n], "gains": g_h[o:o + n], "coverage": c_h[j]})
+        o += k
+    return out, {f: getattr(st, f) for f, _ in _BatchStats._fields_}
 
 
 def release():

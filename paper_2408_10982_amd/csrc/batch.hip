@@ -1,0 +1,247 @@
+// batch.hip -- many independent (graph, seed, k, theta) tasks in one set of
+// launches (im_solve_batch).
+//
+// The tasks' samples are laid out one after the other in one canonical CSR,
+// their vertices one after the other in one count array, and every task
+// becomes one partition of the greedy launches (own vertex range, own
+// samples, own k).  All IC tasks are sampled by one launch and all LT tasks
+// by another; covering subsets of all tasks are built by one histogram, one
+// scan and one scatter; the greedy runs max k picks for all tasks together.
+// Each task's seeds are therefore exactly those of im_sample_rrr +
+// im_build_incidence + im_greedy_cover on that task alone.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "cover.h"
+#include "sample.h"
+
+namespace im {
+
+constexpr int kBatchBlock = 256;
+constexpr int kBatchRun = 16;  // members per thread
+
+struct BatchInc {
+  const int64_t* __restrict__ off;    // over all samples
+  const int32_t* __restrict__ mem;    // task-local vertex ids
+  int64_t total;
+  int64_t count;
+  const int64_t* __restrict__ sbase;  // ntasks+1 sample positions
+  const int64_t* __restrict__ vbase;  // ntasks+1 vertex positions
+  int32_t ntasks;
+  uint32_t* __restrict__ deg;
+  uint32_t* __restrict__ fill;
+  const int64_t* __restrict__ inc_off;
+  int32_t* __restrict__ inc_mem;      // task-local sample ids
+};
+
+__device__ __forceinline__ int64_t last_leq(const int64_t* a, int64_t n, int64_t x) {
+  int64_t lo = 0, hi = n - 1;  // last index with a[i] <= x
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Each thread walks kBatchRun consecutive members, tracking the sample and
+// the task that own them.  scatter = false: degree histogram; true: scatter.
+template <bool kScatter>
+__global__ __launch_bounds__(kBatchBlock) void k_batch_incidence(BatchInc B) {
+  const int64_t t0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kBatchRun;
+  if (t0 >= B.total) return;
+  int64_t j = last_leq(B.off, B.count, t0);
+  int64_t end_j = B.off[j + 1];
+  int task = (int)last_leq(B.sbase, B.ntasks, j);
+  int64_t task_end = B.sbase[task + 1];
+  const int64_t t1 = min(t0 + kBatchRun, B.total);
+  for (int64_t t = t0; t < t1; ++t) {
+    while (t >= end_j) {
+      ++j;
+      end_j = B.off[j + 1];
+    }
+    while (j >= task_end) {
+      ++task;
+      task_end = B.sbase[task + 1];
+    }
+    const int64_t gv = B.vbase[task] + B.mem[t];
+    if (!kScatter) {
+      atomicAdd(&B.deg[gv], 1u);
+    } else {
+      const uint32_t slot = atomicAdd(&B.fill[gv], 1u);
+      B.inc_mem[B.inc_off[gv] + slot] = (int32_t)(j - B.sbase[task]);
+    }
+  }
+}
+
+static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32_t* seeds,
+                       int64_t* gains, int32_t* nsel, int64_t* coverage, im_batch_stats* st,
+                       hipStream_t s) {
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  std::vector<TaskDesc> td(nt);
+  std::vector<int64_t> sb(nt + 1), vb(nt + 1), ko(nt);
+  std::vector<int32_t> kp(nt);
+  int64_t S = 0, V = 0, K = out_base;
+  int32_t max_n = 1, max_k = 1;
+  for (int t = 0; t < nt; ++t) {
+    const im_task& q = tasks[t];
+    sb[t] = S;
+    vb[t] = V;
+    ko[t] = K;
+    kp[t] = q.k;
+    td[t] = task_of(&q.graph, q.seed, q.stream_tag, 0, q.theta, S);
+    S += q.theta;
+    V += q.graph.n;
+    K += q.k;
+    max_n = std::max(max_n, q.graph.n);
+    max_k = std::max(max_k, q.k);
+  }
+  sb[nt] = S;
+  vb[nt] = V;
+  if (S >= ((int64_t)1 << 32) || V >= ((int64_t)1 << 31)) return IM_EINVAL;
+  // tables | off | inc_off | deg | fill | cnt | covered | gmax | done
+  const size_t tab = (size_t)(nt + 1) * 16 + (size_t)nt * 12 + 256;
+  const size_t bytes = tab + (size_t)(S + 1) * 8 + (size_t)(V + 1) * 8 + (size_t)V * 12 +
+                       (size_t)S + (size_t)max_k * nt * 8 + 64 + 8 * 64;
+  void* p = nullptr;
+  IM_TRY(scratch(s, kSlotBatch, bytes, &p));
+  char* c = (char*)p;
+  auto take = [&](size_t b) {
+    char* r = c;
+    c += (b + 63) / 64 * 64;
+    return r;
+  };
+  int64_t* d_sb = (int64_t*)take((size_t)(nt + 1) * 8);
+  int64_t* d_vb = (int64_t*)take((size_t)(nt + 1) * 8);
+  int64_t* d_ko = (int64_t*)take((size_t)nt * 8);
+  int32_t* d_kp = (int32_t*)take((size_t)nt * 4);
+  int64_t* off = (int64_t*)take((size_t)(S + 1) * 8);
+  int64_t* inc_off = (int64_t*)take((size_t)(V + 1) * 8);
+  uint32_t* deg = (uint32_t*)take((size_t)V * 4);
+  uint32_t* fill = (uint32_t*)take((size_t)V * 4);
+  uint32_t* cnt = (uint32_t*)take((size_t)V * 4);
+  uint8_t* covered = (uint8_t*)take((size_t)S);
+  unsigned long long* gmax = (unsigned long long*)take((size_t)max_k * nt * 8);
+  int32_t* done = (int32_t*)take(64);
+  IM_HIP(hipMemcpyAsync(d_sb, sb.data(), (size_t)(nt + 1) * 8, hipMemcpyHostToDevice, s));
+  IM_HIP(hipMemcpyAsync(d_vb, vb.data(), (size_t)(nt + 1) * 8, hipMemcpyHostToDevice, s));
+  IM_HIP(hipMemcpyAsync(d_ko, ko.data(), (size_t)nt * 8, hipMemcpyHostToDevice, s));
+  IM_HIP(hipMemcpyAsync(d_kp, kp.data(), (size_t)nt * 4, hipMemcpyHostToDevice, s));
+
+  hipEvent_t ev[4];
+  for (auto& e : ev) IM_HIP(hipEventCreate(&e));
+  struct G {
+    hipEvent_t* e;
+    ~G() {
+      for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[j]);
+    }
+  } guard{ev};
+  // sampling (members land in a grow-only scratch buffer)
+  static thread_local int64_t last_total = 0;
+  int64_t cap = std::max<int64_t>(last_total, S * 4);
+  int64_t total = 0;
+  im_sample_stats ss{};
+  IM_HIP(hipEventRecord(ev[0], s));
+  int32_t* mem = nullptr;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    void* mp = nullptr;
+    IM_TRY(scratch(s, kSlotBatchMem, (size_t)std::max<int64_t>(cap, 1) * 4, &mp));
+    mem = (int32_t*)mp;
+    const int rc = sample_tasks(td.data(), nt, S, max_n, off, mem, cap, &total, &ss, true, s);
+    if (rc == IM_ERANGE) {
+      cap = total;
+      continue;
+    }
+    IM_TRY(rc);
+    break;
+  }
+  if (total > cap) return IM_ENOMEM;
+  last_total = total;
+  IM_HIP(hipEventRecord(ev[1], s));
+  // covering subsets of every task, by global vertex position
+  void* ip = nullptr;
+  IM_TRY(scratch(s, kSlotBatchInc, (size_t)std::max<int64_t>(total, 1) * 4, &ip));
+  int32_t* inc_mem = (int32_t*)ip;
+  IM_HIP(hipMemsetAsync(deg, 0, (size_t)V * 4, s));
+  IM_HIP(hipMemsetAsync(fill, 0, (size_t)V * 4, s));
+  BatchInc B{off, mem, total, S, d_sb, d_vb, nt, deg, fill, inc_off, inc_mem};
+  const int64_t blocks = ((total + kBatchRun - 1) / kBatchRun + kBatchBlock - 1) / kBatchBlock;
+  if (total > 0) {
+    k_batch_incidence<false><<<dim3((unsigned)blocks), dim3(kBatchBlock), 0, s>>>(B);
+    IM_HIP(hipGetLastError());
+  }
+  IM_TRY(exclusive_scan_u32_to_i64(deg, V, inc_off, s));
+  if (total > 0) {
+    k_batch_incidence<true><<<dim3((unsigned)blocks), dim3(kBatchBlock), 0, s>>>(B);
+    IM_HIP(hipGetLastError());
+  }
+  IM_HIP(hipEventRecord(ev[2], s));
+  // greedy on every task at once
+  CoverArgs A{};
+  A.n = (int32_t)V;
+  A.m = nt;
+  A.count = S;
+  A.k = max_k;
+  A.off = off;
+  A.mem = mem;
+  A.inc_off = inc_off;
+  A.inc_mem = inc_mem;
+  A.pbase = d_vb;
+  A.kpart = d_kp;
+  A.koff = d_ko;
+  A.sbase = d_sb;
+  A.local_ids = 1;
+  A.cnt = cnt;
+  A.covered = covered;
+  A.gmax = gmax;
+  A.done = done;
+  A.seeds = seeds;
+  A.gains = gains;
+  A.nsel = nsel;
+  A.cover = coverage;
+  IM_HIP(hipMemsetAsync(gains + out_base, 0, (size_t)(K - out_base) * 8, s));
+  IM_TRY(launch_cover(A, s));
+  IM_HIP(hipEventRecord(ev[3], s));
+  IM_HIP(hipStreamSynchronize(s));
+  if (st) {
+    float a = 0.f, b = 0.f, c2 = 0.f;
+    IM_HIP(hipEventElapsedTime(&a, ev[0], ev[1]));
+    IM_HIP(hipEventElapsedTime(&b, ev[1], ev[2]));
+    IM_HIP(hipEventElapsedTime(&c2, ev[2], ev[3]));
+    st->sets += S;
+    st->total += total;
+    st->examined += ss.examined;
+    st->live += ss.live;
+    st->ms_sample += a;
+    st->ms_incidence += b;
+    st->ms_cover += c2;
+  }
+  return IM_OK;
+}
+
+}  // namespace im
+
+extern "C" int im_solve_batch(const im_task* tasks, int32_t ntasks, int32_t* seeds,
+                              int64_t* gains, int32_t* nsel, int64_t* coverage,
+                              im_batch_stats* stats, void* stream) {
+  using namespace im;
+  if (!tasks || ntasks <= 0 || !seeds || !gains || !nsel || !coverage) return IM_EINVAL;
+  for (int32_t t = 0; t < ntasks; ++t) {
+    const im_task& q = tasks[t];
+    if (!graph_ok(&q.graph) || q.k <= 0 || q.theta < 0 || q.theta >= ((int64_t)1 << 32))
+      return IM_EINVAL;
+  }
+  if (stats) *stats = im_batch_stats{};
+  hipStream_t s = (hipStream_t)stream;
+  int64_t out = 0;
+  for (int32_t c0 = 0; c0 < ntasks; c0 += kMaxParts) {
+    const int32_t nt = std::min<int32_t>(kMaxParts, ntasks - c0);
+    IM_TRY(batch_chunk(tasks + c0, nt, out, seeds, gains, nsel + c0, coverage + c0, stats, s));
+    for (int32_t t = 0; t < nt; ++t) out += tasks[c0 + t].k;
+  }
+  return IM_OK;
+}

@@ -144,6 +144,10 @@ enum Slot {
   kSlotSolveIncOff,
   kSlotSolveOut,
   kSlotSolveLocal,
+  kSlotSampleTasks,
+  kSlotBatch,
+  kSlotBatchMem,
+  kSlotBatchInc,
   kSlotCount
 };
 

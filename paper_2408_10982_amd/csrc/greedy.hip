@@ -20,41 +20,25 @@
 #include <vector>
 
 #include "common.h"
+#include "cover.h"
 
 namespace im {
 
 constexpr int kGBlock = 1024;
 constexpr int kArgTile = kGBlock * 8;  // positions per workgroup in the argmax pass
 constexpr int kApplyBlock = 256;
-constexpr int kMaxParts = 256;
-
-struct CoverArgs {
-  int32_t n;
-  int32_t m;                 // partitions (1 for the standard greedy)
-  int64_t count;             // samples
-  int32_t k;
-  const int64_t* __restrict__ off;
-  const int32_t* __restrict__ mem;
-  const int64_t* __restrict__ inc_off;
-  const int32_t* __restrict__ inc_mem;
-  const int32_t* __restrict__ order;     // n: vertex at each position (nullptr: identity)
-  const int32_t* __restrict__ pos_of;    // n: position of each vertex (nullptr: identity)
-  const int64_t* __restrict__ pbase;     // m+1: positions of partition p (nullptr: [0, n))
-  uint32_t* __restrict__ cnt;            // n, by position: uncovered samples of the vertex
-  uint8_t* __restrict__ covered;         // m * count
-  unsigned long long* __restrict__ gmax; // k * m argmax keys, one row per pick
-  int32_t* __restrict__ done;            // set once no partition can gain
-  int32_t* __restrict__ seeds;           // m*k
-  int64_t* __restrict__ gains;           // m*k
-  int32_t* __restrict__ nsel;            // m
-  int64_t* __restrict__ cover;           // m
-};
 
 __device__ __forceinline__ int64_t part_lo(const CoverArgs& A, int p) {
   return A.pbase ? A.pbase[p] : 0;
 }
 __device__ __forceinline__ int64_t part_hi(const CoverArgs& A, int p) {
   return A.pbase ? A.pbase[p + 1] : (int64_t)A.n;
+}
+__device__ __forceinline__ int32_t part_k(const CoverArgs& A, int p) {
+  return A.kpart ? A.kpart[p] : A.k;
+}
+__device__ __forceinline__ int64_t part_out(const CoverArgs& A, int p) {
+  return A.koff ? A.koff[p] : (int64_t)p * A.k;
 }
 
 __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long x,
@@ -77,7 +61,8 @@ __global__ __launch_bounds__(kGBlock) void k_cover_init(CoverArgs A) {
     const int32_t v = A.order ? A.order[pos] : (int32_t)pos;
     A.cnt[pos] = (uint32_t)(A.inc_off[v + 1] - A.inc_off[v]);
   }
-  for (int64_t j = gtid; j < (int64_t)A.m * A.count; j += gthreads) A.covered[j] = 0;
+  const int64_t ncov = A.sbase ? A.count : (int64_t)A.m * A.count;
+  for (int64_t j = gtid; j < ncov; j += gthreads) A.covered[j] = 0;
   for (int64_t j = gtid; j < (int64_t)A.m * A.k; j += gthreads) A.gmax[j] = 0ull;
   if (gtid == 0) *A.done = 0;
 }
@@ -104,6 +89,7 @@ __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
   for (; p < A.m; ++p) {
     const int64_t lo = max(b0, part_lo(A, p)), hi = min(b1, part_hi(A, p));
     if (lo >= b1) break;
+    if (it >= part_k(A, p)) continue;  // this partition has made all its picks (uniform)
     unsigned long long best = 0ull;
     for (int64_t pos = lo + threadIdx.x; pos < hi; pos += kGBlock) {
       const int32_t v = A.order ? A.order[pos] : (int32_t)pos;
@@ -129,7 +115,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   if (tid == 0) {
     int64_t acc = 0;
     for (int p = 0; p < m; ++p) {
-      const unsigned long long b = gm[p];
+      const unsigned long long b = it < part_k(A, p) ? gm[p] : 0ull;
       pbest[p] = b;
       pre[p] = acc;
       if (key_count(b) > 0) {
@@ -149,8 +135,9 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
     for (int p = tid; p < m; p += kApplyBlock) {
       const unsigned long long b = pbest[p];
       if (key_count(b) > 0) {
-        A.seeds[(int64_t)p * A.k + it] = (int32_t)key_vertex(b);
-        A.gains[(int64_t)p * A.k + it] = (int64_t)key_count(b);
+        const int64_t v = key_vertex(b);
+        A.seeds[part_out(A, p) + it] = (int32_t)(A.local_ids ? v - part_lo(A, p) : v);
+        A.gains[part_out(A, p) + it] = (int64_t)key_count(b);
       }
     }
   }
@@ -174,9 +161,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
       p = lo;
       const uint32_t v = key_vertex(pbest[p]);
       smp = A.inc_mem[A.inc_off[v] + (f - pre[p])];
-      uint8_t* cov = A.covered + (int64_t)p * A.count;
-      if (!cov[smp]) {  // each sample occurs once in S(v), so no race
-        cov[smp] = 1;
+      // flag index: a global sample position when each partition owns its
+      // own samples, else one flag array per partition over all samples
+      const int64_t fi = A.sbase ? A.sbase[p] + smp : (int64_t)p * A.count + smp;
+      if (!A.covered[fi]) {  // each sample occurs once in S(v), so no race
+        A.covered[fi] = 1;
         fresh = true;
       }
     }
@@ -187,10 +176,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
       const int32_t s_smp = __shfl(smp, src, kWave);
       const int s_p = __shfl(p, src, kWave);
       const int64_t lo_p = part_lo(A, s_p), hi_p = part_hi(A, s_p);
-      const int64_t a = A.off[s_smp], b = A.off[s_smp + 1];
+      const int64_t gs = A.sbase ? A.sbase[s_p] + s_smp : (int64_t)s_smp;
+      const int64_t a = A.off[gs], b = A.off[gs + 1];
       for (int64_t t = a + lane; t < b; t += kWave) {
         const int32_t u = A.mem[t];
-        const int64_t pos = A.pos_of ? A.pos_of[u] : u;
+        const int64_t pos = A.local_ids ? lo_p + u : (A.pos_of ? A.pos_of[u] : u);
         if (pos >= lo_p && pos < hi_p) atomicSub(&A.cnt[pos], 1u);
       }
     }
@@ -203,15 +193,17 @@ __global__ void k_cover_finish(CoverArgs A) {
   if (p >= A.m) return;
   int32_t c = 0;
   int64_t s = 0;
-  for (int it = 0; it < A.k; ++it) {
-    const int64_t g = A.gains[(int64_t)p * A.k + it];
+  const int32_t kp = part_k(A, p);
+  const int64_t o = part_out(A, p);
+  for (int it = 0; it < kp; ++it) {
+    const int64_t g = A.gains[o + it];
     if (g <= 0) break;
     ++c;
     s += g;
   }
-  for (int it = c; it < A.k; ++it) {
-    A.seeds[(int64_t)p * A.k + it] = -1;
-    A.gains[(int64_t)p * A.k + it] = 0;
+  for (int it = c; it < kp; ++it) {
+    A.seeds[o + it] = -1;
+    A.gains[o + it] = 0;
   }
   A.nsel[p] = c;
   A.cover[p] = s;
@@ -268,7 +260,7 @@ __global__ void k_pos_of(int32_t n, const int32_t* __restrict__ order,
 
 // k picks = 2k small launches; kernel boundaries make each pass's writes
 // visible device-wide (one cache flush per launch rather than per wave).
-static int launch_cover(CoverArgs& A, hipStream_t s) {
+int launch_cover(CoverArgs& A, hipStream_t s) {
   DeviceInfo di;
   IM_TRY(device_info(&di));
   const int64_t init_blocks = std::min<int64_t>(

@@ -30,6 +30,7 @@
 #include <utility>
 
 #include "common.h"
+#include "sample.h"
 
 namespace im {
 
@@ -46,26 +47,77 @@ constexpr int kGatherSortCap = kLtCap;      // LT sets sorted by the gather kern
 constexpr int32_t kEmpty = -1;
 
 struct SampleArgs {
-  int32_t n;
-  const int32_t* __restrict__ in_off;
-  const int32_t* __restrict__ in_src;
-  const uint32_t* __restrict__ thr;
-  uint32_t seed_lo, seed_hi;
-  uint32_t stream;
-  uint32_t first;
-  uint32_t count;
+  const TaskDesc* __restrict__ tasks;
+  int32_t ntasks;
+  // this launch's work: segment j covers work items [seg_base[j], seg_base[j+1])
+  // of task seg_task[j]
+  const int64_t* __restrict__ seg_base;
+  const int32_t* __restrict__ seg_task;
+  int32_t nseg;
+  uint64_t count;                // work items of this launch
   int32_t* __restrict__ arena;
   uint64_t arena_cap;
-  int64_t* __restrict__ start;   // per sample: arena position
-  int32_t* __restrict__ len;     // per sample: size (-1 while on the large path)
-  uint32_t* __restrict__ big_list;
+  int64_t* __restrict__ start;   // per output position: arena position
+  int32_t* __restrict__ len;     // per output position: size (-1 while on the large path)
+  uint32_t* __restrict__ big_list;       // output positions handed to the large path
   struct Handoff* __restrict__ handoff;  // kMaxHandoff snapshots (IC)
-  unsigned long long* __restrict__ ctr;  // [0] work, [1] cursor, [2] big count,
+  unsigned long long* __restrict__ ctr;  // [0] IC work, [1] cursor, [2] big count,
                                          // [3] examined, [4] live, [5] big work,
                                          // [6] big examined, [7] big live, [8] big total,
                                          // [9] examined in abandoned rounds,
-                                         // [10] sum of set sizes
+                                         // [10] sum of set sizes, [11] LT work
 };
+
+// The graph and random stream of one task, as the kernels use them.
+struct GView {
+  const int32_t* in_off;
+  const int32_t* in_src;
+  const uint32_t* thr;
+  uint32_t n, seed_lo, seed_hi, stream;
+};
+
+__device__ __forceinline__ GView view_of(const TaskDesc& T) {
+  GView g;
+  g.in_off = T.in_off;
+  g.in_src = T.in_src;
+  g.thr = T.thr;
+  g.n = (uint32_t)T.n;
+  g.seed_lo = T.seed_lo;
+  g.seed_hi = T.seed_hi;
+  g.stream = T.stream;
+  return g;
+}
+
+// Work item w of this launch -> (task, sample id, output position).
+__device__ __forceinline__ void locate_work(const SampleArgs& A, uint64_t w, int* task,
+                                            uint32_t* sample, int64_t* pos) {
+  int lo = 0, hi = A.nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if ((uint64_t)A.seg_base[mid] <= w)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int t = A.seg_task[lo];
+  const int64_t local = (int64_t)w - A.seg_base[lo];
+  *task = t;
+  *sample = A.tasks[t].first + (uint32_t)local;
+  *pos = A.tasks[t].sample_base + local;
+}
+
+// Output position -> task.
+__device__ __forceinline__ int task_of_pos(const SampleArgs& A, int64_t pos) {
+  int lo = 0, hi = A.ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (A.tasks[mid].sample_base <= pos)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t v, int bits) {
   return ((uint32_t)v * 2654435761u) >> (32 - bits);
@@ -184,12 +236,15 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       next = b;
       end = min(b + kGrab, (unsigned long long)A.count);
     }
-    const uint32_t il = (uint32_t)next++;
-    const uint32_t i = A.first + il;
+    int tk;
+    uint32_t i;
+    int64_t il;
+    locate_work(A, next++, &tk, &i, &il);
+    const GView G = view_of(A.tasks[tk]);
     const int32_t root =
-        (int32_t)scale_draw(draw1(((uint64_t)A.seed_hi << 32) | A.seed_lo, kTagRoot, A.stream,
+        (int32_t)scale_draw(draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream,
                                   0u, i),
-                            (uint32_t)A.n);
+                            G.n);
     for (int j = lane; j < kSmallH; j += kWave) L.hash[j] = kEmpty;
     wave_sync();
     if (lane == 0) {
@@ -212,8 +267,8 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       int32_t a = 0, b = 0, ng = 0;
       if (lane < nf) {
         const int32_t v = L.queue[head + lane];
-        a = A.in_off[v];
-        b = A.in_off[v + 1];
+        a = G.in_off[v];
+        b = G.in_off[v + 1];
         if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
         s_ex += (unsigned long long)(b - a);
       }
@@ -242,14 +297,14 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
             g[u] = (uint32_t)(L.gbase[o] + gi);
             ea[u] = L.ea[o];
             eb[u] = L.eb[o];
-            q[u] = reinterpret_cast<const uint4*>(A.thr)[g[u]];
+            q[u] = reinterpret_cast<const uint4*>(G.thr)[g[u]];
           }
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           if (ea[u] < eb[u]) {
-            const uint4 r = philox4x32_10(make_uint4(g[u], i, kTagEdge, A.stream), A.seed_lo,
-                                          A.seed_hi);
+            const uint4 r = philox4x32_10(make_uint4(g[u], i, kTagEdge, G.stream), G.seed_lo,
+                                          G.seed_hi);
             const int32_t e0 = (int32_t)(g[u] << 2);
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
@@ -257,7 +312,7 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
               const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
               if (e >= ea[u] && e < eb[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
                 ++s_lv;
-                lds_insert(L, A.in_src[e], &over);
+                lds_insert(L, G.in_src[e], &over);
               }
             }
           }
@@ -347,10 +402,10 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
 
 // ------------------------------------------------------------------ large sets
 struct BigArgs {
-  int32_t model;
-  uint32_t nwords;                  // ceil(n / 32)
+  uint32_t nwords;                  // ceil(max n / 32)
+  uint32_t qcap;                    // max n over the tasks
   uint32_t* __restrict__ bitmaps;   // per worker, nwords words, all zero between uses
-  int32_t* __restrict__ queues;     // per worker, n entries
+  int32_t* __restrict__ queues;     // per worker, qcap entries
 };
 
 __device__ __forceinline__ int64_t block_exclusive_scan64(int64_t x, int64_t* lds,
@@ -386,9 +441,8 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
   __shared__ uint32_t s_item;
   __shared__ unsigned long long s_pos;
   uint32_t* bm = Bg.bitmaps + (size_t)blockIdx.x * Bg.nwords;
-  int32_t* queue = Bg.queues + (size_t)blockIdx.x * (size_t)A.n;
+  int32_t* queue = Bg.queues + (size_t)blockIdx.x * (size_t)Bg.qcap;
   const int t = threadIdx.x;
-  const uint64_t seed = ((uint64_t)A.seed_hi << 32) | A.seed_lo;
   const uint32_t nbig = (uint32_t)A.ctr[2];
   unsigned long long t_ex = 0, t_lv = 0, t_tot = 0;
   for (;;) {
@@ -397,12 +451,15 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
     const uint32_t item = s_item;
     __syncthreads();
     if (item >= nbig) break;
-    const uint32_t il = A.big_list[item];
-    const uint32_t i = A.first + il;
-    const int32_t root =
-        (int32_t)scale_draw(draw1(seed, kTagRoot, A.stream, 0u, i), (uint32_t)A.n);
+    const int64_t il = (int64_t)A.big_list[item];
+    const int tk = task_of_pos(A, il);
+    const TaskDesc& T = A.tasks[tk];
+    const GView G = view_of(T);
+    const uint32_t i = T.first + (uint32_t)(il - T.sample_base);
+    const uint64_t seed = ((uint64_t)G.seed_hi << 32) | G.seed_lo;
+    const int32_t root = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
     unsigned long long s_ex = 0, s_lv = 0;
-    if (Bg.model == IM_IC) {
+    if (T.model == IM_IC) {
       int32_t head = 0, tail = 1;
       if (item < kMaxHandoff) {  // resume from the small path's snapshot
         const Handoff& H = A.handoff[item];
@@ -429,8 +486,8 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
         int32_t a = 0, b = 0, ng = 0;
         if (t < nf) {
           const int32_t v = queue[head + t];
-          a = A.in_off[v];
-          b = A.in_off[v + 1];
+          a = G.in_off[v];
+          b = G.in_off[v + 1];
           if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
           s_ex += (unsigned long long)(b - a);
         }
@@ -459,14 +516,14 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
               g[u] = (uint32_t)(gbase[o] + gi);
               e_a[u] = ea[o];
               e_b[u] = eb[o];
-              q[u] = reinterpret_cast<const uint4*>(A.thr)[g[u]];
+              q[u] = reinterpret_cast<const uint4*>(G.thr)[g[u]];
             }
           }
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
             if (e_a[u] < e_b[u]) {
               const uint4 r =
-                  philox4x32_10(make_uint4(g[u], i, kTagEdge, A.stream), A.seed_lo, A.seed_hi);
+                  philox4x32_10(make_uint4(g[u], i, kTagEdge, G.stream), G.seed_lo, G.seed_hi);
               const int32_t e0 = (int32_t)(g[u] << 2);
 #pragma unroll
               for (int w = 0; w < 4; ++w) {
@@ -474,7 +531,7 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
                 const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
                 if (e >= e_a[u] && e < e_b[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
                   ++s_lv;
-                  const int32_t v2 = A.in_src[e];
+                  const int32_t v2 = G.in_src[e];
                   const uint32_t bit = 1u << (v2 & 31);
                   const uint32_t old = atomicOr(&bm[v2 >> 5], bit);
                   if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = v2;
@@ -492,14 +549,14 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
       bm[v >> 5] |= 1u << (v & 31);
       queue[len++] = v;
       for (;;) {
-        const int32_t a = A.in_off[v], b = A.in_off[v + 1];
+        const int32_t a = G.in_off[v], b = G.in_off[v + 1];
         if (a == b) break;
         s_ex += ceil_log2_plus1(b - a);
-        const uint32_t r = draw1(seed, kTagVert, A.stream, i, (uint32_t)v);
+        const uint32_t r = draw1(seed, kTagVert, G.stream, i, (uint32_t)v);
         int32_t lo = a, hi = b;
         while (lo < hi) {
           const int32_t mid = lo + ((hi - lo) >> 1);
-          const uint32_t c = A.thr[mid];
+          const uint32_t c = G.thr[mid];
           if (c > r || c == 0xFFFFFFFFu)
             hi = mid;
           else
@@ -507,7 +564,7 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
         }
         if (lo == b) break;
         ++s_lv;
-        const int32_t u = A.in_src[lo];
+        const int32_t u = G.in_src[lo];
         const uint32_t bit = 1u << (u & 31);
         if (bm[u >> 5] & bit) break;
         bm[u >> 5] |= bit;
@@ -619,9 +676,11 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
   int32_t* Ls = lane_list + gl * kLtCap;
   const int lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
-  const uint64_t seed = ((uint64_t)A.seed_hi << 32) | A.seed_lo;
   bool have = false, done = false;
-  uint32_t il = 0, i = 0;
+  uint32_t i = 0;
+  int64_t il = 0;
+  GView G{};
+  uint64_t seed = 0;
   int32_t v = 0, len = 0;
   unsigned long long ex = 0, lv = 0, s_ex = 0, s_lv = 0, w_tot = 0;
   unsigned long long pnext = 0, pend = 0;  // this wave's pool of sample ids
@@ -632,7 +691,7 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
     if (need) {
       if (pnext == pend && !dry) {
         unsigned long long b = 0;
-        if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kLtGrab);
+        if (lane == 0) b = atomicAdd(&A.ctr[11], (unsigned long long)kLtGrab);
         b = shfl_u64(b, 0);
         if (b >= A.count) {
           dry = true;
@@ -645,9 +704,11 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
       const unsigned long long rank = (unsigned long long)__popcll(need & below);
       if (!have && !done) {
         if (rank < avail) {
-          il = (uint32_t)(pnext + rank);
-          i = A.first + il;
-          v = (int32_t)scale_draw(draw1(seed, kTagRoot, A.stream, 0u, i), (uint32_t)A.n);
+          int tk;
+          locate_work(A, pnext + rank, &tk, &i, &il);
+          G = view_of(A.tasks[tk]);
+          seed = ((uint64_t)G.seed_hi << 32) | G.seed_lo;
+          v = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
           lt_insert(H, v);
           Ls[0] = v;
           len = 1;
@@ -662,16 +723,16 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
     if (!__any(have)) break;
     bool fin = false, over = false;
     if (have) {
-      const int32_t a = A.in_off[v], b = A.in_off[v + 1];
+      const int32_t a = G.in_off[v], b = G.in_off[v + 1];
       if (a == b) {
         fin = true;
       } else {
         s_ex += ceil_log2_plus1(b - a);
-        const uint32_t r = draw1(seed, kTagVert, A.stream, i, (uint32_t)v);
+        const uint32_t r = draw1(seed, kTagVert, G.stream, i, (uint32_t)v);
         int32_t lo = a, hi = b;
         while (lo < hi) {
           const int32_t mid = lo + ((hi - lo) >> 1);
-          const uint32_t c = A.thr[mid];
+          const uint32_t c = G.thr[mid];
           if (c > r || c == 0xFFFFFFFFu)
             hi = mid;
           else
@@ -681,7 +742,7 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
           fin = true;
         } else {
           ++s_lv;
-          const int32_t u = A.in_src[lo];
+          const int32_t u = G.in_src[lo];
           if (lt_contains(H, u)) {
             fin = true;
           } else if (len == kLtCap) {
@@ -787,34 +848,63 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
   }
 }
 
-}  // namespace im
-
-// ------------------------------------------------------------------ entry
-extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag,
-                             int64_t first, int64_t count, int64_t* off, int32_t* mem,
-                             int64_t capacity, int64_t* total, im_sample_stats* stats,
-                             void* stream) {
-  using namespace im;
-  if (!g || !off || !total || first < 0 || count < 0 || capacity < 0 ||
-      first + count > (int64_t)1 << 32 || (capacity > 0 && !mem))
-    return IM_EINVAL;
-  if (g->n <= 0 || g->num_edges < 0 || g->num_edges >= (int64_t)0x7FFFFFFF || !g->in_off ||
-      (g->num_edges > 0 && (!g->in_src || !g->thr)) ||
-      (g->model != IM_IC && g->model != IM_LT) || ((uintptr_t)g->thr & 15u))
-    return IM_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+// ------------------------------------------------------------------ host
+// Samples every task of a table into one canonical CSR over output positions
+// (task t's sets at [sample_base, sample_base + count)).  IC tasks share one
+// main launch, LT tasks another; both hand oversized sets to one large-path
+// launch.  sort_all: sort every set on the gather (needed when IC and LT
+// tasks share the output); otherwise only LT sets are sorted there.
+int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
+                 int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
+                 im_sample_stats* stats, bool sort_all, hipStream_t s) {
   DeviceInfo di;
   IM_TRY(device_info(&di));
-  if (count == 0) {
+  if (count_total == 0) {
     IM_HIP(hipMemsetAsync(off, 0, sizeof(int64_t), s));
     IM_HIP(hipStreamSynchronize(s));
     *total = 0;
     if (stats) *stats = im_sample_stats{};
     return IM_OK;
   }
-  const uint32_t cnt = (uint32_t)count;
-  // per-sample metadata: start (i64), len (i32), big list (u32), counters
-  const uint32_t nhand = std::min<uint32_t>(cnt, kMaxHandoff);
+  if (count_total >= ((int64_t)1 << 32)) return IM_EINVAL;
+  const uint64_t cnt = (uint64_t)count_total;
+  // work segments per model, in task order
+  std::vector<int64_t> seg_ic{0}, seg_lt{0};
+  std::vector<int32_t> task_ic, task_lt;
+  bool any_lt = false;
+  for (int t = 0; t < ntasks; ++t) {
+    if (h_tasks[t].count == 0) continue;
+    if (h_tasks[t].model == IM_IC) {
+      task_ic.push_back(t);
+      seg_ic.push_back(seg_ic.back() + h_tasks[t].count);
+    } else {
+      any_lt = true;
+      task_lt.push_back(t);
+      seg_lt.push_back(seg_lt.back() + h_tasks[t].count);
+    }
+  }
+  // device copies of the task table and the segment lists
+  const size_t tab_bytes = (size_t)ntasks * sizeof(TaskDesc);
+  const size_t seg_bytes = (seg_ic.size() + seg_lt.size()) * 8 + (task_ic.size() + task_lt.size()) * 4;
+  void* tp = nullptr;
+  IM_TRY(scratch(s, kSlotSampleTasks, tab_bytes + seg_bytes + 256, &tp));
+  char* tc = (char*)tp;
+  TaskDesc* d_tasks = (TaskDesc*)tc;
+  int64_t* d_seg_ic = (int64_t*)(tc + ((tab_bytes + 63) / 64) * 64);
+  int64_t* d_seg_lt = d_seg_ic + seg_ic.size();
+  int32_t* d_task_ic = (int32_t*)(d_seg_lt + seg_lt.size());
+  int32_t* d_task_lt = d_task_ic + task_ic.size();
+  IM_HIP(hipMemcpyAsync(d_tasks, h_tasks, tab_bytes, hipMemcpyHostToDevice, s));
+  IM_HIP(hipMemcpyAsync(d_seg_ic, seg_ic.data(), seg_ic.size() * 8, hipMemcpyHostToDevice, s));
+  IM_HIP(hipMemcpyAsync(d_seg_lt, seg_lt.data(), seg_lt.size() * 8, hipMemcpyHostToDevice, s));
+  if (!task_ic.empty())
+    IM_HIP(hipMemcpyAsync(d_task_ic, task_ic.data(), task_ic.size() * 4, hipMemcpyHostToDevice, s));
+  if (!task_lt.empty())
+    IM_HIP(hipMemcpyAsync(d_task_lt, task_lt.data(), task_lt.size() * 4, hipMemcpyHostToDevice, s));
+
+  // per-position metadata: start (i64), len (i32), big list (u32), counters,
+  // hand-off snapshots
+  const uint32_t nhand = (uint32_t)std::min<uint64_t>(cnt, kMaxHandoff);
   const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 128 + 256 +
                             (size_t)nhand * sizeof(Handoff) + 64;
   void* mp = nullptr;
@@ -829,7 +919,7 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
   // room for the sets plus the unfilled tails of the per-wave arena chunks
   const uint64_t slack = (uint64_t)di.num_cus * 32 * 4 * kChunk;
   uint64_t arena_cap =
-      (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total), (int64_t)cnt * 2) +
+      (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total), count_total * 2) +
       slack;
   unsigned long long hc[16] = {0};
   // device times of the launches, only when statistics are requested
@@ -846,20 +936,12 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     }
   } ev_guard{ev, timed};
   float ms_main = 0.f, ms_large = 0.f, ms_canon = 0.f;
-  const bool lt = g->model == IM_LT;
   for (int attempt = 0; attempt < 3; ++attempt) {
     void* ap = nullptr;
     IM_TRY(scratch(s, kSlotSampleArena, arena_cap * sizeof(int32_t), &ap));
-    SampleArgs A;
-    A.n = g->n;
-    A.in_off = g->in_off;
-    A.in_src = g->in_src;
-    A.thr = g->thr;
-    A.seed_lo = (uint32_t)seed;
-    A.seed_hi = (uint32_t)(seed >> 32);
-    A.stream = stream_tag;
-    A.first = (uint32_t)first;
-    A.count = cnt;
+    SampleArgs A{};
+    A.tasks = d_tasks;
+    A.ntasks = ntasks;
     A.arena = (int32_t*)ap;
     A.arena_cap = arena_cap;
     A.start = start;
@@ -869,10 +951,22 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     A.ctr = ctr;
     IM_HIP(hipMemsetAsync(ctr, 0, 128, s));
     if (timed) IM_HIP(hipEventRecord(ev[0], s));
-    if (!lt) {
+    if (!task_ic.empty()) {
+      SampleArgs Ai = A;
+      Ai.seg_base = d_seg_ic;
+      Ai.seg_task = d_task_ic;
+      Ai.nseg = (int32_t)task_ic.size();
+      Ai.count = (uint64_t)seg_ic.back();
       const int blocks = di.num_cus * 8;
-      k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(A);
-    } else {
+      k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(Ai);
+      IM_HIP(hipGetLastError());
+    }
+    if (!task_lt.empty()) {
+      SampleArgs Al = A;
+      Al.seg_base = d_seg_lt;
+      Al.seg_task = d_task_lt;
+      Al.nseg = (int32_t)task_lt.size();
+      Al.count = (uint64_t)seg_lt.back();
       const int blocks = di.num_cus * 2;
       const size_t lanes = (size_t)blocks * kLtBlock;
       bool fresh = false;
@@ -882,9 +976,9 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       if (fresh) IM_HIP(hipMemsetAsync(hp, 0xFF, lanes * kLtH * sizeof(int32_t), s));
       int32_t* lane_hash = (int32_t*)hp;
       int32_t* lane_list = lane_hash + lanes * kLtH;
-      k_sample_lt<<<dim3(blocks), dim3(kLtBlock), 0, s>>>(A, lane_hash, lane_list);
+      k_sample_lt<<<dim3(blocks), dim3(kLtBlock), 0, s>>>(Al, lane_hash, lane_list);
+      IM_HIP(hipGetLastError());
     }
-    IM_HIP(hipGetLastError());
     if (timed) IM_HIP(hipEventRecord(ev[1], s));
     IM_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
     IM_HIP(hipStreamSynchronize(s));
@@ -892,9 +986,9 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
     ms_large = 0.f;
     if (hc[2] > 0) {
       const uint32_t nbig = (uint32_t)hc[2];
-      const uint32_t nwords = (uint32_t)(((int64_t)g->n + 31) / 32);
+      const uint32_t nwords = (uint32_t)(((int64_t)max_n + 31) / 32);
       // workers each hold an n-bit bitmap and an n-entry queue
-      const size_t per_worker = (size_t)nwords * 4 + (size_t)g->n * 4;
+      const size_t per_worker = (size_t)nwords * 4 + (size_t)max_n * 4;
       // up to 8 workers per CU, within a 16 GiB budget; the bitmaps are zero
       // between uses (each set clears its own bits), so only a new buffer
       // needs clearing
@@ -907,8 +1001,8 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       bool bfresh = false;
       IM_TRY(scratch_fresh(s, kSlotSampleBig, (size_t)cap_workers * per_worker, &bp, &bfresh));
       BigArgs Bg;
-      Bg.model = g->model;
       Bg.nwords = nwords;
+      Bg.qcap = (uint32_t)max_n;
       Bg.bitmaps = (uint32_t*)bp;
       Bg.queues = (int32_t*)((char*)bp + (size_t)cap_workers * nwords * 4);
       // the zero invariant only holds for the layout that last used the buffer
@@ -934,9 +1028,9 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
       if (timed) IM_HIP(hipEventElapsedTime(&ms_large, ev[2], ev[3]));
     }
     if (hc[1] <= arena_cap) break;
-    // the sets are deterministic, the chunk slack is not: leave room for it
-    arena_cap = hc[1] + hc[1] / 8 + (uint64_t)di.num_cus * 64 * 4 * kChunk;
     if (attempt == 2) return IM_ENOMEM;
+    // the sets are deterministic, the chunk slack is not: leave room for it
+    arena_cap = hc[1] + hc[1] / 8 + slack;
   }
   const int64_t tot = (int64_t)hc[10];
   last_total = tot;
@@ -964,13 +1058,54 @@ extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_t
   }
   void* ap = nullptr;
   IM_TRY(scratch(s, kSlotSampleArena, arena_cap * sizeof(int32_t), &ap));
-  const int gblocks = std::min<int64_t>(((int64_t)cnt + 3) / 4, (int64_t)di.num_cus * 16);
+  const int gblocks = (int)std::min<int64_t>(((int64_t)cnt + 3) / 4, (int64_t)di.num_cus * 16);
   k_gather<<<dim3(std::max(gblocks, 1)), dim3(kGatherBlock), 0, s>>>(
-      cnt, start, lens, off, (const int32_t*)ap, mem, lt ? 1 : 0);
+      (uint32_t)cnt, start, lens, off, (const int32_t*)ap, mem, (sort_all || any_lt) ? 1 : 0);
   IM_HIP(hipGetLastError());
   if (timed) IM_HIP(hipEventRecord(ev[5], s));
   IM_HIP(hipStreamSynchronize(s));
   if (timed) IM_HIP(hipEventElapsedTime(&ms_canon, ev[4], ev[5]));
   fill_stats();
   return IM_OK;
+}
+
+int graph_ok(const im_graph* g) {
+  if (!g || g->n <= 0 || g->num_edges < 0 || g->num_edges >= (int64_t)0x7FFFFFFF ||
+      !g->in_off || (g->num_edges > 0 && (!g->in_src || !g->thr)) ||
+      (g->model != IM_IC && g->model != IM_LT) || ((uintptr_t)g->thr & 15u))
+    return 0;
+  return 1;
+}
+
+TaskDesc task_of(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t first,
+                 int64_t count, int64_t sample_base) {
+  TaskDesc T;
+  T.in_off = g->in_off;
+  T.in_src = g->in_src;
+  T.thr = g->thr;
+  T.n = g->n;
+  T.model = g->model;
+  T.seed_lo = (uint32_t)seed;
+  T.seed_hi = (uint32_t)(seed >> 32);
+  T.stream = stream_tag;
+  T.first = (uint32_t)first;
+  T.sample_base = sample_base;
+  T.count = count;
+  return T;
+}
+
+}  // namespace im
+
+// ------------------------------------------------------------------ entry
+extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag,
+                             int64_t first, int64_t count, int64_t* off, int32_t* mem,
+                             int64_t capacity, int64_t* total, im_sample_stats* stats,
+                             void* stream) {
+  using namespace im;
+  if (!off || !total || first < 0 || count < 0 || capacity < 0 ||
+      first + count > (int64_t)1 << 32 || (capacity > 0 && !mem) || !graph_ok(g))
+    return IM_EINVAL;
+  const TaskDesc T = task_of(g, seed, stream_tag, first, count, 0);
+  return sample_tasks(&T, 1, count, g->n, off, mem, capacity, total, stats, false,
+                      (hipStream_t)stream);
 }

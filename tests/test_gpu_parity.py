@@ -215,3 +215,37 @@ def test_solve_imm(im, name, k, eps, selector):
     assert got["lower_bound"] == exp["lb"]
     assert got["seeds"] == exp["seeds"].tolist()
     assert got["coverage"] == exp["coverage"]
+
+
+def test_batch_matches_single_calls_and_oracle(im):
+    """im_solve_batch: every task equals its own sample + incidence + greedy
+    calls on the GPU and the oracle's standard greedy (mixed IC/LT, uneven
+    n, k and theta, including sets large enough for the large-set path)."""
+    _say("batch")
+    specs = [("ic_sparse", 5, 0, 7, 3000), ("lt_small", 6, 1, 12, 4000), ("rmat12", 7, 0, 16, 5000),
+             ("ic_dense", 8, 2, 3, 1500), ("lt_chain", 9, 0, 5, 700), ("ic_p1", 10, 0, 4, 400)]
+    for j in range(4):
+        t = W.batch_tasks(count=64, seed=77)[j * 13]
+        g = W.make_graph("chunglu", t["model"], n=min(t["n"], 3000), avg_deg=t["avg_deg"],
+                         graph_seed=t["graph_seed"], weight_seed=t["weight_seed"])
+        GRAPHS["cl%d" % j] = (lambda gg=g: gg)
+        specs.append(("cl%d" % j, 100 + j, 0, t["k"], 2000))
+    graphs = {name: GRAPHS[name]() for name, *_ in specs}
+    prepared = {name: _prep(im, g) for name, g in graphs.items()}
+    tasks = [(prepared[name], seed, tag, k, theta) for name, seed, tag, k, theta in specs]
+    out, stats = im.solve_batch(tasks)
+    assert stats["sets"] == sum(t[4] for t in tasks)
+    for (name, seed, tag, k, theta), res in zip(specs, out):
+        g = graphs[name]
+        G = prepared[name]
+        r = im.sample_rrr(G, seed, tag, 0, theta)
+        io, imem = im.build_incidence(g.n, r)
+        s1, g1, n1, c1 = im.greedy_cover(g.n, r, io, imem, k)
+        n1 = int(_np(n1)[0])
+        assert res["seeds"] == _np(s1)[:n1].tolist(), name
+        assert res["gains"] == _np(g1)[:n1].tolist(), name
+        assert res["coverage"] == int(_np(c1)[0]), name
+        o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), seed, tag, 0, theta)
+        oio, oim = O.incidence(g.n, o)
+        os_, og, oc = O.greedy(g.n, theta, oio, oim, k)
+        assert res["seeds"] == os_.tolist() and res["coverage"] == oc, name
