@@ -60,8 +60,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--tasks", type=int, default=256)
+    ap.add_argument("--queries", type=int, default=24)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--alpha", type=float, default=0.125)
     ap.add_argument("--cpu-sample", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,6 +96,8 @@ def main():
         return
     if args.config == 4:
         return bench_batch(args, im, W, torch)
+    if args.config == 5:
+        return bench_serve(args, im, W, torch)
     t0 = time.time()
     w = W.config(args.config)
     g = w.graph
@@ -258,6 +262,102 @@ def bench_batch(args, im, W, torch):
         "per_query_loop_queries_per_s": round(nt / dt_l, 2),
         "speedup_vs_per_query": round(dt_l / dt_b, 3),
         "batch_stats": st,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, im, W, torch):
+    """Served configuration: IM queries (graph, model, k, eps) over resident
+    R-MAT graphs (scales 18, 20, 22; IC weighted cascade and LT), Poisson
+    arrivals at rates swept around the plain path's saturation rate.
+
+    Plain path: each query alone with fresh sampling (im_solve), one at a
+    time; its latencies at a given arrival sequence follow from its measured
+    service times through a single FIFO queue.  Served path: the Server
+    (resident pools extended on demand, continuous batching over
+    --slots streams, HBM-footprint admission), started cold for each rate.
+    Every served result is checked equal to the plain result."""
+    import numpy as np
+
+    from paper_2408_10982_amd import serve as S
+    graphs = {}
+    t0 = time.time()
+    for scale in (18, 20, 22):
+        n, src, dst = W.rmat_edges(scale, 16 << scale, 6000 + scale)
+        in_off, in_src, _ = W._to_in_csr(n, src, dst)
+        del src, dst
+        graphs["s%d-ic" % scale] = im.prepare_graph(in_off, in_src, W.ic_weighted_cascade(in_off),
+                                                    im.IC)
+        graphs["s%d-lt" % scale] = im.prepare_graph(
+            in_off, in_src, W.lt_normalized_weights(in_off, 7000 + scale), im.LT)
+    torch.cuda.synchronize()
+    log("resident graphs ready in %.1fs" % (time.time() - t0))
+    rng = np.random.default_rng(5000)
+    names = sorted(graphs)
+    spec = [(names[int(rng.integers(0, len(names)))], int(rng.integers(10, 201)),
+             float(rng.choice([0.5, 0.25, 0.13]))) for _ in range(args.queries)]
+    seed = 5005
+    # plain path, one query at a time, fresh sampling
+    im.solve(graphs[spec[0][0]], spec[0][1], spec[0][2], seed=seed)  # warm-up
+    torch.cuda.synchronize()
+    plain, service = [], []
+    for name, k, eps in spec:
+        t1 = time.perf_counter()
+        plain.append(im.solve(graphs[name], k, eps, seed=seed))
+        service.append(time.perf_counter() - t1)
+    mu = len(service) / sum(service)
+    log("plain path: %.2f queries/s saturation (mean service %.3fs)" % (mu, 1 / mu))
+    points = []
+    for frac in (0.5, 1.0, 1.2, None):
+        if frac is None:  # burst: every query arrives at once (saturation)
+            lam = float("inf")
+            arr = np.zeros(len(spec))
+        else:
+            lam = frac * mu
+            gaps = np.random.default_rng(5100 + int(frac * 100)).exponential(1.0 / lam, len(spec))
+            arr = np.cumsum(gaps) - gaps[0]
+        # plain: FIFO single server with the measured service times
+        fin, lat = 0.0, []
+        for a, sv in zip(arr, service):
+            fin = max(fin, a) + sv
+            lat.append(fin - a)
+        lat_s = sorted(lat)
+        plain_pt = {"queries_per_s": len(lat) / (fin - arr[0]),
+                    "p50_s": lat_s[int(np.ceil(0.5 * len(lat))) - 1],
+                    "p99_s": lat_s[int(np.ceil(0.99 * len(lat))) - 1]}
+        server = S.Server(graphs, seed=seed, slots=args.slots, hbm_budget=160 << 30)
+        qs = [S.Query(qid=j, graph=name, k=k, eps=eps, arrival=float(arr[j]))
+              for j, (name, k, eps) in enumerate(spec)]
+        done = S.run_arrivals(server, qs)
+        server.close()
+        for q, p in zip(done, plain):
+            assert q.result["seeds"] == p["seeds"] and q.result["coverage"] == p["coverage"]
+        served_pt = S.latency_summary(done)
+        served_pt["max_in_flight"] = server.max_in_flight
+        served_pt["pools"] = server.pool_stats()
+        points.append({"lambda_frac_of_plain_saturation": frac if frac else "burst",
+                       "lambda_qps": round(lam, 3) if frac else "burst",
+                       "served": served_pt, "plain": plain_pt})
+        log("lambda %s: served %.2f q/s p50 %.3fs p99 %.3fs | plain %.2f q/s p50 %.3fs p99 %.3fs"
+            % (frac or "burst", served_pt["queries_per_s"], served_pt["p50_s"],
+               served_pt["p99_s"], plain_pt["queries_per_s"], plain_pt["p50_s"],
+               plain_pt["p99_s"]))
+    top = points[-2]       # the highest Poisson rate
+    burst = points[-1]
+    out = {
+        "metric": "served queries/s (IMM + greedy per query, bit-exact vs alone), p50/p99",
+        "value": round(top["served"]["queries_per_s"], 3), "unit": "queries/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(1e3 * top["served"]["makespan_s"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "serve_rmat18_20_22", "graphs": "R-MAT scales 18/20/22, "
+                   "edge factor 16, IC weighted cascade and LT", "queries": len(spec),
+                   "k": "10..200", "eps": [0.5, 0.25, 0.13], "slots": args.slots,
+                   "selector": "greedy (IMM)"},
+        "p50_s": round(top["served"]["p50_s"], 4), "p99_s": round(top["served"]["p99_s"], 4),
+        "plain_saturation_qps": round(mu, 3),
+        "served_saturation_qps": round(burst["served"]["queries_per_s"], 3),
+        "sweep": points,
     }
     print(json.dumps(out), flush=True)
 

@@ -191,6 +191,18 @@ int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off, const int3
                     const int64_t* lcover, double delta, double alpha, int32_t* seeds,
                     int32_t* nsel, int64_t* coverage, int32_t* info, void* stream);
 
+/* IMM sample-size schedule (host values; see im_solve). */
+typedef struct {
+  double ell, eps_prime, log_binom, lambda_prime, lambda_star;
+  int64_t theta1;   /* samples of the first martingale round */
+  int32_t rounds;   /* floor(log2 n) - 1 */
+} im_imm_plan_t;
+
+/* The fp64 IMM bounds im_solve uses (Alg. 1 with Tang et al. 2015), so that a
+ * caller driving the rounds itself (e.g. over resident sample pools) takes
+ * exactly the same decisions.  Host only; 2 <= n, 1 <= k <= n, 0 < eps < 1. */
+int im_imm_plan(int32_t n, int32_t k, double eps, im_imm_plan_t* out);
+
 /* Options of im_solve. */
 typedef struct {
   int32_t selector;      /* IM_SEL_GREEDY or IM_SEL_GREEDIRIS */

@@ -26,7 +26,7 @@ _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM
 # every symbol the header declares
 EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
            "im_build_incidence", "im_greedy_cover", "im_randgreedi", "im_stream_cover",
-           "im_solve", "im_solve_batch")
+           "im_solve", "im_solve_batch", "im_imm_plan")
 
 
 class ImError(RuntimeError):
@@ -59,6 +59,12 @@ class _SolveResult(C.Structure):
                 ("rounds", C.c_int32), ("lower_bound", C.c_double),
                 ("martingale_samples", C.c_int64), ("bucket", C.c_int32),
                 ("global_won", C.c_int32), ("final_total", C.c_int64)]
+
+
+class _ImmPlan(C.Structure):
+    _fields_ = [("ell", C.c_double), ("eps_prime", C.c_double), ("log_binom", C.c_double),
+                ("lambda_prime", C.c_double), ("lambda_star", C.c_double),
+                ("theta1", C.c_int64), ("rounds", C.c_int32)]
 
 
 class _Task(C.Structure):
@@ -99,6 +105,7 @@ def lib():
                                C.POINTER(_SolveResult), P]
         L.im_solve_batch.argtypes = [C.POINTER(_Task), I32, P, P, P, P, C.POINTER(_BatchStats),
                                      P]
+        L.im_imm_plan.argtypes = [I32, I32, D, C.POINTER(_ImmPlan)]
         for f in EXPORTS[2:]:
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -293,6 +300,27 @@ def solve_batch(tasks, stream=None):
         out.append({"seeds": s_h[o:o + n], "gains": g_h[o:o + n], "coverage": c_h[j]})
         o += k
     return out, {f: getattr(st, f) for f, _ in _BatchStats._fields_}
+
+
+def imm_plan(n: int, k: int, eps: float) -> dict:
+    p = _ImmPlan()
+    _check(lib().im_imm_plan(n, k, eps, C.byref(p)), "im_imm_plan")
+    return {f: getattr(p, f) for f, _ in _ImmPlan._fields_}
+
+
+def sample_into(g: Graph, seed: int, stream_tag: int, first: int, count: int,
+                off: torch.Tensor, mem: torch.Tensor, stream=None):
+    """Samples sets [first, first+count) into caller tensors: off (count+1
+    int64, starts at 0) and mem (int32, its whole length is the capacity).
+    Returns the member total, or -total if mem was too small (IM_ERANGE)."""
+    gs = g.struct()
+    total = C.c_int64()
+    st = lib().im_sample_rrr(C.byref(gs), seed, stream_tag, first, count, _ptr(off), _ptr(mem),
+                             mem.numel(), C.byref(total), None, _stream(stream))
+    if st == IM_ERANGE:
+        return -int(total.value)
+    _check(st, "im_sample_rrr")
+    return int(total.value)
 
 
 def release():

@@ -148,21 +148,10 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
 
 }  // namespace im
 
-extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* o,
-                        int32_t* seeds, im_solve_result* res, void* stream) {
-  using namespace im;
-  if (!g || !o || !seeds || !res || k <= 0 || g->n <= 0 || k > g->n || !(eps > 0.0 && eps < 1.0) ||
-      (o->selector != IM_SEL_GREEDY && o->selector != IM_SEL_GREEDIRIS) || o->theta < 0)
-    return IM_EINVAL;
-  if (o->selector == IM_SEL_GREEDIRIS &&
-      (o->m < 1 || o->m > 256 || !(o->delta > 0.0 && o->delta < 0.5) ||
-       !(o->alpha > 0.0 && o->alpha <= 1.0)))
-    return IM_EINVAL;
-  if (g->model != IM_IC && g->model != IM_LT) return IM_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  const int32_t n = g->n;
-  const double nd = (double)n;
+extern "C" int im_imm_plan(int32_t n, int32_t k, double eps, im_imm_plan_t* out) {
+  if (n <= 1 || k <= 0 || k > n || !(eps > 0.0 && eps < 1.0) || !out) return IM_EINVAL;
   // IMM bounds (fp64, fixed order)
+  const double nd = (double)n;
   const double ln_n = log(nd);
   const double ell = 1.0 * (1.0 + log(2.0) / ln_n);
   const double eps_p = sqrt(2.0) * eps;
@@ -175,10 +164,37 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   const double a_i = sqrt(ell * ln_n + log(2.0));
   const double b_i = sqrt(e1 * (lbin + ell * ln_n + log(2.0)));
   const double sm = e1 * a_i + b_i;
-  const double lambda_s = 2.0 * nd * sm * sm / (eps * eps);
+  out->ell = ell;
+  out->eps_prime = eps_p;
+  out->log_binom = lbin;
+  out->lambda_prime = lambda_p;
+  out->lambda_star = 2.0 * nd * sm * sm / (eps * eps);
+  out->theta1 = (int64_t)ceil(lambda_p / (nd / 2.0));
   int32_t lg = 0;
   while (((int64_t)1 << (lg + 1)) <= (int64_t)n) ++lg;
-  const int32_t rounds = lg - 1;
+  out->rounds = lg - 1;
+  return IM_OK;
+}
+
+extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* o,
+                        int32_t* seeds, im_solve_result* res, void* stream) {
+  using namespace im;
+  if (!g || !o || !seeds || !res || k <= 0 || g->n <= 1 || k > g->n || !(eps > 0.0 && eps < 1.0) ||
+      (o->selector != IM_SEL_GREEDY && o->selector != IM_SEL_GREEDIRIS) || o->theta < 0)
+    return IM_EINVAL;
+  if (o->selector == IM_SEL_GREEDIRIS &&
+      (o->m < 1 || o->m > 256 || !(o->delta > 0.0 && o->delta < 0.5) ||
+       !(o->alpha > 0.0 && o->alpha <= 1.0)))
+    return IM_EINVAL;
+  if (g->model != IM_IC && g->model != IM_LT) return IM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int32_t n = g->n;
+  const double nd = (double)n;
+  im_imm_plan_t plan;
+  IM_TRY(im_imm_plan(n, k, eps, &plan));
+  const double eps_p = plan.eps_prime;
+  const double lambda_s = plan.lambda_star;
+  const int32_t rounds = plan.rounds;
 
   *res = im_solve_result{};
   res->bucket = -1;
@@ -190,7 +206,7 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
     theta = o->theta;
   } else {
     Pool P;
-    int64_t th = (int64_t)ceil(lambda_p / (nd / 2.0));
+    int64_t th = plan.theta1;
     for (int32_t i = 1; i <= rounds; ++i) {
       if (i > 1) th *= 2;
       if (th >= ((int64_t)1 << 31)) return IM_ERANGE;

@@ -249,3 +249,31 @@ def test_batch_matches_single_calls_and_oracle(im):
         oio, oim = O.incidence(g.n, o)
         os_, og, oc = O.greedy(g.n, theta, oio, oim, k)
         assert res["seeds"] == os_.tolist() and res["coverage"] == oc, name
+
+
+def test_serving_results_equal_alone(im):
+    """Queries served together from shared, growing sample pools (3 slots on
+    3 streams) return exactly what im_solve returns for each query alone;
+    with a one-byte HBM budget admission serialises them, same results."""
+    _say("serving")
+    from paper_2408_10982_amd import serve as S
+    gs = {"ic": W.random_small_graph(3000, 15000, seed=21, p_hi=0.2),
+          "lt": W.random_small_graph(3000, 15000, seed=22, model=W.LT)}
+    prepared = {k: _prep(im, g) for k, g in gs.items()}
+    rng = np.random.default_rng(5)
+    spec = [("ic" if j % 2 else "lt", int(rng.integers(3, 20)), float(rng.choice([0.5, 0.3])))
+            for j in range(10)]
+    alone = [im.solve(prepared[name], k, eps, seed=5005) for name, k, eps in spec]
+    for budget, expect_overlap in ((1 << 40, True), (1, False)):
+        server = S.Server(prepared, seed=5005, slots=3, hbm_budget=budget)
+        qs = [S.Query(qid=j, graph=name, k=k, eps=eps, arrival=0.0)
+              for j, (name, k, eps) in enumerate(spec)]
+        done = S.run_arrivals(server, qs)
+        server.close()
+        assert (server.max_in_flight > 1) == expect_overlap
+        for q, a in zip(done, alone):
+            r = q.result
+            assert r["seeds"] == a["seeds"] and r["coverage"] == a["coverage"], q.qid
+            assert r["theta"] == a["theta"] and r["rounds"] == a["rounds"]
+            assert r["lower_bound"] == a["lower_bound"]
+            assert r["martingale_samples"] == a["martingale_samples"]

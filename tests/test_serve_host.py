@@ -1,0 +1,40 @@
+"""Host logic of the server (no GPU): admission by slots and HBM footprint."""
+
+
+def _admission():
+    # importing the package loads no GPU state; Admission is plain host logic
+    import paper_2408_10982_amd.serve as S
+    return S.Admission
+
+
+def test_admission_slots_and_budget():
+    Admission = _admission()
+    a = Admission(slots=2, budget=100)
+    for j, fp in enumerate([60, 30, 50, 10]):
+        a.push(j, fp)
+    assert a.pop() == (0, 60)
+    assert a.pop() == (1, 30)          # 90 <= 100
+    assert a.pop() is None             # slots full
+    a.release(60)
+    assert a.pop() == (2, 50)          # 30 + 50 <= 100
+    assert a.pop() is None             # slots full again
+    a.release(30)
+    a.release(50)
+    assert a.pop() == (3, 10)
+    assert a.max_in_flight == 2
+
+
+def test_admission_refuses_over_budget_and_keeps_order():
+    Admission = _admission()
+    a = Admission(slots=8, budget=100)
+    a.push("big", 90)
+    a.push("small", 5)
+    a.push("huge", 500)
+    assert a.pop() == ("big", 90)
+    assert a.pop() == ("small", 5)
+    assert a.pop() is None             # 500 does not fit beside 95
+    a.release(90)
+    assert a.pop() is None             # still not beside 5
+    a.release(5)
+    assert a.pop() == ("huge", 500)    # alone it is admitted
+    assert a.in_flight == 1 and a.reserved == 500
