@@ -83,8 +83,11 @@ def lib():
         L.or_lt_thresholds.argtypes = [C.c_int32, P, P, P]
         L.or_root.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32]
         L.or_root.restype = C.c_int32
-        L.or_sample.argtypes = [C.c_int, C.c_int32, P, P, P, C.c_uint64, C.c_uint32,
+        L.or_sample.argtypes = [C.c_int, C.c_int32, P, P, P, P, C.c_uint64, C.c_uint32,
                                 C.c_uint32, C.c_int64, C.POINTER(_Rrr)]
+        L.or_log.argtypes = [C.c_double]
+        L.or_log.restype = C.c_double
+        L.or_ic_skip_table.argtypes = [C.c_int32, P, P, P]
         L.or_rrr_free.argtypes = [C.POINTER(_Rrr)]
         L.or_incidence.argtypes = [C.c_int32, C.c_int64, P, P, P, P]
         L.or_coverage.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P]
@@ -105,7 +108,7 @@ def lib():
                                       C.c_int64, P, P, P]
         L.or_imm_parameters.argtypes = [C.c_int32, C.c_int32, C.c_double,
                                         C.POINTER(_ImmParams)]
-        L.or_imm.argtypes = [C.c_int32, P, P, P, C.POINTER(_ImmOpts), P,
+        L.or_imm.argtypes = [C.c_int32, P, P, P, P, C.POINTER(_ImmOpts), P,
                              C.POINTER(_ImmResult)]
         _lib = L
     return _lib
@@ -157,6 +160,30 @@ def thresholds(model: int, in_off, w) -> np.ndarray:
     return ic_thresholds(w) if model == IC else lt_thresholds(in_off, w)
 
 
+def log(x: float) -> float:
+    """The method's deterministic natural log (IEEE basic operations only)."""
+    return float(lib().or_log(x))
+
+
+def ic_skip_table(in_off, thr) -> np.ndarray:
+    """Per vertex: 1/log(1 - q/2^32) if its >= 2 in-edges share one threshold
+    q in (0, 0xFFFFFFFF), else 0 (one coin per in-edge)."""
+    in_off = _c(in_off, np.int32)
+    thr = _c(thr, np.uint32)
+    n = in_off.shape[0] - 1
+    out = np.zeros(n, np.float64)
+    lib().or_ic_skip_table(n, _p(in_off), _p(thr), _p(out))
+    return out
+
+
+def _skip_arg(model, in_off, thr, skip):
+    if model != IC or skip is None:
+        return None
+    if isinstance(skip, str) and skip == "auto":
+        return ic_skip_table(in_off, thr)
+    return _c(skip, np.float64)
+
+
 @dataclass
 class RRR:
     off: np.ndarray       # int64 [count+1]
@@ -177,13 +204,17 @@ class RRR:
 
 
 def sample(model: int, in_off, in_src, thr, seed: int, stream: int, first: int,
-           count: int) -> RRR:
+           count: int, skip="auto") -> RRR:
+    """skip: "auto" derives the run-length table for IC (what the method
+    uses); None flips one coin per in-edge everywhere."""
     in_off = _c(in_off, np.int32)
     in_src = _c(in_src, np.int32)
     thr = _c(thr, np.uint32)
+    sk = _skip_arg(model, in_off, thr, skip)
     r = _Rrr()
-    if lib().or_sample(model, in_off.shape[0] - 1, _p(in_off), _p(in_src), _p(thr), seed,
-                       stream, first, count, C.byref(r)):
+    if lib().or_sample(model, in_off.shape[0] - 1, _p(in_off), _p(in_src), _p(thr),
+                       _p(sk) if sk is not None else None, seed, stream, first, count,
+                       C.byref(r)):
         raise MemoryError("oracle sampling failed")
     try:
         off = np.ctypeslib.as_array(r.off, shape=(count + 1,)).copy()
@@ -305,17 +336,18 @@ def imm_parameters(n: int, k: int, eps: float) -> dict:
 
 def imm(model: int, in_off, in_src, thr, k: int, eps: float, seed: int,
         selector: int = SEL_GREEDY, m: int = 1, delta: float = 0.077, alpha: float = 1.0,
-        part_seed: int = 0, theta: int = 0, lazy: bool = True):
+        part_seed: int = 0, theta: int = 0, lazy: bool = True, skip="auto"):
     in_off = _c(in_off, np.int32)
     in_src = _c(in_src, np.int32)
     thr = _c(thr, np.uint32)
+    sk = _skip_arg(model, in_off, thr, skip)
     o = _ImmOpts(model=model, selector=selector, lazy=int(lazy), k=k, m=m, eps=eps,
                  delta=delta, alpha=alpha, seed=seed, part_seed=part_seed,
                  theta_override=theta)
     res = _ImmResult()
     seeds = np.zeros(k, np.int32)
-    if lib().or_imm(in_off.shape[0] - 1, _p(in_off), _p(in_src), _p(thr), C.byref(o),
-                    _p(seeds), C.byref(res)):
+    if lib().or_imm(in_off.shape[0] - 1, _p(in_off), _p(in_src), _p(thr),
+                    _p(sk) if sk is not None else None, C.byref(o), _p(seeds), C.byref(res)):
         raise MemoryError("oracle IMM failed")
     out = {f: getattr(res, f) for f, _ in _ImmResult._fields_}
     out["seeds"] = seeds[:res.nsel].copy()

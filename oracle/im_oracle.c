@@ -89,6 +89,73 @@ int or_lt_thresholds(int32_t n, const int32_t* in_off, const float* w, uint32_t*
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Run-length form of IC for vertices whose in-edges share one threshold.    */
+/* The live in-edges of such a vertex form a Bernoulli(p) sequence over its  */
+/* in-edge list, so the gap before the next live edge is Geometric(p):       */
+/* G = floor(log(U) / log(1 - p)), U uniform on (0, 1].  log is evaluated by */
+/* a fixed sequence of IEEE-754 basic operations (below) so that every       */
+/* implementation of the method obtains the same bits.                      */
+/* ------------------------------------------------------------------------ */
+double or_log(double x) {
+  /* x > 0, finite, normal.  x = m 2^e with m in [1, 2), folded into
+   * [sqrt(1/2), sqrt(2)); log m = 2 atanh(s), s = (m - 1)/(m + 1), as the
+   * odd series 2 (s + s^3/3 + ... + s^19/19). */
+  uint64_t bits;
+  memcpy(&bits, &x, sizeof bits);
+  int32_t e = (int32_t)((bits >> 52) & 0x7FF) - 1023;
+  uint64_t mb = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+  double m;
+  memcpy(&m, &mb, sizeof m);
+  if (m > 1.4142135623730951) {
+    m = m * 0.5;
+    e = e + 1;
+  }
+  double s = (m - 1.0) / (m + 1.0);
+  double z = s * s;
+  double t = 2.0 / 19.0;
+  t = t * z + 2.0 / 17.0;
+  t = t * z + 2.0 / 15.0;
+  t = t * z + 2.0 / 13.0;
+  t = t * z + 2.0 / 11.0;
+  t = t * z + 2.0 / 9.0;
+  t = t * z + 2.0 / 7.0;
+  t = t * z + 2.0 / 5.0;
+  t = t * z + 2.0 / 3.0;
+  t = t * z + 2.0;
+  return (double)e * 0.6931471805599453 + s * t;
+}
+
+void or_ic_skip_table(int32_t n, const int32_t* in_off, const uint32_t* thr, double* skip) {
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t a = in_off[v], b = in_off[v + 1];
+    skip[v] = 0.0;
+    if (b - a < 2) continue;
+    uint32_t q = thr[a];
+    if (q == 0u || q == 0xFFFFFFFFu) continue;
+    int same = 1;
+    for (int32_t e = a + 1; e < b; ++e)
+      if (thr[e] != q) {
+        same = 0;
+        break;
+      }
+    if (!same) continue;
+    double keep = (4294967296.0 - (double)q) * 2.3283064365386963e-10; /* (2^32 - q) 2^-32 */
+    skip[v] = 1.0 / or_log(keep);
+  }
+}
+
+/* Uniform on (0, 1] from 53 bits of draw pair j of (sample i, vertex v). */
+static double skip_uniform(uint64_t seed, uint32_t stream, uint32_t i, uint32_t v, uint32_t j) {
+  uint32_t ctr[4] = {v, i, 0x80000000u | (j >> 1), stream};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  or_philox4x32_10(ctr, key, out);
+  uint32_t hi = out[2 * (j & 1u)] >> 11, lo = out[2 * (j & 1u) + 1];
+  double u = (double)(((uint64_t)hi << 32) | lo) + 1.0;
+  return u * 1.1102230246251565e-16; /* 2^-53 */
+}
+
 int32_t or_root(uint64_t seed, uint32_t stream, uint32_t i, int32_t n) {
   uint32_t r = or_draw(seed, OR_TAG_ROOT, stream, 0u, i);
   return (int32_t)(((uint64_t)r * (uint64_t)(uint32_t)n) >> 32);
@@ -132,15 +199,33 @@ static int vec_push_many(i32vec* v, const int32_t* src, int64_t cnt) {
  * Explored by BFS over in-edges; every in-edge carries its own coin, so the
  * set does not depend on the visiting order.  Returns the set size. */
 static int32_t sample_ic_one(int32_t n, const int32_t* in_off, const int32_t* in_src,
-                             const uint32_t* thr, uint64_t seed, uint32_t stream, uint32_t i,
-                             uint32_t* mark, uint32_t stamp, int32_t* queue,
-                             int64_t* examined, int64_t* live) {
+                             const uint32_t* thr, const double* skip, uint64_t seed,
+                             uint32_t stream, uint32_t i, uint32_t* mark, uint32_t stamp,
+                             int32_t* queue, int64_t* examined, int64_t* live) {
   int32_t root = or_root(seed, stream, i, n);
   int32_t head = 0, tail = 0;
   queue[tail++] = root;
   mark[root] = stamp;
   while (head < tail) {
     int32_t v = queue[head++];
+    if (skip && skip[v] != 0.0) {
+      /* run-length form: live positions pos_j = pos_{j-1} + 1 + G_j */
+      const int64_t deg = in_off[v + 1] - in_off[v];
+      int64_t pos = -1;
+      for (uint32_t j = 0;; ++j) {
+        ++*examined;
+        double g = floor(or_log(skip_uniform(seed, stream, i, (uint32_t)v, j)) * skip[v]);
+        if (g >= (double)(deg - 1 - pos)) break; /* past the last in-edge */
+        pos += 1 + (int64_t)g;
+        ++*live;
+        int32_t u = in_src[in_off[v] + pos];
+        if (mark[u] != stamp) {
+          mark[u] = stamp;
+          queue[tail++] = u;
+        }
+      }
+      continue;
+    }
     for (int32_t e = in_off[v]; e < in_off[v + 1]; ++e) {
       ++*examined;
       uint32_t q = thr[e];
@@ -192,8 +277,8 @@ static int32_t sample_lt_one(int32_t n, const int32_t* in_off, const int32_t* in
 }
 
 int or_sample(int model, int32_t n, const int32_t* in_off, const int32_t* in_src,
-              const uint32_t* thr, uint64_t seed, uint32_t stream, uint32_t first,
-              int64_t count, or_rrr* out) {
+              const uint32_t* thr, const double* skip, uint64_t seed, uint32_t stream,
+              uint32_t first, int64_t count, or_rrr* out) {
   memset(out, 0, sizeof(*out));
   if (n <= 0 || count < 0 || (model != OR_IC && model != OR_LT)) return -1;
   uint32_t* mark = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
@@ -207,7 +292,7 @@ int or_sample(int model, int32_t n, const int32_t* in_off, const int32_t* in_src
     uint32_t stamp = (uint32_t)(s + 1);
     int32_t len;
     if (model == OR_IC)
-      len = sample_ic_one(n, in_off, in_src, thr, seed, stream, i, mark, stamp, queue,
+      len = sample_ic_one(n, in_off, in_src, thr, skip, seed, stream, i, mark, stamp, queue,
                           &out->examined, &out->live);
     else
       len = sample_lt_one(n, in_off, in_src, thr, seed, stream, i, mark, stamp, queue,
@@ -581,11 +666,11 @@ typedef struct {
 } pool_t;
 
 static int pool_extend(pool_t* P, int model, int32_t n, const int32_t* in_off,
-                       const int32_t* in_src, const uint32_t* thr, uint64_t seed,
-                       uint32_t stream, int64_t new_count) {
+                       const int32_t* in_src, const uint32_t* thr, const double* skip,
+                       uint64_t seed, uint32_t stream, int64_t new_count) {
   if (new_count <= P->count) return 0;
   or_rrr add;
-  if (or_sample(model, n, in_off, in_src, thr, seed, stream, (uint32_t)P->count,
+  if (or_sample(model, n, in_off, in_src, thr, skip, seed, stream, (uint32_t)P->count,
                 new_count - P->count, &add))
     return -1;
   int64_t* noff = (int64_t*)realloc(P->off, (size_t)(new_count + 1) * sizeof(int64_t));
@@ -637,7 +722,7 @@ static void select_on(const pool_t* P, int32_t n, const or_imm_opts* opt, int32_
 }
 
 int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32_t* thr,
-           const or_imm_opts* opt, int32_t* seeds, or_imm_result* res) {
+           const double* skip, const or_imm_opts* opt, int32_t* seeds, or_imm_result* res) {
   memset(res, 0, sizeof(*res));
   or_imm_params prm;
   or_imm_parameters(n, opt->k, opt->eps, &prm);
@@ -654,7 +739,8 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
     int64_t th = prm.theta1;
     for (int32_t i = 1; i <= prm.rounds; ++i) {
       if (i > 1) th *= 2;
-      if (pool_extend(&P, opt->model, n, in_off, in_src, thr, opt->seed, 0u, th)) return -1;
+      if (pool_extend(&P, opt->model, n, in_off, in_src, thr, skip, opt->seed, 0u, th))
+        return -1;
       select_on(&P, n, opt, seeds, &nsel, &cov, &bucket, &gwon);
       res->rounds_run = i;
       double x = nd / ldexp(1.0, i);
@@ -669,7 +755,7 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
     theta = (int64_t)ceil(prm.lambda_star / lb);
   }
   pool_t F = {0, 0, NULL, NULL};
-  if (pool_extend(&F, opt->model, n, in_off, in_src, thr, opt->seed, 1u, theta)) return -1;
+  if (pool_extend(&F, opt->model, n, in_off, in_src, thr, skip, opt->seed, 1u, theta)) return -1;
   select_on(&F, n, opt, seeds, &nsel, &cov, &bucket, &gwon);
   free(F.off);
   free(F.mem);

@@ -569,3 +569,81 @@ def test_imm_end_to_end_tiny():
     e1 = 1 - 1 / math.e
     h = 0.5 - 0.077
     assert sigma(out2["seeds"].tolist()) >= (e1 * h / (e1 + h) - eps) * opt
+
+
+# ---------------------------------------------------------------- run-length IC
+def test_log_matches_libm():
+    """The method's log agrees with the C library's to ~1 ulp across the range
+    it is used on (uniforms in (0,1] and 1 - p for p down to 2^-32)."""
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.random(2000), 1.0 - rng.random(200) * 1e-6,
+                         [2.0 ** -53, 0.5, 1.0 - 2.0 ** -32, 1.0, 0.70710678, 1.41421356, 3.0,
+                          1e-300, 1e300]])
+    for x in xs:
+        x = float(x)
+        got, ref = O.log(x), math.log(x)
+        assert abs(got - ref) <= 4e-16 * max(1.0, abs(ref)), (x, got, ref)
+    assert O.log(1.0) == 0.0
+
+
+def test_skip_table():
+    w = W.ic_weighted_cascade(np.array([0, 1, 3, 6, 6, 10], np.int32))
+    in_off = np.array([0, 1, 3, 6, 6, 10], np.int32)
+    thr = O.ic_thresholds(w)
+    sk = O.ic_skip_table(in_off, thr)
+    assert sk[0] == 0.0 and sk[3] == 0.0          # one in-edge / none: coins
+    for v, d in ((1, 2), (2, 3), (4, 4)):
+        q = int(thr[in_off[v]])
+        assert abs(sk[v] - 1.0 / math.log1p(-q / 2 ** 32)) < 1e-12 * abs(sk[v])
+    mixed = thr.copy()
+    mixed[4] ^= 1
+    assert O.ic_skip_table(in_off, mixed)[2] == 0.0   # thresholds differ: coins
+
+
+def test_skip_counts_are_binomial():
+    """A hub with D in-edges of probability p from D private leaves: the number
+    of live in-edges per visit is Binomial(D, p) under the run-length form."""
+    R, D, p = 60, 200, 0.05
+    edges = [(R + h * D + j, h) for h in range(R) for j in range(D)]
+    n = R + R * D
+    g = W.tiny_graph(n, edges, np.full(len(edges), p, np.float32))
+    thr = O.ic_thresholds(g.weight)
+    assert np.all(O.ic_skip_table(g.in_off, thr)[:R] != 0)
+    N = 400000
+    r = O.sample(O.IC, g.in_off, g.in_src, thr, 17, 0, 0, N)
+    roots = np.array([O.root(17, 0, i, n) for i in range(N)])
+    hub = roots < R
+    sizes = np.diff(r.off)[hub] - 1
+    q = int(thr[0]) / 2 ** 32
+    mean, var = D * q, D * q * (1 - q)
+    assert hub.sum() > 1000
+    assert abs(sizes.mean() - mean) < 5 * math.sqrt(var / hub.sum())
+    assert abs(sizes.var() - var) < 0.15 * var
+
+
+def test_skip_membership_matches_exact_enumeration():
+    """Weighted cascade on the tiny graph (uniform thresholds per vertex, so
+    the run-length form is used): Pr[v in R | root = t] equals the exact
+    probability over all live-edge worlds."""
+    n = 6
+    deg = np.bincount([v for _, v in TINY_EDGES], minlength=n)
+    probs = [np.float32(1.0) / np.float32(deg[v]) for _, v in TINY_EDGES]
+    g = W.tiny_graph(n, TINY_EDGES, probs)
+    thr = O.ic_thresholds(g.weight)
+    assert np.count_nonzero(O.ic_skip_table(g.in_off, thr)) >= 3
+    q = O.ic_thresholds(np.array(probs, np.float32)).astype(np.float64) / 2.0 ** 32
+    P = _exact_ic_activation(n, TINY_EDGES, list(q))
+    N = 120000
+    r = O.sample(O.IC, g.in_off, g.in_src, thr, 99, 0, 0, N)
+    roots = np.array([O.root(99, 0, i, n) for i in range(N)])
+    cnt = np.bincount(roots, minlength=n).astype(np.float64)
+    hits = np.zeros((n, n))
+    for i in range(N):
+        for v in r.set(i):
+            hits[v, roots[i]] += 1
+    for t in range(n):
+        for v in range(n):
+            mu = P[v, t]
+            f = hits[v, t] / cnt[t]
+            sd = math.sqrt(max(mu * (1 - mu), 1e-12) / cnt[t])
+            assert abs(f - mu) < 5 * sd + 1e-9, (v, t, f, mu)
