@@ -66,6 +66,7 @@ typedef struct {
   const int32_t* in_src;   /* [device] E, each in [0, n) */
   const uint32_t* thr;     /* [device] round_up(E, 4) entries from im_prepare_graph */
   int32_t model;           /* IM_IC or IM_LT, as given to im_prepare_graph */
+  const double* skip;      /* [device] n entries from im_prepare_graph (IC), or NULL */
 } im_graph;
 
 /* Sampling statistics of one im_sample_rrr call.  The counts are exact and
@@ -105,20 +106,33 @@ int im_release(void);
  *      in-edges of v up to and including e, 0xFFFFFFFF) (live-edge reading of
  *      LT: v keeps in-edge e with probability w_e, none with 1 - sum w).
  *  thr[E .. round_up(E,4)) is written 0.
+ *  IC run-length table (skip may be NULL: one coin per in-edge everywhere):
+ *      skip[v] = 1 / log(1 - q/2^32) when v has >= 2 in-edges that all share
+ *      one threshold q with 0 < q < 0xFFFFFFFF (weighted cascade gives every
+ *      vertex this shape), else 0.  For such a vertex the sampler generates
+ *      its live in-edges by geometric gaps G = floor(log(U) * skip[v]) (U on
+ *      (0,1] from 53 bits of draw pair j of (sample, v): counter (v, i,
+ *      2^31 | j/2, stream)) instead of one coin per in-edge -- the same
+ *      Bernoulli(p) sequence in distribution.  log is a fixed sequence of
+ *      IEEE basic operations (exponent split, fold into [sqrt(1/2),
+ *      sqrt(2)), odd atanh series to s^19), so results are reproducible
+ *      bit for bit.
  * in_off [device] n+1; in_src [device] E; weight [device] E fp32;
- * thr [device] round_up(E,4).  Synchronises `stream`; returns IM_EINVAL if
+ * thr [device] round_up(E,4); skip [device] n fp64 or NULL (ignored for LT).  Synchronises `stream`; returns IM_EINVAL if
  * in_off is not a valid CSR offset array (nothing else is then read), or if a
  * source id is outside [0,n), or a weight is NaN, negative, infinite, or (IC)
  * above 1 (thr is then partly written and must not be used).
  */
 int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off, const int32_t* in_src,
-                     const float* weight, int32_t model, uint32_t* thr, void* stream);
+                     const float* weight, int32_t model, uint32_t* thr, double* skip,
+                     void* stream);
 
 /*
  * RRR sampling (Def. 2.3 and Sec. 2.1; Alg. 1 Sample, Alg. 3 sampling step).
  * Generates the sets of sample ids [first, first+count) of (seed, stream_tag):
  *  root_i = floor(draw(root, i) * n / 2^32) (uniform over V);
- *  IC: R(i) = vertices with a path to root_i over edges live in sample i;
+ *  IC: R(i) = vertices with a path to root_i over edges live in sample i
+ *      (coins per in-edge, or run-length gaps where g->skip marks a vertex);
  *  LT: R(i) = the chain root_i <- u1 <- u2 ... where each vertex keeps the
  *      first in-edge e with draw(vertex, i, v) < thr[e] (or thr[e] saturated),
  *      ending at a vertex that keeps none or at a repeated vertex.

@@ -38,7 +38,8 @@ class ImError(RuntimeError):
 
 class _Graph(C.Structure):
     _fields_ = [("n", C.c_int32), ("num_edges", C.c_int64), ("in_off", C.c_void_p),
-                ("in_src", C.c_void_p), ("thr", C.c_void_p), ("model", C.c_int32)]
+                ("in_src", C.c_void_p), ("thr", C.c_void_p), ("model", C.c_int32),
+                ("skip", C.c_void_p)]
 
 
 class _Stats(C.Structure):
@@ -94,7 +95,7 @@ def lib():
         L.im_version.restype = C.c_char_p
         L.im_last_error.restype = C.c_char_p
         L.im_release.argtypes = []
-        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P]
+        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P, P]
         L.im_sample_rrr.argtypes = [C.POINTER(_Graph), U64, U32, I64, I64, P, P, I64,
                                     C.POINTER(C.c_int64), C.POINTER(_Stats), P]
         L.im_build_incidence.argtypes = [I32, I64, P, P, I64, P, P, P]
@@ -142,28 +143,36 @@ class Graph:
     in_off: torch.Tensor   # int32 [n+1]
     in_src: torch.Tensor   # int32 [E]
     thr: torch.Tensor      # int32 storage of uint32 thresholds, [round_up(E, 4)]
+    skip: torch.Tensor | None = None   # float64 [n]: IC run-length table
 
     def struct(self) -> _Graph:
         return _Graph(self.n, self.num_edges, self.in_off.data_ptr(),
                       self.in_src.data_ptr() if self.num_edges else None,
-                      self.thr.data_ptr(), self.model)
+                      self.thr.data_ptr(), self.model,
+                      self.skip.data_ptr() if self.skip is not None else None)
 
     def hbm_bytes(self) -> int:
-        return 4 * (self.in_off.numel() + self.in_src.numel() + self.thr.numel())
+        return (4 * (self.in_off.numel() + self.in_src.numel() + self.thr.numel()) +
+                (8 * self.skip.numel() if self.skip is not None else 0))
 
 
-def prepare_graph(in_off, in_src, weight, model: int, device="cuda", stream=None) -> Graph:
-    """Uploads an in-edge CSR with fp32 weights and derives the thresholds."""
+def prepare_graph(in_off, in_src, weight, model: int, device="cuda", stream=None,
+                  run_length: bool = True) -> Graph:
+    """Uploads an in-edge CSR with fp32 weights and derives the thresholds
+    (and, for IC, the run-length table unless run_length is False)."""
     in_off = torch.as_tensor(in_off, dtype=torch.int32).to(device).contiguous()
     in_src = torch.as_tensor(in_src, dtype=torch.int32).to(device).contiguous()
     weight = torch.as_tensor(weight, dtype=torch.float32).to(device).contiguous()
     n = in_off.numel() - 1
     E = in_src.numel()
     thr = torch.empty(max((E + 3) // 4 * 4, 4), dtype=torch.int32, device=device)
+    skip = (torch.empty(n, dtype=torch.float64, device=device)
+            if model == IC and run_length else None)
     st = lib().im_prepare_graph(n, E, _ptr(in_off), _ptr(in_src) if E else None,
-                                _ptr(weight) if E else None, model, _ptr(thr), _stream(stream))
+                                _ptr(weight) if E else None, model, _ptr(thr), _ptr(skip),
+                                _stream(stream))
     _check(st, "im_prepare_graph")
-    return Graph(n, E, model, in_off, in_src, thr)
+    return Graph(n, E, model, in_off, in_src, thr, skip)
 
 
 @dataclass

@@ -48,6 +48,56 @@ __device__ __forceinline__ uint32_t draw1(uint64_t seed, uint32_t tag, uint32_t 
   return pick_word(r, id & 3u);
 }
 
+// Natural log for x > 0 (normal) from IEEE-754 basic operations only, so the
+// result is the same bits on every implementation of the method: split
+// x = m 2^e, fold m into [sqrt(1/2), sqrt(2)), log m = 2 atanh(s) with
+// s = (m-1)/(m+1) as the odd series up to s^19.
+__host__ __device__ inline double im_log(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+#else
+  unsigned long long bits;
+  __builtin_memcpy(&bits, &x, sizeof bits);
+#endif
+  int e = (int)((bits >> 52) & 0x7FF) - 1023;
+  const unsigned long long mb = (bits & 0x000FFFFFFFFFFFFFull) | 0x3FF0000000000000ull;
+#if defined(__HIP_DEVICE_COMPILE__)
+  double m = __longlong_as_double((long long)mb);
+#else
+  double m;
+  __builtin_memcpy(&m, &mb, sizeof m);
+#endif
+  if (m > 1.4142135623730951) {
+    m = m * 0.5;
+    e = e + 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double z = s * s;
+  double t = 2.0 / 19.0;
+  t = t * z + 2.0 / 17.0;
+  t = t * z + 2.0 / 15.0;
+  t = t * z + 2.0 / 13.0;
+  t = t * z + 2.0 / 11.0;
+  t = t * z + 2.0 / 9.0;
+  t = t * z + 2.0 / 7.0;
+  t = t * z + 2.0 / 5.0;
+  t = t * z + 2.0 / 3.0;
+  t = t * z + 2.0;
+  return (double)e * 0.6931471805599453 + s * t;
+}
+
+// Uniform on (0, 1] from 53 bits of draw pair j of (sample i, vertex v):
+// counter (v, i, 2^31 | j/2, stream), words 2(j&1) (high 21 bits) and
+// 2(j&1)+1.
+__device__ __forceinline__ double skip_uniform(uint32_t seed_lo, uint32_t seed_hi,
+                                               uint32_t stream, uint32_t i, uint32_t v,
+                                               uint32_t j) {
+  const uint4 r = philox4x32_10(make_uint4(v, i, 0x80000000u | (j >> 1), stream), seed_lo, seed_hi);
+  const uint32_t hi = ((j & 1u) ? r.z : r.x) >> 11, lo = (j & 1u) ? r.w : r.y;
+  const double u = (double)(((unsigned long long)hi << 32) | lo) + 1.0;
+  return u * 1.1102230246251565e-16;  // 2^-53
+}
+
 // floor(r * n / 2^32): maps a uniform word onto [0, n).
 __device__ __forceinline__ uint32_t scale_draw(uint32_t r, uint32_t n) {
   return (uint32_t)(((uint64_t)r * (uint64_t)n) >> 32);

@@ -69,11 +69,31 @@ __global__ void k_lt_thresholds(int32_t n, int64_t E, int64_t E4,
   }
 }
 
+// Run-length table: 1/log(1 - q/2^32) for vertices whose >= 2 in-edges share
+// one threshold strictly between 0 and 0xFFFFFFFF; 0 elsewhere.
+__global__ void k_ic_skip(int32_t n, const int32_t* __restrict__ in_off,
+                          const uint32_t* __restrict__ thr, double* __restrict__ skip) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t a = in_off[v], b = in_off[v + 1];
+  double out = 0.0;
+  if (b - a >= 2) {
+    const uint32_t q = thr[a];
+    bool same = q != 0u && q != 0xFFFFFFFFu;
+    for (int32_t e = a + 1; same && e < b; ++e) same = thr[e] == q;
+    if (same) {
+      const double keep = (4294967296.0 - (double)q) * 2.3283064365386963e-10;  // (2^32-q) 2^-32
+      out = 1.0 / im_log(keep);
+    }
+  }
+  skip[v] = out;
+}
+
 }  // namespace im
 
 extern "C" int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off,
                                 const int32_t* in_src, const float* weight, int32_t model,
-                                uint32_t* thr, void* stream) {
+                                uint32_t* thr, double* skip, void* stream) {
   using namespace im;
   if (n <= 0 || num_edges < 0 || num_edges >= (int64_t)0x7FFFFFFF || !in_off || !thr ||
       (num_edges > 0 && (!weight || !in_src)) || (model != IM_IC && model != IM_LT))
@@ -102,6 +122,10 @@ extern "C" int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_
                                                                            flags);
   }
   IM_HIP(hipGetLastError());
+  if (model == IM_IC && skip) {
+    k_ic_skip<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, in_off, thr, skip);
+    IM_HIP(hipGetLastError());
+  }
   IM_HIP(hipMemcpyAsync(&hf, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   IM_HIP(hipStreamSynchronize(s));
   return hf ? IM_EINVAL : IM_OK;

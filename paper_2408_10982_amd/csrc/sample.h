@@ -13,6 +13,7 @@ struct TaskDesc {
   const int32_t* in_off;
   const int32_t* in_src;
   const uint32_t* thr;
+  const double* skip;      // IC run-length table or nullptr
   int32_t n;
   int32_t model;
   uint32_t seed_lo, seed_hi;

@@ -73,6 +73,7 @@ struct GView {
   const int32_t* in_off;
   const int32_t* in_src;
   const uint32_t* thr;
+  const double* skip;
   uint32_t n, seed_lo, seed_hi, stream;
 };
 
@@ -81,6 +82,7 @@ __device__ __forceinline__ GView view_of(const TaskDesc& T) {
   g.in_off = T.in_off;
   g.in_src = T.in_src;
   g.thr = T.thr;
+  g.skip = T.model == IM_IC ? T.skip : nullptr;
   g.n = (uint32_t)T.n;
   g.seed_lo = T.seed_lo;
   g.seed_hi = T.seed_hi;
@@ -264,13 +266,32 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       ex0 = s_ex;
       lv0 = s_lv;
       const int32_t nf = min(tail - head, kWave);
-      int32_t a = 0, b = 0, ng = 0;
+      int32_t a = 0, b = 0, ng = 0, v = 0;
+      double sk = 0.0;
       if (lane < nf) {
-        const int32_t v = L.queue[head + lane];
+        v = L.queue[head + lane];
         a = G.in_off[v];
         b = G.in_off[v + 1];
-        if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
-        s_ex += (unsigned long long)(b - a);
+        if (G.skip) sk = G.skip[v];
+        if (sk == 0.0) {
+          if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
+          s_ex += (unsigned long long)(b - a);
+        }
+      }
+      // run-length vertices: this lane walks the geometric gaps itself
+      if (sk != 0.0) {
+        const int64_t deg = b - a;
+        int64_t pos = -1;
+        for (uint32_t j = 0;; ++j) {
+          ++s_ex;
+          const double gap =
+              floor(im_log(skip_uniform(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j)) * sk);
+          if (gap >= (double)(deg - 1 - pos)) break;
+          pos += 1 + (int64_t)gap;
+          ++s_lv;
+          lds_insert(L, G.in_src[a + pos], &over);
+          if (over) break;
+        }
       }
       const int32_t inc = wave_inclusive_scan(ng);
       const int32_t total = __shfl(inc, kWave - 1, kWave);
@@ -488,8 +509,27 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
           const int32_t v = queue[head + t];
           a = G.in_off[v];
           b = G.in_off[v + 1];
-          if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
-          s_ex += (unsigned long long)(b - a);
+          const double sk = G.skip ? G.skip[v] : 0.0;
+          if (sk == 0.0) {
+            if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
+            s_ex += (unsigned long long)(b - a);
+          } else {  // run-length vertex: walk its geometric gaps here
+            const int64_t deg = b - a;
+            int64_t pos = -1;
+            for (uint32_t j = 0;; ++j) {
+              ++s_ex;
+              const double gap = floor(
+                  im_log(skip_uniform(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j)) * sk);
+              if (gap >= (double)(deg - 1 - pos)) break;
+              pos += 1 + (int64_t)gap;
+              ++s_lv;
+              const int32_t v2 = G.in_src[a + pos];
+              const uint32_t bit = 1u << (v2 & 31);
+              const uint32_t old = atomicOr(&bm[v2 >> 5], bit);
+              if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = v2;
+            }
+            a = b = 0;
+          }
         }
         int64_t tot64;
         const int32_t ex = (int32_t)block_exclusive_scan64(ng, scan_lds, &tot64);
@@ -1083,6 +1123,7 @@ TaskDesc task_of(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t 
   T.in_off = g->in_off;
   T.in_src = g->in_src;
   T.thr = g->thr;
+  T.skip = g->skip;
   T.n = g->n;
   T.model = g->model;
   T.seed_lo = (uint32_t)seed;

@@ -51,6 +51,8 @@ GRAPHS = {
     "lt_chain": lambda: W.tiny_graph(3000, [(v, v + 1) for v in range(2999)],
                                      np.ones(2999, np.float32), model=W.LT),
     "rmat12": lambda: W.config(1).graph,
+    "rmat14_wc": lambda: W.make_graph("rmat", W.IC, scale=14, num_edges=1 << 18, graph_seed=77,
+                                      weight_seed=78, weights="wc"),
 }
 
 
@@ -62,12 +64,15 @@ def test_thresholds(im, name):
     got = _np(G.thr).view(np.uint32)[:g.num_edges]
     assert np.array_equal(got, _oracle_thr(g))
     assert np.all(_np(G.thr)[g.num_edges:] == 0)
+    if g.model == W.IC:  # run-length table, bit for bit (exercises the log)
+        sk = O.ic_skip_table(g.in_off, _oracle_thr(g))
+        assert np.array_equal(_np(G.skip).view(np.uint64), sk.view(np.uint64))
 
 
 @pytest.mark.parametrize("name,first,count", [
     ("ic_sparse", 0, 3000), ("ic_dense", 17, 2001), ("ic_p1", 5, 700), ("lt_small", 0, 4000),
     ("lt_chain", 3, 600), ("rmat12", 0, 16384), ("rmat12", 100000, 999),
-    ("ic_p1", 0, 70000)])
+    ("ic_p1", 0, 70000), ("rmat14_wc", 0, 20000), ("rmat14_wc", 12345, 3000)])
 def test_sample_rrr(im, name, first, count):
     _say("sample", name, first, count)
     g = GRAPHS[name]()
@@ -147,7 +152,7 @@ def _pipeline(im, g, count, seed):
 
 @pytest.mark.parametrize("name,count,k", [("ic_sparse", 3000, 10), ("ic_dense", 2000, 25),
                                           ("lt_small", 6000, 40), ("rmat12", 16384, 16),
-                                          ("ic_p1", 500, 8)])
+                                          ("ic_p1", 500, 8), ("rmat14_wc", 20000, 30)])
 def test_greedy(im, name, count, k):
     _say("greedy", name, count, k)
     g = GRAPHS[name]()
