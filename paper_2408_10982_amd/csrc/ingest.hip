@@ -71,20 +71,42 @@ __global__ void k_lt_thresholds(int32_t n, int64_t E, int64_t E4,
 
 // Run-length table: 1/log(1 - q/2^32) for vertices whose >= 2 in-edges share
 // one threshold strictly between 0 and 0xFFFFFFFF; 0 elsewhere.
-__global__ void k_ic_skip(int32_t n, const int32_t* __restrict__ in_off,
-                          const uint32_t* __restrict__ thr, double* __restrict__ skip) {
+__global__ __launch_bounds__(256) void k_ic_skip(int32_t n, const int32_t* __restrict__ in_off,
+                                                 const uint32_t* __restrict__ thr,
+                                                 double* __restrict__ skip) {
+  constexpr int kShort = 16;  // lists up to this length are checked by their own lane
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int32_t a = in_off[v], b = in_off[v + 1];
-  double out = 0.0;
-  if (b - a >= 2) {
-    const uint32_t q = thr[a];
-    bool same = q != 0u && q != 0xFFFFFFFFu;
-    for (int32_t e = a + 1; same && e < b; ++e) same = thr[e] == q;
-    if (same) {
-      const double keep = (4294967296.0 - (double)q) * 2.3283064365386963e-10;  // (2^32-q) 2^-32
-      out = 1.0 / im_log(keep);
+  const int lane = lane_id();
+  int32_t a = 0, b = 0;
+  uint32_t q = 0;
+  bool same = false;
+  if (v < n) {
+    a = in_off[v];
+    b = in_off[v + 1];
+    if (b - a >= 2) {
+      q = thr[a];
+      same = q != 0u && q != 0xFFFFFFFFu;
     }
+  }
+  if (same && b - a <= kShort)
+    for (int32_t e = a + 1; same && e < b; ++e) same = thr[e] == q;
+  // long lists: the whole wavefront compares one list at a time
+  unsigned long long todo = __ballot(same && b - a > kShort);
+  while (todo) {
+    const int src = __ffsll(todo) - 1;
+    todo &= todo - 1;
+    const int32_t sa = __shfl(a, src, kWave), sb = __shfl(b, src, kWave);
+    const uint32_t sq = (uint32_t)__shfl((int)q, src, kWave);
+    bool ok = true;
+    for (int32_t e = sa + 1 + lane; e < sb; e += kWave) ok = ok && thr[e] == sq;
+    const bool all = __ballot(!ok) == 0ull;
+    if (lane == src) same = all;
+  }
+  if (v >= n) return;
+  double out = 0.0;
+  if (same) {
+    const double keep = (4294967296.0 - (double)q) * 2.3283064365386963e-10;  // (2^32-q) 2^-32
+    out = 1.0 / im_log(keep);
   }
   skip[v] = out;
 }

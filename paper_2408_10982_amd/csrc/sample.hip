@@ -37,6 +37,7 @@ namespace im {
 constexpr int kSmallBlock = 256;            // 4 waves, each its own sample
 constexpr int kSmallH = 512;                // LDS hash slots per wave
 constexpr int kSmallCap = 256;              // members before handing off
+constexpr int kStage = 128;                 // staged live in-edges per wave
 constexpr int kBigBlock = 256;
 constexpr int kBigSortCap = 2048;           // large sets up to this size sort in LDS
 constexpr uint32_t kMaxHandoff = 1u << 16;  // large sets that resume from a snapshot
@@ -143,12 +144,13 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 // Tuning knobs (compile-time): groups per lane per iteration, and an
 // occupancy hint for the two IC kernels.
 // Measured on MI355X (R-MAT 2^20, IC weighted cascade, 2^20 sets): two groups
-// per lane at 8 waves per SIMD beat four groups at 4 waves per SIMD by 22%.
+// per lane beat four by 22%; with the fp64 log of the run-length walks, 6
+// waves per SIMD (80 VGPRs) beat 8 (64 VGPRs, spilling), 5 and 4.
 #ifndef IM_UNROLL
 #define IM_UNROLL 2
 #endif
 #ifndef IM_IC_WAVES_PER_EU
-#define IM_IC_WAVES_PER_EU 8
+#define IM_IC_WAVES_PER_EU 6
 #endif
 #define IM_IC_ATTR __attribute__((amdgpu_waves_per_eu(IM_IC_WAVES_PER_EU)))
 constexpr int kUnroll = IM_UNROLL;  // 4-edge groups per lane per iteration
@@ -163,6 +165,14 @@ constexpr unsigned long long kChunk = 1024;
 __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
   const uint32_t lo = __shfl((uint32_t)x, src, kWave);
   const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// A value every lane holds alike, moved to scalar registers (the compiler
+// cannot prove that a value read back from one lane is wave-uniform).
+__device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
   return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -188,8 +198,10 @@ struct __align__(16) WaveLds {
   int32_t gbase[kWave];  // group id of a lane's first group minus its prefix start
   int32_t ea[kWave];     // in-edge range of each frontier vertex
   int32_t eb[kWave];
+  int32_t stage[kStage];  // live in-edges whose sources are still to be loaded
   int32_t tail;
-  int32_t pad[3];
+  int32_t nst;            // entries pushed to stage (may exceed kStage)
+  int32_t pad[2];
 };
 
 // Inserts u; returns true if it was new.  Gives up (sets *over) once the
@@ -220,6 +232,29 @@ __device__ __forceinline__ void lds_insert(WaveLds& L, int32_t u, bool* over) {
   }
 }
 
+// Live in-edges are staged by edge index and their sources loaded together,
+// one load per lane, so a BFS level waits for one round trip to in_src
+// instead of one per live edge of its busiest lane.  An edge that finds the
+// stage full is loaded and inserted at once.
+__device__ __forceinline__ void stage_push(WaveLds& L, const int32_t* __restrict__ in_src,
+                                           int32_t e, bool* over) {
+  const int32_t k = atomicAdd(&L.nst, 1);
+  if (k < kStage)
+    L.stage[k] = e;
+  else
+    lds_insert(L, in_src[e], over);
+}
+
+__device__ __forceinline__ void stage_flush(WaveLds& L, const int32_t* __restrict__ in_src,
+                                            int lane, bool* over) {
+  wave_sync();
+  const int32_t ns = min(L.nst, kStage);
+  for (int32_t k = lane; k < ns; k += kWave) lds_insert(L, in_src[L.stage[k]], over);
+  wave_sync();
+  if (lane == 0) L.nst = 0;
+  wave_sync();
+}
+
 __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(SampleArgs A) {
   __shared__ WaveLds lds_all[kSmallBlock / kWave];
   WaveLds& L = lds_all[threadIdx.x / kWave];
@@ -233,7 +268,7 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
     if (next == end) {
       unsigned long long b = 0;
       if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kGrab);
-      b = shfl_u64(b, 0);
+      b = first_lane_u64(shfl_u64(b, 0));
       if (b >= A.count) break;
       next = b;
       end = min(b + kGrab, (unsigned long long)A.count);
@@ -253,13 +288,14 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       L.hash[hash_slot(root, 9)] = root;
       L.queue[0] = root;
       L.tail = 1;
+      L.nst = 0;
     }
     wave_sync();
     int32_t head = 0, tail = 1;
     bool over = false;
-    unsigned long long s_ex = 0, s_lv = 0;
+    uint32_t s_ex = 0, s_lv = 0;  // this set's draws / live edges, per lane
     int32_t head0 = 0, tail0 = 1;
-    unsigned long long ex0 = 0, lv0 = 0;
+    uint32_t ex0 = 0, lv0 = 0;
     while (head < tail) {
       head0 = head;  // snapshot for a hand-off
       tail0 = tail;
@@ -275,7 +311,7 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
         if (G.skip) sk = G.skip[v];
         if (sk == 0.0) {
           if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
-          s_ex += (unsigned long long)(b - a);
+          s_ex += (uint32_t)(b - a);
         }
       }
       // run-length vertices: this lane walks the geometric gaps itself
@@ -289,7 +325,7 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
           if (gap >= (double)(deg - 1 - pos)) break;
           pos += 1 + (int64_t)gap;
           ++s_lv;
-          lds_insert(L, G.in_src[a + pos], &over);
+          stage_push(L, G.in_src, a + (int32_t)pos, &over);
           if (over) break;
         }
       }
@@ -321,6 +357,7 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
             q[u] = reinterpret_cast<const uint4*>(G.thr)[g[u]];
           }
         }
+        uint32_t lm = 0;  // live words of this lane's groups, bit u * 4 + w
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           if (ea[u] < eb[u]) {
@@ -331,17 +368,37 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
             for (int w = 0; w < 4; ++w) {
               const int32_t e = e0 + w;
               const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
-              if (e >= ea[u] && e < eb[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
-                ++s_lv;
-                lds_insert(L, G.in_src[e], &over);
-              }
+              if (e >= ea[u] && e < eb[u] && (qw == 0xFFFFFFFFu || rw < qw)) lm |= 1u << (u * 4 + w);
             }
           }
         }
-        wave_sync();
+        {  // stage this iteration's live edges at wave-scanned positions
+          const int32_t c = __popc(lm);
+          const int32_t incl = wave_inclusive_scan(c);
+          const int32_t base = L.nst;
+          int32_t k = base + incl - c;
+          s_lv += (uint32_t)c;
+          while (lm) {
+            const int bit = __ffs(lm) - 1;
+            lm &= lm - 1;
+            uint32_t gb = g[0];
+#pragma unroll
+            for (int u = 1; u < kUnroll; ++u)
+              if ((bit >> 2) == u) gb = g[u];
+            const int32_t e = (int32_t)(gb << 2) + (bit & 3);
+            if (k < kStage)
+              L.stage[k] = e;
+            else
+              lds_insert(L, G.in_src[e], &over);
+            ++k;
+          }
+          wave_sync();
+          if (lane == kWave - 1) L.nst = base + incl;
+        }
+        stage_flush(L, G.in_src, lane, &over);
         if (__any(over)) break;
       }
-      wave_sync();
+      stage_flush(L, G.in_src, lane, &over);  // the walks' edges when no groups ran
       tail = L.tail;
       if (__any(over) || tail > kSmallCap) {
         over = true;
@@ -349,8 +406,9 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       }
     }
     if (over) {
-      const unsigned long long hex = wave_sum(ex0), hlv = wave_sum(lv0);
-      const unsigned long long redo = wave_sum(s_ex - ex0);
+      const unsigned long long hex = wave_sum((unsigned long long)ex0);
+      const unsigned long long hlv = wave_sum((unsigned long long)lv0);
+      const unsigned long long redo = wave_sum((unsigned long long)(s_ex - ex0));
       if (lane == 0 && redo) atomicAdd(&A.ctr[9], redo);
       uint32_t slot = 0;
       if (lane == 0) slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
@@ -396,7 +454,7 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       const unsigned long long want = max((unsigned long long)tail, kChunk);
       unsigned long long b = 0;
       if (lane == 0) b = atomicAdd(&A.ctr[1], want);
-      cpos = shfl_u64(b, 0);
+      cpos = first_lane_u64(shfl_u64(b, 0));
       cend = cpos + want;
     }
     const unsigned long long pos = cpos;
@@ -449,6 +507,42 @@ __device__ __forceinline__ int64_t block_exclusive_scan64(int64_t x, int64_t* ld
   return r;
 }
 
+constexpr int kBigStage = 1024;  // staged live in-edges per workgroup
+
+// Marks u visited in the worker's bitmap and queues it if it was new.
+__device__ __forceinline__ void big_insert(int32_t u, uint32_t* __restrict__ bm,
+                                           int32_t* __restrict__ queue, int32_t* s_tail) {
+  const uint32_t bit = 1u << (u & 31);
+  const uint32_t old = atomicOr(&bm[u >> 5], bit);
+  if (!(old & bit)) queue[atomicAdd(s_tail, 1)] = u;
+}
+
+// As in the small path: live in-edges are staged by index and their sources
+// loaded together; an edge that finds the stage full is handled at once.
+__device__ __forceinline__ void big_push(int32_t e, int32_t* stage, int32_t* s_nst,
+                                         const int32_t* __restrict__ in_src,
+                                         uint32_t* __restrict__ bm, int32_t* __restrict__ queue,
+                                         int32_t* s_tail) {
+  const int32_t k = atomicAdd(s_nst, 1);
+  if (k < kBigStage)
+    stage[k] = e;
+  else
+    big_insert(in_src[e], bm, queue, s_tail);
+}
+
+// Every thread of the block must call.
+__device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
+                                          const int32_t* __restrict__ in_src,
+                                          uint32_t* __restrict__ bm, int32_t* __restrict__ queue,
+                                          int32_t* s_tail) {
+  __syncthreads();
+  const int32_t ns = min(*s_nst, kBigStage);
+  for (int32_t k = threadIdx.x; k < ns; k += kBigBlock) big_insert(in_src[stage[k]], bm, queue, s_tail);
+  __syncthreads();
+  if (threadIdx.x == 0) *s_nst = 0;
+  __syncthreads();
+}
+
 // One workgroup per large set: visited bitmap and queue in HBM (private to
 // the worker), members written in ascending order.
 __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
@@ -458,6 +552,8 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
   __shared__ int32_t eb[kBigBlock];
   __shared__ int64_t scan_lds[kBigBlock / kWave + 1];
   __shared__ int32_t sorted[kBigSortCap];
+  __shared__ int32_t stage[kBigStage];
+  __shared__ int32_t s_nst;
   __shared__ int32_t s_tail;
   __shared__ uint32_t s_item;
   __shared__ unsigned long long s_pos;
@@ -501,6 +597,7 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
         queue[0] = root;
         s_tail = 1;
       }
+      if (t == 0) s_nst = 0;
       __syncthreads();
       while (head < tail) {
         const int32_t nf = min(tail - head, kBigBlock);
@@ -523,10 +620,7 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
               if (gap >= (double)(deg - 1 - pos)) break;
               pos += 1 + (int64_t)gap;
               ++s_lv;
-              const int32_t v2 = G.in_src[a + pos];
-              const uint32_t bit = 1u << (v2 & 31);
-              const uint32_t old = atomicOr(&bm[v2 >> 5], bit);
-              if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = v2;
+              big_push(a + (int32_t)pos, stage, &s_nst, G.in_src, bm, queue, &s_tail);
             }
             a = b = 0;
           }
@@ -571,16 +665,15 @@ __global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs 
                 const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
                 if (e >= e_a[u] && e < e_b[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
                   ++s_lv;
-                  const int32_t v2 = G.in_src[e];
-                  const uint32_t bit = 1u << (v2 & 31);
-                  const uint32_t old = atomicOr(&bm[v2 >> 5], bit);
-                  if (!(old & bit)) queue[atomicAdd(&s_tail, 1)] = v2;
+                  big_push(e, stage, &s_nst, G.in_src, bm, queue, &s_tail);
                 }
               }
             }
           }
+          __syncthreads();
+          if (s_nst >= kBigStage / 2) big_flush(stage, &s_nst, G.in_src, bm, queue, &s_tail);
         }
-        __syncthreads();
+        big_flush(stage, &s_nst, G.in_src, bm, queue, &s_tail);
         tail = s_tail;
         __syncthreads();
       }
