@@ -152,7 +152,15 @@ int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t
  * Covering subsets (Sec. 3.2; Alg. 3 per-vertex step): S(v) = {j : v in R(j)}
  * for the count sets in (off, mem), j local indices in [0, count).
  * inc_off [device] n+1 int64; inc_mem [device] off[count] int32.  The order of
- * the ids inside one S(v) is unspecified (S(v) is a set).  Asynchronous.
+ * the ids inside one S(v) is unspecified (S(v) is a set).  Members must lie in
+ * [0, n) (the caller's contract; sets from im_sample_rrr do).  Collections of
+ * at most 256 members per vertex (the environment variable
+ * IM_INCIDENCE_DENSE_RATIO changes that bound) are transposed through LDS
+ * histograms: scratch holds 8 bytes per member, up to 40% of the free device
+ * memory, and a larger collection is transposed in rounds of vertex-id ranges
+ * (IM_INCIDENCE_PAIR_BUDGET, a member count, lowers that cap; the round split
+ * synchronises `stream` once).  Denser collections use one global atomic per
+ * member and pass.  Otherwise asynchronous.
  */
 int im_build_incidence(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                        int64_t total, int64_t* inc_off, int32_t* inc_mem, void* stream);

@@ -5,8 +5,9 @@
 // their vertices one after the other in one count array, and every task
 // becomes one partition of the greedy launches (own vertex range, own
 // samples, own k).  All IC tasks are sampled by one launch and all LT tasks
-// by another; covering subsets of all tasks are built by one histogram, one
-// scan and one scatter; the greedy runs max k picks for all tasks together.
+// by another; covering subsets of all tasks are built by one transpose
+// (vertices of task t at vbase[t] + id); the greedy runs max k picks for all
+// tasks together.
 // Each task's seeds are therefore exactly those of im_sample_rrr +
 // im_build_incidence + im_greedy_cover on that task alone.
 #include <algorithm>
@@ -14,68 +15,10 @@
 
 #include "common.h"
 #include "cover.h"
+#include "incidence.h"
 #include "sample.h"
 
 namespace im {
-
-constexpr int kBatchBlock = 256;
-constexpr int kBatchRun = 16;  // members per thread
-
-struct BatchInc {
-  const int64_t* __restrict__ off;    // over all samples
-  const int32_t* __restrict__ mem;    // task-local vertex ids
-  int64_t total;
-  int64_t count;
-  const int64_t* __restrict__ sbase;  // ntasks+1 sample positions
-  const int64_t* __restrict__ vbase;  // ntasks+1 vertex positions
-  int32_t ntasks;
-  uint32_t* __restrict__ deg;
-  uint32_t* __restrict__ fill;
-  const int64_t* __restrict__ inc_off;
-  int32_t* __restrict__ inc_mem;      // task-local sample ids
-};
-
-__device__ __forceinline__ int64_t last_leq(const int64_t* a, int64_t n, int64_t x) {
-  int64_t lo = 0, hi = n - 1;  // last index with a[i] <= x
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (a[mid] <= x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// Each thread walks kBatchRun consecutive members, tracking the sample and
-// the task that own them.  scatter = false: degree histogram; true: scatter.
-template <bool kScatter>
-__global__ __launch_bounds__(kBatchBlock) void k_batch_incidence(BatchInc B) {
-  const int64_t t0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kBatchRun;
-  if (t0 >= B.total) return;
-  int64_t j = last_leq(B.off, B.count, t0);
-  int64_t end_j = B.off[j + 1];
-  int task = (int)last_leq(B.sbase, B.ntasks, j);
-  int64_t task_end = B.sbase[task + 1];
-  const int64_t t1 = min(t0 + kBatchRun, B.total);
-  for (int64_t t = t0; t < t1; ++t) {
-    while (t >= end_j) {
-      ++j;
-      end_j = B.off[j + 1];
-    }
-    while (j >= task_end) {
-      ++task;
-      task_end = B.sbase[task + 1];
-    }
-    const int64_t gv = B.vbase[task] + B.mem[t];
-    if (!kScatter) {
-      atomicAdd(&B.deg[gv], 1u);
-    } else {
-      const uint32_t slot = atomicAdd(&B.fill[gv], 1u);
-      B.inc_mem[B.inc_off[gv] + slot] = (int32_t)(j - B.sbase[task]);
-    }
-  }
-}
 
 static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32_t* seeds,
                        int64_t* gains, int32_t* nsel, int64_t* coverage, im_batch_stats* st,
@@ -103,9 +46,9 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   sb[nt] = S;
   vb[nt] = V;
   if (S >= ((int64_t)1 << 32) || V >= ((int64_t)1 << 31)) return IM_EINVAL;
-  // tables | off | inc_off | deg | fill | cnt | covered | gmax | done
+  // tables | off | inc_off | cnt | covered | gmax | done
   const size_t tab = (size_t)(nt + 1) * 16 + (size_t)nt * 12 + 256;
-  const size_t bytes = tab + (size_t)(S + 1) * 8 + (size_t)(V + 1) * 8 + (size_t)V * 12 +
+  const size_t bytes = tab + (size_t)(S + 1) * 8 + (size_t)(V + 1) * 8 + (size_t)V * 4 +
                        (size_t)S + (size_t)max_k * nt * 8 + 64 + 8 * 64;
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotBatch, bytes, &p));
@@ -121,8 +64,6 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   int32_t* d_kp = (int32_t*)take((size_t)nt * 4);
   int64_t* off = (int64_t*)take((size_t)(S + 1) * 8);
   int64_t* inc_off = (int64_t*)take((size_t)(V + 1) * 8);
-  uint32_t* deg = (uint32_t*)take((size_t)V * 4);
-  uint32_t* fill = (uint32_t*)take((size_t)V * 4);
   uint32_t* cnt = (uint32_t*)take((size_t)V * 4);
   uint8_t* covered = (uint8_t*)take((size_t)S);
   unsigned long long* gmax = (unsigned long long*)take((size_t)max_k * nt * 8);
@@ -166,19 +107,8 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   void* ip = nullptr;
   IM_TRY(scratch(s, kSlotBatchInc, (size_t)std::max<int64_t>(total, 1) * 4, &ip));
   int32_t* inc_mem = (int32_t*)ip;
-  IM_HIP(hipMemsetAsync(deg, 0, (size_t)V * 4, s));
-  IM_HIP(hipMemsetAsync(fill, 0, (size_t)V * 4, s));
-  BatchInc B{off, mem, total, S, d_sb, d_vb, nt, deg, fill, inc_off, inc_mem};
-  const int64_t blocks = ((total + kBatchRun - 1) / kBatchRun + kBatchBlock - 1) / kBatchBlock;
-  if (total > 0) {
-    k_batch_incidence<false><<<dim3((unsigned)blocks), dim3(kBatchBlock), 0, s>>>(B);
-    IM_HIP(hipGetLastError());
-  }
-  IM_TRY(exclusive_scan_u32_to_i64(deg, V, inc_off, s));
-  if (total > 0) {
-    k_batch_incidence<true><<<dim3((unsigned)blocks), dim3(kBatchBlock), 0, s>>>(B);
-    IM_HIP(hipGetLastError());
-  }
+  const IncSrc src{off, S, mem, total, d_sb, d_vb, nt};
+  IM_TRY(build_incidence(src, (int32_t)V, inc_off, inc_mem, s));
   IM_HIP(hipEventRecord(ev[2], s));
   // greedy on every task at once
   CoverArgs A{};

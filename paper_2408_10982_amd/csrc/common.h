@@ -198,6 +198,7 @@ enum Slot {
   kSlotBatch,
   kSlotBatchMem,
   kSlotBatchInc,
+  kSlotIncPairs,
   kSlotCount
 };
 

@@ -141,6 +141,65 @@ def test_incidence(im, name, count):
     assert np.array_equal(gim, oim)
 
 
+def _segments_sorted(inc_off, inc_mem):
+    """Each S(v) sorted (the order inside a covering subset is unspecified)."""
+    io = np.asarray(inc_off)
+    seg = np.repeat(np.arange(io.shape[0] - 1), np.diff(io))
+    im_ = np.asarray(inc_mem)
+    return io, im_[np.lexsort((im_, seg))]
+
+
+@pytest.mark.parametrize("form", ["auto", "dense"])
+@pytest.mark.parametrize("n,count,max_size,seed", [
+    (5000, 4000, 40, 1),                 # one bucket of vertex ids, ragged tail
+    (4096 * 4096 + 4099, 3000, 300, 2),  # ids wider than 4096 buckets of 2^12
+    (70000, 1, 60000, 3),                # a single set spanning many chunks
+])
+def test_incidence_synthetic(im, n, count, max_size, seed, form, monkeypatch):
+    """Covering subsets of synthetic collections (distinct ids per set, sizes
+    from 0 up), against the oracle's transpose; "dense" forces the atomic form."""
+    _say("incidence synthetic", n, count, max_size, form)
+    if form == "dense":
+        monkeypatch.setenv("IM_INCIDENCE_DENSE_RATIO", "0")
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(0, max_size + 1, size=count)
+    sizes[0] = max_size
+    off = np.zeros(count + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    mem = np.concatenate([np.sort(rng.choice(n, size=int(z), replace=False)) for z in sizes]
+                         ).astype(np.int32)
+    o = O.RRR(off=off, mem=mem, examined=0, live=0)
+    oio, oim = O.incidence(n, o)
+    r = im.RRR(off=torch.from_numpy(off).cuda(), mem=torch.from_numpy(mem).cuda(),
+               total=int(off[-1]), examined=0, live=0, large_sets=0)
+    io, imem = im.build_incidence(n, r)
+    gio, gim = _segments_sorted(_np(io), _np(imem))
+    assert np.array_equal(gio, oio)
+    assert np.array_equal(gim, oim)
+
+
+@pytest.mark.parametrize("budget", ["1", "2000", "50000"])
+def test_incidence_rounds(im, budget, monkeypatch):
+    """The transpose in rounds of buckets (pair budget forced small; budget 1
+    gives every bucket a round of its own, larger than the budget)."""
+    _say("incidence rounds", budget)
+    monkeypatch.setenv("IM_INCIDENCE_PAIR_BUDGET", budget)
+    n, count = 3 * 4096 + 77, 2500
+    rng = np.random.default_rng(9)
+    sizes = rng.integers(0, 120, size=count)
+    off = np.zeros(count + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    mem = np.concatenate([np.sort(rng.choice(n, size=int(z), replace=False)) for z in sizes]
+                         ).astype(np.int32)
+    oio, oim = O.incidence(n, O.RRR(off=off, mem=mem, examined=0, live=0))
+    r = im.RRR(off=torch.from_numpy(off).cuda(), mem=torch.from_numpy(mem).cuda(),
+               total=int(off[-1]), examined=0, live=0, large_sets=0)
+    io, imem = im.build_incidence(n, r)
+    gio, gim = _segments_sorted(_np(io), _np(imem))
+    assert np.array_equal(gio, oio)
+    assert np.array_equal(gim, oim)
+
+
 def _pipeline(im, g, count, seed):
     G = _prep(im, g)
     r = im.sample_rrr(G, seed, 0, 0, count)
