@@ -31,11 +31,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def sampling_bytes(sets, total, examined, live):
+def sampling_bytes(sets, total, examined, live, run_length=True):
     """Algorithmic bytes of IC sampling: per set its offset (8 B); per member
-    its two in-CSR offsets read (8 B) and its id written (4 B); per examined
-    in-edge its threshold (4 B); per live in-edge its source id (4 B)."""
-    return 8 * sets + 12 * total + 4 * examined + 4 * live
+    its two in-CSR offsets read (8 B), its run-length table entry read (8 B,
+    when the graph has the table) and its id written (4 B); per examined
+    in-edge or run-length draw 4 B (the threshold; draws read nothing, so this
+    over-counts them); per live in-edge its source id (4 B)."""
+    return 8 * sets + (20 if run_length else 12) * total + 4 * examined + 4 * live
 
 
 def cpu_baseline(w, sample_sets):
