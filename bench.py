@@ -40,6 +40,40 @@ def sampling_bytes(sets, total, examined, live, run_length=True):
     return 8 * sets + (20 if run_length else 12) * total + 4 * examined + 4 * live
 
 
+# Measured HBM traffic per launch of a kernel: profiles/traffic_<workload>.md
+# holds lines "traffic <kernel> bytes_per_launch=<B> source_sha256=<H>", taken
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled against a plain copy.
+# A figure counts only while the kernel's sources hash to H.
+KERNEL_SOURCES = {
+    "k_sample_ic_small": ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],
+    "k_sample_big": ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2408_10982_amd", rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % workload)
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    want = kernel_source_hash(kernel)
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel:
+                kv = dict(x.split("=", 1) for x in parts[2:])
+                if kv.get("source_sha256") == want:
+                    return int(kv["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(w, sample_sets):
     import numpy as np  # noqa: F401
 
@@ -51,10 +85,11 @@ def cpu_baseline(w, sample_sets):
     io, im_ = O.incidence(g.n, r)
     O.greedy(g.n, sample_sets, io, im_, w.k, lazy=True)
     dt = time.perf_counter() - t0
+    what = ("all %d RRR sets of the workload" % w.theta if sample_sets == w.theta else
+            "RRR sets 0..%d of the %d-set workload" % (sample_sets - 1, w.theta))
     return {"value": sample_sets / dt, "unit": "RRR sets/s", "cores": 1, "kind": "oracle",
-            "sample": "RRR sets 0..%d of the %d-set workload (same graph, seed, stream), "
-                      "then covering subsets and greedy k=%d over them; %.1f s"
-                      % (sample_sets - 1, w.theta, w.k, dt)}
+            "sample": "%s (same graph, seed, stream), then covering subsets and greedy k=%d "
+                      "over them; %.1f s" % (what, w.k, dt)}
 
 
 def main():
@@ -67,7 +102,8 @@ def main():
     ap.add_argument("--queries", type=int, default=24)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--alpha", type=float, default=0.125)
-    ap.add_argument("--cpu-sample", type=int, default=40000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="RRR sets the CPU oracle times (0: the whole workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -168,8 +204,9 @@ def main():
     # 4-edge Philox4x32-10 groups: ~200 full-rate-equivalent integer ops each
     # (the 40 32x32 multiplies run at quarter rate) -> ~50 per examined edge
     alu_tops = 50.0 * ex_dom / (ms_dom * 1e-3) / 1e12
+    traffic = measured_traffic(w.name, dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "algorithmic_bytes": int(bytes_dom),
                 "kernel_ms": round(ms_dom, 4),
                 "alu_view": {"int_tops": round(alu_tops, 2), "peak_int_tops": INT_PEAK_TOPS,
@@ -206,8 +243,9 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on %d sets" % args.cpu_sample)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        n_cpu = args.cpu_sample if args.cpu_sample > 0 else w.theta
+        log("cpu baseline: oracle on %d sets" % n_cpu)
+        out["cpu_baseline"] = cpu_baseline(w, min(n_cpu, w.theta))
     print(json.dumps(out), flush=True)
 
 
