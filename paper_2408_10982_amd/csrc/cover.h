@@ -37,9 +37,14 @@ struct CoverArgs {
   int64_t* __restrict__ gains;
   int32_t* __restrict__ nsel;            // m
   int64_t* __restrict__ cover;           // m
+  // one-partition covers: a pick that covers at least this many samples
+  // rebuilds all counts instead of decrementing per member (0: never);
+  // set by launch_cover
+  int64_t recount_min;
 };
 
-// Enqueues the whole greedy (2k + 2 launches).  gains must be zeroed first.
+// Enqueues the whole greedy (2k + 2 launches, plus one per early pick of a
+// one-partition cover).  gains must be zeroed first.
 int launch_cover(CoverArgs& A, hipStream_t s);
 
 }  // namespace im

@@ -27,6 +27,17 @@ namespace im {
 constexpr int kGBlock = 1024;
 constexpr int kArgTile = kGBlock * 8;  // positions per workgroup in the argmax pass
 constexpr int kApplyBlock = 256;
+static_assert(kMaxParts <= kApplyBlock, "one apply thread per partition");
+constexpr int kRecountBlock = 256;
+constexpr int kRecountUnroll = 4;  // elements per lane per step of the recount
+constexpr int kRecountPicks = 8;   // picks that may rebuild the counts
+// Entries of S(v*) per wavefront chunk in the apply pass: a newly covered
+// sample is walked by the whole wavefront, so small chunks spread the walks of
+// a pick over many wavefronts.
+#ifndef IM_APPLY_ENTRIES
+#define IM_APPLY_ENTRIES 4
+#endif
+constexpr int kApplyEntries = IM_APPLY_ENTRIES;
 
 __device__ __forceinline__ int64_t part_lo(const CoverArgs& A, int p) {
   return A.pbase ? A.pbase[p] : 0;
@@ -71,7 +82,8 @@ __global__ __launch_bounds__(kGBlock) void k_cover_init(CoverArgs A) {
 // argmax key (count << 32 | ~v) of each partition it overlaps.
 __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
   __shared__ unsigned long long red[kGBlock / kWave];
-  if (*A.done) return;
+  const int32_t done = *A.done;  // uniform; checked only before the atomic, so the
+                                 // count loads do not wait for it
   const int64_t b0 = (int64_t)blockIdx.x * kArgTile;
   const int64_t b1 = min((int64_t)A.n, b0 + kArgTile);
   int p = 0;
@@ -91,13 +103,29 @@ __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
     if (lo >= b1) break;
     if (it >= part_k(A, p)) continue;  // this partition has made all its picks (uniform)
     unsigned long long best = 0ull;
-    for (int64_t pos = lo + threadIdx.x; pos < hi; pos += kGBlock) {
-      const int32_t v = A.order ? A.order[pos] : (int32_t)pos;
-      const unsigned long long key = argmax_key(A.cnt[pos], (uint32_t)v);
-      best = key > best ? key : best;
+    for (int64_t base = lo + threadIdx.x; base < hi; base += (int64_t)kArgTile) {
+      uint32_t c[kArgTile / kGBlock];
+      int32_t vv[kArgTile / kGBlock];
+#pragma unroll
+      for (int q = 0; q < kArgTile / kGBlock; ++q) {  // all loads first
+        const int64_t pos = base + (int64_t)q * kGBlock;
+        c[q] = 0u;
+        vv[q] = 0;
+        if (pos < hi) {
+          c[q] = A.cnt[pos];
+          vv[q] = A.order ? A.order[pos] : (int32_t)pos;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kArgTile / kGBlock; ++q) {
+        if (base + (int64_t)q * kGBlock < hi) {
+          const unsigned long long key = argmax_key(c[q], (uint32_t)vv[q]);
+          best = key > best ? key : best;
+        }
+      }
     }
     best = block_max_u64(best, red);
-    if (threadIdx.x == 0 && best) atomicMax(&A.gmax[(int64_t)it * A.m + p], best);
+    if (threadIdx.x == 0 && best && !done) atomicMax(&A.gmax[(int64_t)it * A.m + p], best);
   }
 }
 
@@ -105,25 +133,50 @@ __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
 // decrement the counts of the members of every newly covered sample.  Each
 // wavefront takes 64 consecutive entries of the picks' subsets; a newly
 // covered sample is then walked by the whole wavefront.
+// One of the first kRecountPicks picks whose gain reaches recount_min
+// (one-partition covers only): mark its samples covered and zero every count;
+// k_cover_recount, launched for exactly those picks, then rebuilds them.
+__device__ __forceinline__ bool recount_pick(const CoverArgs& A, int it) {
+  return A.recount_min > 0 && it < kRecountPicks &&
+         (int64_t)key_count(A.gmax[it]) >= A.recount_min;
+}
+
 __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it) {
   __shared__ unsigned long long pbest[kMaxParts];
   __shared__ int64_t pre[kMaxParts + 1];
-  if (*A.done) return;
+  __shared__ int64_t part_scan[kApplyBlock / kWave + 1];
   const int tid = threadIdx.x, lane = lane_id();
   const int m = A.m;
   const unsigned long long* gm = A.gmax + (int64_t)it * m;
-  if (tid == 0) {
-    int64_t acc = 0;
-    for (int p = 0; p < m; ++p) {
-      const unsigned long long b = it < part_k(A, p) ? gm[p] : 0ull;
-      pbest[p] = b;
-      pre[p] = acc;
-      if (key_count(b) > 0) {
-        const uint32_t v = key_vertex(b);
-        acc += A.inc_off[v + 1] - A.inc_off[v];
-      }
+  const int32_t done = *A.done;  // uniform; loaded together with the picks
+  // one thread per partition: its pick and the size of the pick's S(v)
+  // (m <= kMaxParts = kApplyBlock)
+  int64_t sz = 0;
+  if (tid < m) {
+    const unsigned long long b = it < part_k(A, tid) ? gm[tid] : 0ull;
+    pbest[tid] = b;
+    if (key_count(b) > 0) {
+      const uint32_t v = key_vertex(b);
+      sz = A.inc_off[v + 1] - A.inc_off[v];
     }
-    pre[m] = acc;
+  }
+  {  // pre = exclusive prefix of the sizes, pre[m] = total
+    const int w = tid / kWave;
+    const int64_t inc = wave_inclusive_scan(sz);
+    if (lane == kWave - 1) part_scan[w] = inc;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t acc = 0;
+      for (int j = 0; j < kApplyBlock / kWave; ++j) {
+        const int64_t x = part_scan[j];
+        part_scan[j] = acc;
+        acc += x;
+      }
+      part_scan[kApplyBlock / kWave] = acc;
+    }
+    __syncthreads();
+    if (tid < m) pre[tid] = part_scan[w] + inc - sz;
+    if (tid == 0) pre[m] = done ? 0 : part_scan[kApplyBlock / kWave];
   }
   __syncthreads();
   const int64_t tot = pre[m];
@@ -142,14 +195,18 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
     }
   }
   const int64_t gtid = (int64_t)blockIdx.x * kApplyBlock + tid;
-  const int64_t nchunks = (tot + kWave - 1) / kWave;
+  const bool decrement = !recount_pick(A, it);
+  if (!decrement)
+    for (int64_t pos = gtid; pos < A.n; pos += (int64_t)gridDim.x * kApplyBlock) A.cnt[pos] = 0u;
+  const int64_t nchunks = (tot + kApplyEntries - 1) / kApplyEntries;
   const int64_t wid = gtid / kWave, nw = (int64_t)gridDim.x * kApplyBlock / kWave;
   for (int64_t c = wid; c < nchunks; c += nw) {
-    const int64_t f = c * kWave + lane;
+    const int64_t f = c * kApplyEntries + lane;
     int p = 0;
     int32_t smp = -1;
     bool fresh = false;
-    if (f < tot) {
+    int64_t ma = 0, mb = 0;  // the sample's member range, loaded with its flag
+    if (lane < kApplyEntries && f < tot) {
       int lo = 0, hi = m - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -164,26 +221,118 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
       // flag index: a global sample position when each partition owns its
       // own samples, else one flag array per partition over all samples
       const int64_t fi = A.sbase ? A.sbase[p] + smp : (int64_t)p * A.count + smp;
-      if (!A.covered[fi]) {  // each sample occurs once in S(v), so no race
+      const int64_t gs = A.sbase ? A.sbase[p] + smp : (int64_t)smp;
+      const uint8_t was = A.covered[fi];
+      if (decrement) {
+        ma = A.off[gs];
+        mb = A.off[gs + 1];
+      }
+      if (!was) {  // each sample occurs once in S(v), so no race
         A.covered[fi] = 1;
         fresh = true;
       }
     }
-    unsigned long long todo = __ballot(fresh);
+    unsigned long long todo = decrement ? __ballot(fresh) : 0ull;
     while (todo) {
       const int src = __ffsll(todo) - 1;
       todo &= todo - 1;
-      const int32_t s_smp = __shfl(smp, src, kWave);
       const int s_p = __shfl(p, src, kWave);
       const int64_t lo_p = part_lo(A, s_p), hi_p = part_hi(A, s_p);
-      const int64_t gs = A.sbase ? A.sbase[s_p] + s_smp : (int64_t)s_smp;
-      const int64_t a = A.off[gs], b = A.off[gs + 1];
+      const int64_t a = __shfl(ma, src, kWave), b = __shfl(mb, src, kWave);
       for (int64_t t = a + lane; t < b; t += kWave) {
         const int32_t u = A.mem[t];
         const int64_t pos = A.local_ids ? lo_p + u : (A.pos_of ? A.pos_of[u] : u);
         if (pos >= lo_p && pos < hi_p) atomicSub(&A.cnt[pos], 1u);
       }
     }
+  }
+}
+
+// One-partition cover after its first pick: cnt[v] = |S(v) minus covered| for
+// every v, without per-member atomics.  Each wavefront takes an equal slice of
+// the covering-subset elements and walks it 64 vertices at a time (their
+// element ranges, clipped to the slice, are consecutive: coalesced loads,
+// owner by binary search over 64 prefix sums), counting uncovered samples per
+// vertex in LDS.  A vertex whose S(v) lies inside the slice is stored; a
+// vertex cut by a slice boundary is added atomically (counts were zeroed).
+__global__ __launch_bounds__(kRecountBlock) void k_cover_recount(CoverArgs A, int it) {
+  __shared__ int64_t wpre[kRecountBlock / kWave][kWave];
+  __shared__ uint32_t wcnt[kRecountBlock / kWave][kWave];
+  if (*A.done || !recount_pick(A, it)) return;
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  const int64_t n = A.n;
+  const int64_t E = A.inc_off[n];
+  const int64_t nwaves = (int64_t)gridDim.x * (kRecountBlock / kWave);
+  const int64_t per = (E + nwaves - 1) / nwaves;
+  const int64_t e0 = min(E, ((int64_t)blockIdx.x * (kRecountBlock / kWave) + wv) * per);
+  const int64_t e1 = min(E, e0 + per);
+  if (e0 >= e1) return;  // this wavefront only; the kernel has no block barrier
+  int64_t lo = 0, hi = n - 1;  // last vertex with inc_off[v] <= e0
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (A.inc_off[mid] <= e0)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  int64_t vg = lo;
+  for (;;) {
+    const int64_t v = vg + lane;
+    int64_t a = E, b = E;
+    if (v < n) {
+      a = A.inc_off[v];
+      b = A.inc_off[v + 1];
+    }
+    const int64_t ca = max(a, e0), cb = min(b, e1);
+    const int64_t sz = cb > ca ? cb - ca : 0;
+    const int64_t incl = wave_inclusive_scan(sz);
+    const int64_t all = __shfl(incl, kWave - 1, kWave);
+    const int64_t first = __shfl(ca, 0, kWave);
+    wpre[wv][lane] = incl;
+    wcnt[wv][lane] = 0u;
+    wave_sync();
+    // kRecountUnroll elements per lane per step, in three phases so that each
+    // phase's loads are in flight together
+    for (int64_t x0 = lane; x0 < all; x0 += kWave * kRecountUnroll) {
+      int own[kRecountUnroll];
+      int32_t smp[kRecountUnroll];
+      uint8_t cov[kRecountUnroll];
+#pragma unroll
+      for (int q = 0; q < kRecountUnroll; ++q) {
+        const int64_t x = x0 + q * kWave;
+        own[q] = -1;
+        smp[q] = 0;
+        if (x < all) {
+          int o_lo = 0, o_hi = kWave - 1;  // first lane whose inclusive prefix exceeds x
+          while (o_lo < o_hi) {
+            const int mid = (o_lo + o_hi) >> 1;
+            if (wpre[wv][mid] > x)
+              o_hi = mid;
+            else
+              o_lo = mid + 1;
+          }
+          own[q] = o_lo;
+          smp[q] = A.inc_mem[first + x];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kRecountUnroll; ++q) cov[q] = own[q] >= 0 ? A.covered[smp[q]] : 1;
+#pragma unroll
+      for (int q = 0; q < kRecountUnroll; ++q)
+        if (!cov[q]) atomicAdd(&wcnt[wv][own[q]], 1u);
+    }
+    wave_sync();
+    if (v < n) {
+      const uint32_t c = wcnt[wv][lane];
+      if (a >= e0 && b <= e1)
+        A.cnt[v] = c;  // all of S(v) is in this slice
+      else if (c)
+        atomicAdd(&A.cnt[v], c);
+    }
+    const int64_t last_end = __shfl(b, kWave - 1, kWave);
+    wave_sync();
+    if (vg + kWave >= n || last_end >= e1) break;
+    vg += kWave;
   }
 }
 
@@ -269,10 +418,20 @@ int launch_cover(CoverArgs& A, hipStream_t s) {
   IM_HIP(hipGetLastError());
   const unsigned arg_blocks = (unsigned)std::max<int64_t>(((int64_t)A.n + kArgTile - 1) / kArgTile, 1);
   const unsigned apply_blocks = (unsigned)di.num_cus * 4;
+  // A plain one-partition cover rebuilds all counts after an early pick that
+  // covers at least count / 64 samples (a member decrement per device atomic
+  // costs more there than one pass over the covering subsets: at 2^20
+  // weighted-cascade sets the first pick's 12 M decrements take 0.74 ms, a
+  // recount 0.1 ms); the decision is taken on the device from the pick's gain.
+  const bool can_recount = A.m == 1 && !A.order && !A.pos_of && !A.sbase && !A.local_ids;
+  A.recount_min = can_recount ? std::max<int64_t>(1, A.count / 64) : 0;
   for (int it = 0; it < A.k; ++it) {
     k_cover_argmax<<<dim3(arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
     k_cover_apply<<<dim3(apply_blocks), dim3(kApplyBlock), 0, s>>>(A, it);
+    if (can_recount && it < kRecountPicks)
+      k_cover_recount<<<dim3((unsigned)di.num_cus * 8), dim3(kRecountBlock), 0, s>>>(A, it);
   }
+  A.recount_min = 0;
   k_cover_finish<<<dim3((unsigned)((A.m + 255) / 256)), dim3(256), 0, s>>>(A);
   IM_HIP(hipGetLastError());
   return IM_OK;

@@ -144,15 +144,21 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 // Tuning knobs (compile-time): groups per lane per iteration, and an
 // occupancy hint for the two IC kernels.
 // Measured on MI355X (R-MAT 2^20, IC weighted cascade, 2^20 sets): two groups
-// per lane beat four by 22%; with the fp64 log of the run-length walks, 6
-// waves per SIMD (80 VGPRs) beat 8 (64 VGPRs, spilling), 5 and 4.
+// per lane beat four by 22% on coin-drawn graphs (with run-length walks one and
+// two are even); with the fp64 log of the walks, the small-set kernel runs best
+// at 7 waves per SIMD (3.24 ms against 3.31 at 6 and 3.29 at 8) and the
+// large-set kernel at 8 (1.84 ms against 2.08 at 6).
 #ifndef IM_UNROLL
 #define IM_UNROLL 2
 #endif
 #ifndef IM_IC_WAVES_PER_EU
-#define IM_IC_WAVES_PER_EU 6
+#define IM_IC_WAVES_PER_EU 7
+#endif
+#ifndef IM_BIG_WAVES_PER_EU
+#define IM_BIG_WAVES_PER_EU 8
 #endif
 #define IM_IC_ATTR __attribute__((amdgpu_waves_per_eu(IM_IC_WAVES_PER_EU)))
+#define IM_BIG_ATTR __attribute__((amdgpu_waves_per_eu(IM_BIG_WAVES_PER_EU)))
 constexpr int kUnroll = IM_UNROLL;  // 4-edge groups per lane per iteration
 
 // Same-address atomics serialise at one coherence point, so work and arena
@@ -545,7 +551,7 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
 
 // One workgroup per large set: visited bitmap and queue in HBM (private to
 // the worker), members written in ascending order.
-__global__ __launch_bounds__(kBigBlock) IM_IC_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
+__global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
   __shared__ int32_t pre[kBigBlock];
   __shared__ int32_t gbase[kBigBlock];
   __shared__ int32_t ea[kBigBlock];
