@@ -38,8 +38,18 @@ constexpr int kSmallBlock = 256;            // 4 waves, each its own sample
 constexpr int kSmallH = 512;                // LDS hash slots per wave
 constexpr int kSmallCap = 256;              // members before handing off
 constexpr int kStage = 128;                 // staged live in-edges per wave
-constexpr int kBigBlock = 256;
-constexpr int kBigSortCap = 2048;           // large sets up to this size sort in LDS
+// Large sets: threads per workgroup (one set each) and workgroups per CU.
+// A large set's frontier averages a few dozen vertices per level, so one
+// wavefront per set with more sets in flight beats a wide workgroup: at 2^20
+// weighted-cascade sets, 64 threads with a 512-member LDS tier take 1.57 ms
+// against 2.18 ms for 256 threads with 1024 members.
+#ifndef IM_BIG_BLOCK
+#define IM_BIG_BLOCK 64
+#endif
+#ifndef IM_BIG_PER_CU
+#define IM_BIG_PER_CU 24
+#endif
+constexpr int kBigBlock = IM_BIG_BLOCK;
 constexpr uint32_t kMaxHandoff = 1u << 16;  // large sets that resume from a snapshot
 constexpr int kLtH = 2048;                  // per-lane HBM hash slots (LT)
 constexpr int kLtCap = 1024;                // per-lane walk length before handing off
@@ -513,54 +523,101 @@ __device__ __forceinline__ int64_t block_exclusive_scan64(int64_t x, int64_t* ld
   return r;
 }
 
-constexpr int kBigStage = 1024;  // staged live in-edges per workgroup
+// staged live in-edges per workgroup (at 256 threads, the LDS of 8 per CU fits)
+constexpr int kBigStage = kBigBlock >= 256 ? 960 : 4 * kBigBlock;
+// A large set is first grown with its visited set in LDS (open addressing,
+// kMedH slots) and its member list in LDS (kMedCap); a level that would pass
+// kMedCap members is redone with the worker's HBM bitmap and queue.
+#ifndef IM_MED_BITS
+#define IM_MED_BITS 10
+#endif
+constexpr int kMedBits = IM_MED_BITS;
+constexpr int kMedH = 1 << kMedBits;
+constexpr int kMedCap = kMedH / 2;
+static_assert(kMedCap >= kSmallCap, "a hand-off snapshot must fit the LDS tier");
 
-// Marks u visited in the worker's bitmap and queues it if it was new.
-__device__ __forceinline__ void big_insert(int32_t u, uint32_t* __restrict__ bm,
-                                           int32_t* __restrict__ queue, int32_t* s_tail) {
-  const uint32_t bit = 1u << (u & 31);
-  const uint32_t old = atomicOr(&bm[u >> 5], bit);
-  if (!(old & bit)) queue[atomicAdd(s_tail, 1)] = u;
+// The visited set and member list of the set a workgroup is growing.
+struct BigSet {
+  bool lds;             // LDS mode (block-uniform)
+  int32_t* mhash;       // LDS: kMedH slots
+  int32_t* mq;          // LDS: kMedCap members
+  uint32_t* bm;         // HBM: n-bit bitmap
+  int32_t* queue;       // HBM: n members
+  int32_t* s_tail;      // members so far
+  int32_t* s_over;      // LDS mode only: a member did not fit
+};
+
+// Adds u to the set if it is new.  In LDS mode the member count is checked
+// before a slot is claimed, so the hash holds at most kMedCap + kBigBlock - 1
+// keys and probing always ends at u or at a free slot.
+__device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
+  if (S.lds) {
+    uint32_t h = hash_slot(u, kMedBits);
+    for (;;) {
+      const int32_t cur = S.mhash[h];
+      if (cur == u) return;
+      if (cur == kEmpty) {
+        if (__atomic_load_n(S.s_tail, __ATOMIC_RELAXED) >= kMedCap) {
+          *S.s_over = 1;
+          return;
+        }
+        const int32_t old = atomicCAS(&S.mhash[h], kEmpty, u);
+        if (old == kEmpty) {
+          const int32_t pos = atomicAdd(S.s_tail, 1);
+          if (pos < kMedCap)
+            S.mq[pos] = u;
+          else
+            *S.s_over = 1;
+          return;
+        }
+        if (old == u) return;
+      }
+      h = (h + 1) & (kMedH - 1);
+    }
+  } else {
+    const uint32_t bit = 1u << (u & 31);
+    const uint32_t old = atomicOr(&S.bm[u >> 5], bit);
+    if (!(old & bit)) S.queue[atomicAdd(S.s_tail, 1)] = u;
+  }
 }
 
 // As in the small path: live in-edges are staged by index and their sources
 // loaded together; an edge that finds the stage full is handled at once.
 __device__ __forceinline__ void big_push(int32_t e, int32_t* stage, int32_t* s_nst,
-                                         const int32_t* __restrict__ in_src,
-                                         uint32_t* __restrict__ bm, int32_t* __restrict__ queue,
-                                         int32_t* s_tail) {
+                                         const int32_t* __restrict__ in_src, const BigSet& S) {
   const int32_t k = atomicAdd(s_nst, 1);
   if (k < kBigStage)
     stage[k] = e;
   else
-    big_insert(in_src[e], bm, queue, s_tail);
+    set_insert(S, in_src[e]);
 }
 
 // Every thread of the block must call.
 __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
-                                          const int32_t* __restrict__ in_src,
-                                          uint32_t* __restrict__ bm, int32_t* __restrict__ queue,
-                                          int32_t* s_tail) {
+                                          const int32_t* __restrict__ in_src, const BigSet& S) {
   __syncthreads();
   const int32_t ns = min(*s_nst, kBigStage);
-  for (int32_t k = threadIdx.x; k < ns; k += kBigBlock) big_insert(in_src[stage[k]], bm, queue, s_tail);
+  for (int32_t k = threadIdx.x; k < ns; k += kBigBlock) set_insert(S, in_src[stage[k]]);
   __syncthreads();
   if (threadIdx.x == 0) *s_nst = 0;
   __syncthreads();
 }
 
-// One workgroup per large set: visited bitmap and queue in HBM (private to
-// the worker), members written in ascending order.
+// One workgroup per large set: visited set and members in LDS while they fit
+// (sorted in LDS), else the worker's private bitmap and queue in HBM (sorted
+// in LDS up to kMedH members, else read in order from the bitmap).
 __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
   __shared__ int32_t pre[kBigBlock];
   __shared__ int32_t gbase[kBigBlock];
   __shared__ int32_t ea[kBigBlock];
   __shared__ int32_t eb[kBigBlock];
   __shared__ int64_t scan_lds[kBigBlock / kWave + 1];
-  __shared__ int32_t sorted[kBigSortCap];
+  __shared__ int32_t mhash[kMedH];  // LDS-mode hash; sort buffer in HBM mode
+  __shared__ int32_t mq[kMedCap];
   __shared__ int32_t stage[kBigStage];
   __shared__ int32_t s_nst;
   __shared__ int32_t s_tail;
+  __shared__ int32_t s_over;
   __shared__ uint32_t s_item;
   __shared__ unsigned long long s_pos;
   uint32_t* bm = Bg.bitmaps + (size_t)blockIdx.x * Bg.nwords;
@@ -582,34 +639,43 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     const uint64_t seed = ((uint64_t)G.seed_hi << 32) | G.seed_lo;
     const int32_t root = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
     unsigned long long s_ex = 0, s_lv = 0;
+    BigSet S{T.model == IM_IC, mhash, mq, bm, queue, &s_tail, &s_over};
     if (T.model == IM_IC) {
       int32_t head = 0, tail = 1;
+      for (int j = t; j < kMedH; j += kBigBlock) mhash[j] = kEmpty;
+      if (t == 0) {
+        s_tail = 0;
+        s_over = 0;
+        s_nst = 0;
+      }
+      __syncthreads();
       if (item < kMaxHandoff) {  // resume from the small path's snapshot
         const Handoff& H = A.handoff[item];
         head = H.head;
-        tail = H.tail;
-        for (int j = t; j < tail; j += kBigBlock) {
-          const int32_t u = H.mem[j];
-          queue[j] = u;
-          atomicOr(&bm[u >> 5], 1u << (u & 31));
-        }
+        tail = H.tail;  // <= kSmallCap < kMedCap: the snapshot fits LDS mode
+        for (int j = t; j < tail; j += kBigBlock) set_insert(S, H.mem[j]);
         if (t == 0) {
-          s_tail = tail;
           s_ex = H.ex;
           s_lv = H.lv;
         }
       } else if (t == 0) {
-        bm[root >> 5] = 1u << (root & 31);
-        queue[0] = root;
-        s_tail = 1;
+        set_insert(S, root);
       }
-      if (t == 0) s_nst = 0;
+      __syncthreads();
+      if (S.lds) {  // the snapshot's members were distinct; keep its order
+        for (int j = t; j < tail; j += kBigBlock)
+          mq[j] = item < kMaxHandoff ? A.handoff[item].mem[j] : root;
+      }
       __syncthreads();
       while (head < tail) {
+        // level start: what a redo in HBM mode restarts from
+        const int32_t head0 = head, tail0 = tail;
+        const unsigned long long ex0 = s_ex, lv0 = s_lv;
+        const int32_t* Q = S.lds ? mq : queue;
         const int32_t nf = min(tail - head, kBigBlock);
         int32_t a = 0, b = 0, ng = 0;
         if (t < nf) {
-          const int32_t v = queue[head + t];
+          const int32_t v = Q[head + t];
           a = G.in_off[v];
           b = G.in_off[v + 1];
           const double sk = G.skip ? G.skip[v] : 0.0;
@@ -626,7 +692,7 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
               if (gap >= (double)(deg - 1 - pos)) break;
               pos += 1 + (int64_t)gap;
               ++s_lv;
-              big_push(a + (int32_t)pos, stage, &s_nst, G.in_src, bm, queue, &s_tail);
+              big_push(a + (int32_t)pos, stage, &s_nst, G.in_src, S);
             }
             a = b = 0;
           }
@@ -671,17 +737,36 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
                 const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
                 if (e >= e_a[u] && e < e_b[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
                   ++s_lv;
-                  big_push(e, stage, &s_nst, G.in_src, bm, queue, &s_tail);
+                  big_push(e, stage, &s_nst, G.in_src, S);
                 }
               }
             }
           }
           __syncthreads();
-          if (s_nst >= kBigStage / 2) big_flush(stage, &s_nst, G.in_src, bm, queue, &s_tail);
+          if (s_nst >= kBigStage / 2) big_flush(stage, &s_nst, G.in_src, S);
         }
-        big_flush(stage, &s_nst, G.in_src, bm, queue, &s_tail);
+        big_flush(stage, &s_nst, G.in_src, S);
         tail = s_tail;
+        const bool over = S.lds && s_over;
         __syncthreads();
+        if (over) {  // the level passed kMedCap members: redo it in HBM mode
+          for (int j = t; j < tail0; j += kBigBlock) {
+            const int32_t u = mq[j];
+            queue[j] = u;
+            atomicOr(&bm[u >> 5], 1u << (u & 31));
+          }
+          S.lds = false;
+          head = head0;
+          tail = tail0;
+          s_ex = ex0;
+          s_lv = lv0;
+          __syncthreads();
+          if (t == 0) {
+            s_tail = tail0;
+            s_over = 0;
+          }
+          __syncthreads();
+        }
       }
     } else if (t == 0) {  // LT: the chain is sequential; one thread walks it
       int32_t v = root, len = 0;
@@ -718,10 +803,14 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     __syncthreads();
     const unsigned long long pos = s_pos;
     const bool fits = pos + (unsigned long long)tail <= A.arena_cap;
-    if (tail <= kBigSortCap) {
+    if (S.lds || tail <= kMedH) {
+      // LDS mode: the members are in mq (tail <= kMedCap); HBM mode: copy them
+      // into the (now unused) hash array
+      int32_t* sorted = S.lds ? mq : mhash;
       int32_t P = 1;
       while (P < tail) P <<= 1;
-      for (int j = t; j < P; j += kBigBlock) sorted[j] = j < tail ? queue[j] : 0x7FFFFFFF;
+      for (int j = t; j < P; j += kBigBlock)
+        if (!S.lds || j >= tail) sorted[j] = j < tail ? queue[j] : 0x7FFFFFFF;
       __syncthreads();
       for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -761,7 +850,8 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
       }
     }
     __syncthreads();
-    for (int j = t; j < tail; j += kBigBlock) bm[queue[j] >> 5] = 0u;
+    if (!S.lds)
+      for (int j = t; j < tail; j += kBigBlock) bm[queue[j] >> 5] = 0u;
     if (t == 0) {
       A.start[il] = (int64_t)pos;
       A.len[il] = tail;
@@ -1128,12 +1218,12 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       const uint32_t nwords = (uint32_t)(((int64_t)max_n + 31) / 32);
       // workers each hold an n-bit bitmap and an n-entry queue
       const size_t per_worker = (size_t)nwords * 4 + (size_t)max_n * 4;
-      // up to 8 workers per CU, within a 16 GiB budget; the bitmaps are zero
+      // up to IM_BIG_PER_CU workers per CU, within a 32 GiB budget; the bitmaps are zero
       // between uses (each set clears its own bits), so only a new buffer
       // needs clearing
-      const uint32_t max_workers = (uint32_t)di.num_cus * 8;
+      const uint32_t max_workers = (uint32_t)di.num_cus * IM_BIG_PER_CU;
       uint32_t cap_workers = max_workers;
-      const size_t budget = (size_t)16 << 30;
+      const size_t budget = (size_t)32 << 30;
       while (cap_workers > 1 && (size_t)cap_workers * per_worker > budget) cap_workers >>= 1;
       const uint32_t workers = std::min<uint32_t>(nbig, cap_workers);
       void* bp = nullptr;
