@@ -38,18 +38,23 @@ constexpr int kSmallBlock = 256;            // 4 waves, each its own sample
 constexpr int kSmallH = 512;                // LDS hash slots per wave
 constexpr int kSmallCap = 256;              // members before handing off
 constexpr int kStage = 128;                 // staged live in-edges per wave
-// Large sets: threads per workgroup (one set each) and workgroups per CU.
-// A large set's frontier averages a few dozen vertices per level, so one
-// wavefront per set with more sets in flight beats a wide workgroup: at 2^20
-// weighted-cascade sets, 64 threads with a 512-member LDS tier take 1.57 ms
-// against 2.18 ms for 256 threads with 1024 members.
-#ifndef IM_BIG_BLOCK
-#define IM_BIG_BLOCK 64
-#endif
-#ifndef IM_BIG_PER_CU
-#define IM_BIG_PER_CU 24
-#endif
-constexpr int kBigBlock = IM_BIG_BLOCK;
+// Large sets: two shapes of the large-set kernel, chosen per launch.
+// A large set's frontier usually holds a few dozen vertices per level, so one
+// wavefront per set with many sets in flight hides more of each level's
+// dependent loads (2^20 weighted-cascade sets: 1.57 ms against 2.18 ms for
+// 256 threads); when most sets are handed off (supercritical cascades with
+// thousands of members) a 256-thread workgroup per set is used instead.
+template <int kBlockT, int kBitsT, int kPerCuT>
+struct BigCfg {
+  static constexpr int kBlock = kBlockT;             // threads per set
+  static constexpr int kStage = kBlockT >= 256 ? 960 : 4 * kBlockT;  // staged live edges
+  static constexpr int kBits = kBitsT;               // LDS tier: hash slots 2^kBits,
+  static constexpr int kH = 1 << kBitsT;             // members kH / 2
+  static constexpr int kCap = kH / 2;
+  static constexpr int kPerCu = kPerCuT;             // workers per CU
+};
+using BigNarrow = BigCfg<64, 10, 24>;
+using BigWide = BigCfg<256, 11, 8>;
 constexpr uint32_t kMaxHandoff = 1u << 16;  // large sets that resume from a snapshot
 constexpr int kLtH = 2048;                  // per-lane HBM hash slots (LT)
 constexpr int kLtCap = 1024;                // per-lane walk length before handing off
@@ -503,44 +508,39 @@ struct BigArgs {
   int32_t* __restrict__ queues;     // per worker, qcap entries
 };
 
+template <int kBlock>
 __device__ __forceinline__ int64_t block_exclusive_scan64(int64_t x, int64_t* lds,
                                                           int64_t* total) {
-  // lds: kBigBlock / kWave + 1 entries; every thread of the block must call
+  // lds: kBlock / kWave + 1 entries; every thread of the block must call
   const int t = threadIdx.x, l = lane_id(), w = t / kWave;
   int64_t inc = wave_inclusive_scan(x);
   if (l == kWave - 1) lds[w] = inc;
   __syncthreads();
   if (w == 0) {
-    int64_t v = l < kBigBlock / kWave ? lds[l] : 0;
+    int64_t v = l < kBlock / kWave ? lds[l] : 0;
     int64_t vi = wave_inclusive_scan(v);
-    if (l < kBigBlock / kWave) lds[l] = vi - v;
-    if (l == kWave - 1) lds[kBigBlock / kWave] = vi;
+    if (l < kBlock / kWave) lds[l] = vi - v;
+    if (l == kWave - 1) lds[kBlock / kWave] = vi;
   }
   __syncthreads();
   int64_t r = lds[w] + inc - x;
-  *total = lds[kBigBlock / kWave];
+  *total = lds[kBlock / kWave];
   __syncthreads();
   return r;
 }
 
-// staged live in-edges per workgroup (at 256 threads, the LDS of 8 per CU fits)
-constexpr int kBigStage = kBigBlock >= 256 ? 960 : 4 * kBigBlock;
+
 // A large set is first grown with its visited set in LDS (open addressing,
-// kMedH slots) and its member list in LDS (kMedCap); a level that would pass
-// kMedCap members is redone with the worker's HBM bitmap and queue.
-#ifndef IM_MED_BITS
-#define IM_MED_BITS 10
-#endif
-constexpr int kMedBits = IM_MED_BITS;
-constexpr int kMedH = 1 << kMedBits;
-constexpr int kMedCap = kMedH / 2;
-static_assert(kMedCap >= kSmallCap, "a hand-off snapshot must fit the LDS tier");
+// kH slots) and its member list in LDS (kCap); a level that would pass kCap
+// members is redone with the worker's HBM bitmap and queue.
+static_assert(BigNarrow::kCap >= kSmallCap && BigWide::kCap >= kSmallCap,
+              "a hand-off snapshot must fit the LDS tier");
 
 // The visited set and member list of the set a workgroup is growing.
 struct BigSet {
   bool lds;             // LDS mode (block-uniform)
-  int32_t* mhash;       // LDS: kMedH slots
-  int32_t* mq;          // LDS: kMedCap members
+  int32_t* mhash;       // LDS: kH slots
+  int32_t* mq;          // LDS: kCap members
   uint32_t* bm;         // HBM: n-bit bitmap
   int32_t* queue;       // HBM: n members
   int32_t* s_tail;      // members so far
@@ -548,23 +548,24 @@ struct BigSet {
 };
 
 // Adds u to the set if it is new.  In LDS mode the member count is checked
-// before a slot is claimed, so the hash holds at most kMedCap + kBigBlock - 1
+// before a slot is claimed, so the hash holds at most C::kCap + kBlock - 1
 // keys and probing always ends at u or at a free slot.
+template <class C>
 __device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
   if (S.lds) {
-    uint32_t h = hash_slot(u, kMedBits);
+    uint32_t h = hash_slot(u, C::kBits);
     for (;;) {
       const int32_t cur = S.mhash[h];
       if (cur == u) return;
       if (cur == kEmpty) {
-        if (__atomic_load_n(S.s_tail, __ATOMIC_RELAXED) >= kMedCap) {
+        if (__atomic_load_n(S.s_tail, __ATOMIC_RELAXED) >= C::kCap) {
           *S.s_over = 1;
           return;
         }
         const int32_t old = atomicCAS(&S.mhash[h], kEmpty, u);
         if (old == kEmpty) {
           const int32_t pos = atomicAdd(S.s_tail, 1);
-          if (pos < kMedCap)
+          if (pos < C::kCap)
             S.mq[pos] = u;
           else
             *S.s_over = 1;
@@ -572,7 +573,7 @@ __device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
         }
         if (old == u) return;
       }
-      h = (h + 1) & (kMedH - 1);
+      h = (h + 1) & (C::kH - 1);
     }
   } else {
     const uint32_t bit = 1u << (u & 31);
@@ -583,21 +584,23 @@ __device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
 
 // As in the small path: live in-edges are staged by index and their sources
 // loaded together; an edge that finds the stage full is handled at once.
+template <class C>
 __device__ __forceinline__ void big_push(int32_t e, int32_t* stage, int32_t* s_nst,
                                          const int32_t* __restrict__ in_src, const BigSet& S) {
   const int32_t k = atomicAdd(s_nst, 1);
-  if (k < kBigStage)
+  if (k < C::kStage)
     stage[k] = e;
   else
-    set_insert(S, in_src[e]);
+    set_insert<C>(S, in_src[e]);
 }
 
 // Every thread of the block must call.
+template <class C>
 __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
                                           const int32_t* __restrict__ in_src, const BigSet& S) {
   __syncthreads();
-  const int32_t ns = min(*s_nst, kBigStage);
-  for (int32_t k = threadIdx.x; k < ns; k += kBigBlock) set_insert(S, in_src[stage[k]]);
+  const int32_t ns = min(*s_nst, C::kStage);
+  for (int32_t k = threadIdx.x; k < ns; k += C::kBlock) set_insert<C>(S, in_src[stage[k]]);
   __syncthreads();
   if (threadIdx.x == 0) *s_nst = 0;
   __syncthreads();
@@ -605,16 +608,17 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
 
 // One workgroup per large set: visited set and members in LDS while they fit
 // (sorted in LDS), else the worker's private bitmap and queue in HBM (sorted
-// in LDS up to kMedH members, else read in order from the bitmap).
-__global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
-  __shared__ int32_t pre[kBigBlock];
-  __shared__ int32_t gbase[kBigBlock];
-  __shared__ int32_t ea[kBigBlock];
-  __shared__ int32_t eb[kBigBlock];
-  __shared__ int64_t scan_lds[kBigBlock / kWave + 1];
-  __shared__ int32_t mhash[kMedH];  // LDS-mode hash; sort buffer in HBM mode
-  __shared__ int32_t mq[kMedCap];
-  __shared__ int32_t stage[kBigStage];
+// in LDS up to C::kH members, else read in order from the bitmap).
+template <class C>
+__global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
+  __shared__ int32_t pre[C::kBlock];
+  __shared__ int32_t gbase[C::kBlock];
+  __shared__ int32_t ea[C::kBlock];
+  __shared__ int32_t eb[C::kBlock];
+  __shared__ int64_t scan_lds[C::kBlock / kWave + 1];
+  __shared__ int32_t mhash[C::kH];  // LDS-mode hash; sort buffer in HBM mode
+  __shared__ int32_t mq[C::kCap];
+  __shared__ int32_t stage[C::kStage];
   __shared__ int32_t s_nst;
   __shared__ int32_t s_tail;
   __shared__ int32_t s_over;
@@ -642,7 +646,7 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     BigSet S{T.model == IM_IC, mhash, mq, bm, queue, &s_tail, &s_over};
     if (T.model == IM_IC) {
       int32_t head = 0, tail = 1;
-      for (int j = t; j < kMedH; j += kBigBlock) mhash[j] = kEmpty;
+      for (int j = t; j < C::kH; j += C::kBlock) mhash[j] = kEmpty;
       if (t == 0) {
         s_tail = 0;
         s_over = 0;
@@ -652,18 +656,18 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
       if (item < kMaxHandoff) {  // resume from the small path's snapshot
         const Handoff& H = A.handoff[item];
         head = H.head;
-        tail = H.tail;  // <= kSmallCap < kMedCap: the snapshot fits LDS mode
-        for (int j = t; j < tail; j += kBigBlock) set_insert(S, H.mem[j]);
+        tail = H.tail;  // <= kSmallCap < C::kCap: the snapshot fits LDS mode
+        for (int j = t; j < tail; j += C::kBlock) set_insert<C>(S, H.mem[j]);
         if (t == 0) {
           s_ex = H.ex;
           s_lv = H.lv;
         }
       } else if (t == 0) {
-        set_insert(S, root);
+        set_insert<C>(S, root);
       }
       __syncthreads();
       if (S.lds) {  // the snapshot's members were distinct; keep its order
-        for (int j = t; j < tail; j += kBigBlock)
+        for (int j = t; j < tail; j += C::kBlock)
           mq[j] = item < kMaxHandoff ? A.handoff[item].mem[j] : root;
       }
       __syncthreads();
@@ -672,7 +676,7 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         const int32_t head0 = head, tail0 = tail;
         const unsigned long long ex0 = s_ex, lv0 = s_lv;
         const int32_t* Q = S.lds ? mq : queue;
-        const int32_t nf = min(tail - head, kBigBlock);
+        const int32_t nf = min(tail - head, C::kBlock);
         int32_t a = 0, b = 0, ng = 0;
         if (t < nf) {
           const int32_t v = Q[head + t];
@@ -692,13 +696,13 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
               if (gap >= (double)(deg - 1 - pos)) break;
               pos += 1 + (int64_t)gap;
               ++s_lv;
-              big_push(a + (int32_t)pos, stage, &s_nst, G.in_src, S);
+              big_push<C>(a + (int32_t)pos, stage, &s_nst, G.in_src, S);
             }
             a = b = 0;
           }
         }
         int64_t tot64;
-        const int32_t ex = (int32_t)block_exclusive_scan64(ng, scan_lds, &tot64);
+        const int32_t ex = (int32_t)block_exclusive_scan64<C::kBlock>(ng, scan_lds, &tot64);
         const int32_t total = (int32_t)tot64;
         pre[t] = ex + ng;
         gbase[t] = (a >> 2) - ex;
@@ -706,19 +710,19 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         eb[t] = b;
         head += nf;
         __syncthreads();
-        for (int32_t base = 0; base < total; base += kBigBlock * kUnroll) {
-          const int o_b = owner_of<kBigBlock>(pre, base);
-          const bool uni = pre[o_b] >= min(total, base + kBigBlock * kUnroll);
+        for (int32_t base = 0; base < total; base += C::kBlock * kUnroll) {
+          const int o_b = owner_of<C::kBlock>(pre, base);
+          const bool uni = pre[o_b] >= min(total, base + C::kBlock * kUnroll);
           uint4 q[kUnroll];
           uint32_t g[kUnroll];
           int32_t e_a[kUnroll], e_b[kUnroll];
 #pragma unroll
           for (int u = 0; u < kUnroll; ++u) {
-            const int32_t gi = base + u * kBigBlock + t;
+            const int32_t gi = base + u * C::kBlock + t;
             e_a[u] = e_b[u] = 0;
             g[u] = 0;
             if (gi < total) {
-              const int o = uni ? o_b : owner_of<kBigBlock>(pre, gi);
+              const int o = uni ? o_b : owner_of<C::kBlock>(pre, gi);
               g[u] = (uint32_t)(gbase[o] + gi);
               e_a[u] = ea[o];
               e_b[u] = eb[o];
@@ -737,20 +741,20 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
                 const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
                 if (e >= e_a[u] && e < e_b[u] && (qw == 0xFFFFFFFFu || rw < qw)) {
                   ++s_lv;
-                  big_push(e, stage, &s_nst, G.in_src, S);
+                  big_push<C>(e, stage, &s_nst, G.in_src, S);
                 }
               }
             }
           }
           __syncthreads();
-          if (s_nst >= kBigStage / 2) big_flush(stage, &s_nst, G.in_src, S);
+          if (s_nst >= C::kStage / 2) big_flush<C>(stage, &s_nst, G.in_src, S);
         }
-        big_flush(stage, &s_nst, G.in_src, S);
+        big_flush<C>(stage, &s_nst, G.in_src, S);
         tail = s_tail;
         const bool over = S.lds && s_over;
         __syncthreads();
-        if (over) {  // the level passed kMedCap members: redo it in HBM mode
-          for (int j = t; j < tail0; j += kBigBlock) {
+        if (over) {  // the level passed C::kCap members: redo it in HBM mode
+          for (int j = t; j < tail0; j += C::kBlock) {
             const int32_t u = mq[j];
             queue[j] = u;
             atomicOr(&bm[u >> 5], 1u << (u & 31));
@@ -803,18 +807,18 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     __syncthreads();
     const unsigned long long pos = s_pos;
     const bool fits = pos + (unsigned long long)tail <= A.arena_cap;
-    if (S.lds || tail <= kMedH) {
-      // LDS mode: the members are in mq (tail <= kMedCap); HBM mode: copy them
+    if (S.lds || tail <= C::kH) {
+      // LDS mode: the members are in mq (tail <= C::kCap); HBM mode: copy them
       // into the (now unused) hash array
       int32_t* sorted = S.lds ? mq : mhash;
       int32_t P = 1;
       while (P < tail) P <<= 1;
-      for (int j = t; j < P; j += kBigBlock)
+      for (int j = t; j < P; j += C::kBlock)
         if (!S.lds || j >= tail) sorted[j] = j < tail ? queue[j] : 0x7FFFFFFF;
       __syncthreads();
       for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-          for (int u = t; u < (P >> 1); u += kBigBlock) {
+          for (int u = t; u < (P >> 1); u += C::kBlock) {
             const int i1 = ((u & ~(j - 1)) << 1) | (u & (j - 1));
             const int i2 = i1 | j;
             const bool asc = (i1 & k) == 0;
@@ -828,16 +832,16 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         }
       }
       if (fits)
-        for (int j = t; j < tail; j += kBigBlock) A.arena[pos + j] = sorted[j];
+        for (int j = t; j < tail; j += C::kBlock) A.arena[pos + j] = sorted[j];
     } else {
       // members in ascending order straight from the bitmap
-      const uint32_t per = (Bg.nwords + kBigBlock - 1) / kBigBlock;
+      const uint32_t per = (Bg.nwords + C::kBlock - 1) / C::kBlock;
       const uint32_t w0 = min((uint32_t)t * per, Bg.nwords);
       const uint32_t w1 = min(w0 + per, Bg.nwords);
       int64_t cnt = 0;
       for (uint32_t w = w0; w < w1; ++w) cnt += __popc(bm[w]);
       int64_t tot;
-      int64_t o = block_exclusive_scan64(cnt, scan_lds, &tot);
+      int64_t o = block_exclusive_scan64<C::kBlock>(cnt, scan_lds, &tot);
       if (fits) {
         for (uint32_t w = w0; w < w1; ++w) {
           uint32_t x = bm[w];
@@ -851,7 +855,7 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     }
     __syncthreads();
     if (!S.lds)
-      for (int j = t; j < tail; j += kBigBlock) bm[queue[j] >> 5] = 0u;
+      for (int j = t; j < tail; j += C::kBlock) bm[queue[j] >> 5] = 0u;
     if (t == 0) {
       A.start[il] = (int64_t)pos;
       A.len[il] = tail;
@@ -862,11 +866,11 @@ __global__ __launch_bounds__(kBigBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     __syncthreads();
   }
   int64_t tot;
-  (void)block_exclusive_scan64((int64_t)t_ex, scan_lds, &tot);
+  (void)block_exclusive_scan64<C::kBlock>((int64_t)t_ex, scan_lds, &tot);
   if (t == 0 && tot) atomicAdd(&A.ctr[6], (unsigned long long)tot);
-  (void)block_exclusive_scan64((int64_t)t_lv, scan_lds, &tot);
+  (void)block_exclusive_scan64<C::kBlock>((int64_t)t_lv, scan_lds, &tot);
   if (t == 0 && tot) atomicAdd(&A.ctr[7], (unsigned long long)tot);
-  (void)block_exclusive_scan64((int64_t)t_tot, scan_lds, &tot);
+  (void)block_exclusive_scan64<C::kBlock>((int64_t)t_tot, scan_lds, &tot);
   if (t == 0 && tot) {
     atomicAdd(&A.ctr[8], (unsigned long long)tot);
     atomicAdd(&A.ctr[10], (unsigned long long)tot);
@@ -1218,10 +1222,13 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       const uint32_t nwords = (uint32_t)(((int64_t)max_n + 31) / 32);
       // workers each hold an n-bit bitmap and an n-entry queue
       const size_t per_worker = (size_t)nwords * 4 + (size_t)max_n * 4;
-      // up to IM_BIG_PER_CU workers per CU, within a 32 GiB budget; the bitmaps are zero
+      // up to kPerCu workers per CU, within a 32 GiB budget; the bitmaps are zero
       // between uses (each set clears its own bits), so only a new buffer
       // needs clearing
-      const uint32_t max_workers = (uint32_t)di.num_cus * IM_BIG_PER_CU;
+      // one wavefront per set unless most sets were handed off
+      const bool narrow = (uint64_t)nbig * 8 <= (uint64_t)cnt;
+      const uint32_t max_workers =
+          (uint32_t)di.num_cus * (narrow ? BigNarrow::kPerCu : BigWide::kPerCu);
       uint32_t cap_workers = max_workers;
       const size_t budget = (size_t)32 << 30;
       while (cap_workers > 1 && (size_t)cap_workers * per_worker > budget) cap_workers >>= 1;
@@ -1249,7 +1256,10 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       if (!same_layout)
         IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)cap_workers * nwords * 4, s));
       if (timed) IM_HIP(hipEventRecord(ev[2], s));
-      k_sample_big<<<dim3(workers), dim3(kBigBlock), 0, s>>>(A, Bg);
+      if (narrow)
+        k_sample_big<BigNarrow><<<dim3(workers), dim3(BigNarrow::kBlock), 0, s>>>(A, Bg);
+      else
+        k_sample_big<BigWide><<<dim3(workers), dim3(BigWide::kBlock), 0, s>>>(A, Bg);
       IM_HIP(hipGetLastError());
       if (timed) IM_HIP(hipEventRecord(ev[3], s));
       IM_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, s));
