@@ -98,6 +98,18 @@ __device__ __forceinline__ double skip_uniform(uint32_t seed_lo, uint32_t seed_h
   return u * 1.1102230246251565e-16;  // 2^-53
 }
 
+// The same uniform, for draws j = 0, 1, 2, ... in order: draws 2t and 2t+1
+// come from one Philox block, which is computed at even j into *blk.
+__device__ __forceinline__ double skip_uniform_seq(uint32_t seed_lo, uint32_t seed_hi,
+                                                   uint32_t stream, uint32_t i, uint32_t v,
+                                                   uint32_t j, uint4* blk) {
+  if (!(j & 1u))
+    *blk = philox4x32_10(make_uint4(v, i, 0x80000000u | (j >> 1), stream), seed_lo, seed_hi);
+  const uint32_t hi = ((j & 1u) ? blk->z : blk->x) >> 11, lo = (j & 1u) ? blk->w : blk->y;
+  const double u = (double)(((unsigned long long)hi << 32) | lo) + 1.0;
+  return u * 1.1102230246251565e-16;  // 2^-53
+}
+
 // floor(r * n / 2^32): maps a uniform word onto [0, n).
 __device__ __forceinline__ uint32_t scale_draw(uint32_t r, uint32_t n) {
   return (uint32_t)(((uint64_t)r * (uint64_t)n) >> 32);

@@ -160,14 +160,14 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 // occupancy hint for the two IC kernels.
 // Measured on MI355X (R-MAT 2^20, IC weighted cascade, 2^20 sets): two groups
 // per lane beat four by 22% on coin-drawn graphs (with run-length walks one and
-// two are even); with the fp64 log of the walks, the small-set kernel runs best
-// at 7 waves per SIMD (3.24 ms against 3.31 at 6 and 3.29 at 8) and the
-// large-set kernel at 8 (1.84 ms against 2.08 at 6).
+// two are even); with the lane pass and the fp64 log of the walks, the
+// small-set kernel runs best at 6 waves per SIMD (2.76 ms against 2.86 at 7
+// and 2.89 at 5).
 #ifndef IM_UNROLL
 #define IM_UNROLL 2
 #endif
 #ifndef IM_IC_WAVES_PER_EU
-#define IM_IC_WAVES_PER_EU 7
+#define IM_IC_WAVES_PER_EU 6
 #endif
 #ifndef IM_BIG_WAVES_PER_EU
 #define IM_BIG_WAVES_PER_EU 8
@@ -177,9 +177,8 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 constexpr int kUnroll = IM_UNROLL;  // 4-edge groups per lane per iteration
 
 // Same-address atomics serialise at one coherence point, so work and arena
-// space are claimed in batches: kGrab sample ids (kLtGrab for LT) and kChunk
-// arena entries per atomic.
-constexpr uint32_t kGrab = 16;
+// space are claimed in batches: 64 sample ids per IC wavefront (kLtGrab for
+// LT) and kChunk arena entries per atomic.
 constexpr uint32_t kLtGrab = 256;
 constexpr unsigned long long kChunk = 1024;
 
@@ -276,28 +275,154 @@ __device__ __forceinline__ void stage_flush(WaveLds& L, const int32_t* __restric
   wave_sync();
 }
 
+// Lane pass: one lane per sample, for sets of at most kTiny members (most
+// sets: 86% of the weighted-cascade sets at R-MAT scale 20).  The lane keeps
+// its members in a list of kTiny entries and expands them one by one with the
+// same draws as the wavefront path; a set that grows past kTiny members, or
+// reaches a coin-drawn vertex with more than kTinyDeg in-edges, is left to the
+// wavefront path, which starts it over.
+constexpr int kTiny = kSmallH / kWave;  // 8: the lists of a wave fill its hash area
+constexpr int32_t kTinyDeg = 16;
+
+__device__ __forceinline__ bool tiny_add(int32_t* list, int32_t* n, int32_t u) {
+  for (int32_t k = 0; k < *n; ++k)
+    if (list[k] == u) return true;
+  if (*n == kTiny) return false;
+  list[(*n)++] = u;
+  return true;
+}
+
+// Grows the set of sample i from root; true if it completed within kTiny
+// members (then list[0, *cnt) holds them and *ex, *lv its counters).
+#ifdef IM_TINY_NOINLINE
+__attribute__((noinline))
+#endif
+__device__ bool tiny_set(const GView& G, uint32_t i, int32_t root, int32_t* list, int32_t* cnt,
+                         uint32_t* ex, uint32_t* lv) {
+  list[0] = root;
+  int32_t n = 1, h = 0;
+  uint32_t e_ = 0, l_ = 0;
+  while (h < n) {
+    const int32_t v = list[h++];
+    const int32_t a = G.in_off[v], b = G.in_off[v + 1];
+    const double sk = G.skip ? G.skip[v] : 0.0;
+    if (sk != 0.0) {  // run-length vertex
+      const int64_t deg = b - a;
+      int64_t pos = -1;
+      uint4 blk;
+      for (uint32_t j = 0;; ++j) {
+        ++e_;
+        const double gap = floor(
+            im_log(skip_uniform_seq(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j, &blk)) * sk);
+        if (gap >= (double)(deg - 1 - pos)) break;
+        pos += 1 + (int64_t)gap;
+        ++l_;
+        if (!tiny_add(list, &n, G.in_src[a + pos])) return false;
+      }
+    } else if (a < b) {  // coins, 4-edge groups as in the wavefront path
+      if (b - a > kTinyDeg) return false;
+      e_ += (uint32_t)(b - a);
+      for (int32_t g = a >> 2; g <= (b - 1) >> 2; ++g) {
+        const uint4 q = reinterpret_cast<const uint4*>(G.thr)[g];
+        const uint4 r =
+            philox4x32_10(make_uint4((uint32_t)g, i, kTagEdge, G.stream), G.seed_lo, G.seed_hi);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int32_t e = (g << 2) + w;
+          const uint32_t qw = pick_word(q, w), rw = pick_word(r, w);
+          if (e >= a && e < b && (qw == 0xFFFFFFFFu || rw < qw)) {
+            ++l_;
+            if (!tiny_add(list, &n, G.in_src[e])) return false;
+          }
+        }
+      }
+    }
+  }
+  // ascending, as every set is stored
+  for (int32_t k = 1; k < n; ++k) {
+    const int32_t x = list[k];
+    int32_t j = k - 1;
+    while (j >= 0 && list[j] > x) {
+      list[j + 1] = list[j];
+      --j;
+    }
+    list[j + 1] = x;
+  }
+  *cnt = n;
+  *ex = e_;
+  *lv = l_;
+  return true;
+}
+
 __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(SampleArgs A) {
   __shared__ WaveLds lds_all[kSmallBlock / kWave];
   WaveLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
   unsigned long long w_ex = 0, w_lv = 0;  // per-lane sums of finished sets
   unsigned long long w_tot = 0;            // members written by this wave
-  unsigned long long next = 0, end = 0;    // claimed sample ids
-  unsigned long long cpos = 0, cend = 0;   // reserved arena chunk
+  unsigned long long batch = 0;           // first of the 64 claimed work items
+  unsigned long long defer = 0;           // items of the batch left to the wavefront path
+  unsigned long long cpos = 0, cend = 0;  // reserved arena chunk
   for (;;) {
     wave_sync();
-    if (next == end) {
+    if (defer == 0) {
+      // claim 64 work items and run the lane pass over them (see tiny_set)
       unsigned long long b = 0;
-      if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kGrab);
+      if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kWave);
       b = first_lane_u64(shfl_u64(b, 0));
       if (b >= A.count) break;
-      next = b;
-      end = min(b + kGrab, (unsigned long long)A.count);
+      batch = b;
+      const unsigned long long my = b + (unsigned long long)lane;
+      const bool have = my < A.count;
+      int32_t* list = L.hash + lane * kTiny;  // the hash is cleared per set below
+      bool done = false;
+      int32_t n = 0;
+      uint32_t t_ex = 0, t_lv = 0;
+      int64_t il = 0;
+      if (have) {
+        int tk;
+        uint32_t i;
+        locate_work(A, my, &tk, &i, &il);
+        const GView G = view_of(A.tasks[tk]);
+        const int32_t root = (int32_t)scale_draw(
+            draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream, 0u, i), G.n);
+        done = tiny_set(G, i, root, list, &n, &t_ex, &t_lv);
+      }
+      const int32_t sz = done ? n : 0;
+      const int32_t incl = wave_inclusive_scan(sz);
+      const unsigned long long tot = (unsigned long long)__shfl(incl, kWave - 1, kWave);
+      if (tot > 0) {
+        if (cpos + tot > cend) {
+          const unsigned long long want = max(tot, kChunk);
+          unsigned long long c = 0;
+          if (lane == 0) c = atomicAdd(&A.ctr[1], want);
+          cpos = first_lane_u64(shfl_u64(c, 0));
+          cend = cpos + want;
+        }
+        const unsigned long long pos = cpos;
+        cpos += tot;
+        w_tot += tot;
+        if (done) {
+          const unsigned long long mine = pos + (unsigned long long)(incl - sz);
+          if (pos + tot <= A.arena_cap)
+            for (int32_t k = 0; k < n; ++k) A.arena[mine + k] = list[k];
+          A.start[il] = (int64_t)mine;
+          A.len[il] = n;
+          w_ex += t_ex;
+          w_lv += t_lv;
+        }
+      }
+      defer = __ballot(have && !done);
+      continue;
     }
+    // the wavefront path, one item left by the lane pass at a time
+    const int dl = __ffsll(defer) - 1;
+    defer &= defer - 1;
+    const unsigned long long item = batch + (unsigned long long)dl;
     int tk;
     uint32_t i;
     int64_t il;
-    locate_work(A, next++, &tk, &i, &il);
+    locate_work(A, item, &tk, &i, &il);
     const GView G = view_of(A.tasks[tk]);
     const int32_t root =
         (int32_t)scale_draw(draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream,
@@ -339,10 +464,12 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
       if (sk != 0.0) {
         const int64_t deg = b - a;
         int64_t pos = -1;
+        uint4 blk;
         for (uint32_t j = 0;; ++j) {
           ++s_ex;
-          const double gap =
-              floor(im_log(skip_uniform(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j)) * sk);
+          const double gap = floor(
+              im_log(skip_uniform_seq(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j, &blk)) *
+              sk);
           if (gap >= (double)(deg - 1 - pos)) break;
           pos += 1 + (int64_t)gap;
           ++s_lv;
@@ -689,10 +816,12 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
           } else {  // run-length vertex: walk its geometric gaps here
             const int64_t deg = b - a;
             int64_t pos = -1;
+            uint4 blk;
             for (uint32_t j = 0;; ++j) {
               ++s_ex;
-              const double gap = floor(
-                  im_log(skip_uniform(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j)) * sk);
+              const double gap = floor(im_log(skip_uniform_seq(G.seed_lo, G.seed_hi, G.stream, i,
+                                                               (uint32_t)v, j, &blk)) *
+                                       sk);
               if (gap >= (double)(deg - 1 - pos)) break;
               pos += 1 + (int64_t)gap;
               ++s_lv;
