@@ -160,14 +160,15 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 // occupancy hint for the two IC kernels.
 // Measured on MI355X (R-MAT 2^20, IC weighted cascade, 2^20 sets): two groups
 // per lane beat four by 22% on coin-drawn graphs (with run-length walks one and
-// two are even); with the lane pass and the fp64 log of the walks, the
-// small-set kernel runs best at 6 waves per SIMD (2.76 ms against 2.86 at 7
-// and 2.89 at 5).
+// two are even); with the lane pass and the wavefront-parallel walks, the
+// small-set kernel runs best at 5 waves per SIMD (2.55-2.67 ms against 2.66
+// at 6, 2.78 at 4 and 2.99 at 7), with 4 draws per vertex per pass (2: 2.98,
+// 8: 2.71).
 #ifndef IM_UNROLL
 #define IM_UNROLL 2
 #endif
 #ifndef IM_IC_WAVES_PER_EU
-#define IM_IC_WAVES_PER_EU 6
+#define IM_IC_WAVES_PER_EU 5
 #endif
 #ifndef IM_BIG_WAVES_PER_EU
 #define IM_BIG_WAVES_PER_EU 8
@@ -194,6 +195,89 @@ __device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long 
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
   return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int64_t shfl_i64(int64_t x, int src) {
+  return (int64_t)shfl_u64((unsigned long long)x, src);
+}
+
+// Run-length walks of the vertices held by a wavefront's lanes, with the
+// draws of each vertex spread over lanes: kWalkD draws per vertex per pass on
+// kWalkD lanes, a segmented prefix sum of (1 + gap) gives the in-edge
+// positions, and a vertex goes on to its next kWalkD draws only if all were
+// live.  Draws of a vertex are consumed in order, so the live edges and the
+// counts (draws up to the one that ends the walk, live edges) equal those of
+// walking each vertex alone; the critical path is one draw per pass instead
+// of one per draw.  rl: this lane holds a run-length vertex v with in-edges
+// [a, a + deg) and table entry sk.  owner_map: kWave ints of LDS.  Every lane
+// of the wavefront must call; push(e) is called for each live in-edge e.
+#ifndef IM_WALK_D
+#define IM_WALK_D 4
+#endif
+constexpr int kWalkD = IM_WALK_D;
+
+template <class Push>
+__device__ __forceinline__ void rl_walks(bool rl, uint32_t v, int32_t a, int32_t deg, double sk,
+                                         uint32_t seed_lo, uint32_t seed_hi, uint32_t stream,
+                                         uint32_t i, int32_t* owner_map, uint32_t* ex,
+                                         uint32_t* lv, Push&& push) {
+  constexpr int D = kWalkD;
+  const int lane = lane_id();
+  int64_t pos = -1;
+  uint32_t jb = 0;
+  bool more = rl;
+  for (;;) {
+    const unsigned long long mm = __ballot(more);
+    if (!mm) break;
+    const int nm = __popcll(mm);
+    const int my_rank = __popcll(mm & ((1ull << lane) - 1ull));
+    if (more) owner_map[my_rank] = lane;
+    wave_sync();
+    for (int f0 = 0; f0 < nm; f0 += kWave / D) {
+      const int r = f0 + lane / D, sub = lane % D;
+      const bool act = r < nm;
+      const int ol = act ? owner_map[r] : lane;
+      const uint32_t vo = (uint32_t)__shfl((int)v, ol, kWave);
+      const int32_t ao = __shfl(a, ol, kWave), dego = __shfl(deg, ol, kWave);
+      const double sko = __shfl(sk, ol, kWave);
+      const uint32_t jbo = (uint32_t)__shfl((int)jb, ol, kWave);
+      const int64_t poso = shfl_i64(pos, ol);
+      int64_t step = 0;
+      if (act) {
+        const double g =
+            floor(im_log(skip_uniform(seed_lo, seed_hi, stream, i, vo, jbo + (uint32_t)sub)) * sko);
+        step = 1 + (int64_t)fmin(g, (double)dego);  // any gap >= deg ends the walk alike
+      }
+      int64_t incl = step;  // inclusive prefix within the D lanes of a vertex
+#pragma unroll
+      for (int d = 1; d < D; d <<= 1) {
+        const int64_t y = __shfl_up(incl, d, kWave);
+        if (sub >= d) incl += y;
+      }
+      const int64_t p = poso + incl;
+      const bool live = act && p <= (int64_t)dego - 1;
+      if (live) push(ao + (int32_t)p);
+      const unsigned long long lm = __ballot(live), tm = __ballot(act && !live);
+      // the owners of this pass take their vertex's outcome
+      const int grp = my_rank - f0;
+      const bool mine = more && grp >= 0 && grp < kWave / D;
+      const int64_t plast = shfl_i64(p, mine ? grp * D + D - 1 : lane);
+      if (mine) {
+        const unsigned long long gm = (1ull << D) - 1ull;
+        const uint32_t nl = (uint32_t)__popcll((lm >> (grp * D)) & gm);
+        const bool term = ((tm >> (grp * D)) & gm) != 0ull;
+        *ex += nl + (term ? 1u : 0u);
+        *lv += nl;
+        if (term) {
+          more = false;
+        } else {
+          pos = plast;
+          jb += D;
+        }
+      }
+    }
+    wave_sync();
+  }
 }
 
 __device__ __forceinline__ uint32_t ceil_log2_plus1(int32_t d) {
@@ -460,23 +544,9 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
           s_ex += (uint32_t)(b - a);
         }
       }
-      // run-length vertices: this lane walks the geometric gaps itself
-      if (sk != 0.0) {
-        const int64_t deg = b - a;
-        int64_t pos = -1;
-        uint4 blk;
-        for (uint32_t j = 0;; ++j) {
-          ++s_ex;
-          const double gap = floor(
-              im_log(skip_uniform_seq(G.seed_lo, G.seed_hi, G.stream, i, (uint32_t)v, j, &blk)) *
-              sk);
-          if (gap >= (double)(deg - 1 - pos)) break;
-          pos += 1 + (int64_t)gap;
-          ++s_lv;
-          stage_push(L, G.in_src, a + (int32_t)pos, &over);
-          if (over) break;
-        }
-      }
+      // run-length vertices: their geometric gaps, drawn across the wavefront
+      rl_walks(sk != 0.0, (uint32_t)v, a, b - a, sk, G.seed_lo, G.seed_hi, G.stream, i, L.gbase,
+               &s_ex, &s_lv, [&](int32_t e) { stage_push(L, G.in_src, e, &over); });
       const int32_t inc = wave_inclusive_scan(ng);
       const int32_t total = __shfl(inc, kWave - 1, kWave);
       L.pre[lane] = inc;
@@ -804,31 +874,26 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         const unsigned long long ex0 = s_ex, lv0 = s_lv;
         const int32_t* Q = S.lds ? mq : queue;
         const int32_t nf = min(tail - head, C::kBlock);
-        int32_t a = 0, b = 0, ng = 0;
+        int32_t a = 0, b = 0, ng = 0, v = 0;
+        double sk = 0.0;
         if (t < nf) {
-          const int32_t v = Q[head + t];
+          v = Q[head + t];
           a = G.in_off[v];
           b = G.in_off[v + 1];
-          const double sk = G.skip ? G.skip[v] : 0.0;
+          sk = G.skip ? G.skip[v] : 0.0;
           if (sk == 0.0) {
             if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
             s_ex += (unsigned long long)(b - a);
-          } else {  // run-length vertex: walk its geometric gaps here
-            const int64_t deg = b - a;
-            int64_t pos = -1;
-            uint4 blk;
-            for (uint32_t j = 0;; ++j) {
-              ++s_ex;
-              const double gap = floor(im_log(skip_uniform_seq(G.seed_lo, G.seed_hi, G.stream, i,
-                                                               (uint32_t)v, j, &blk)) *
-                                       sk);
-              if (gap >= (double)(deg - 1 - pos)) break;
-              pos += 1 + (int64_t)gap;
-              ++s_lv;
-              big_push<C>(a + (int32_t)pos, stage, &s_nst, G.in_src, S);
-            }
-            a = b = 0;
           }
+        }
+        {  // run-length vertices: their geometric gaps, drawn across each wavefront
+          uint32_t wex = 0, wlv = 0;
+          rl_walks(sk != 0.0, (uint32_t)v, a, b - a, sk, G.seed_lo, G.seed_hi, G.stream, i,
+                   gbase + (t / kWave) * kWave, &wex, &wlv,
+                   [&](int32_t e) { big_push<C>(e, stage, &s_nst, G.in_src, S); });
+          s_ex += wex;
+          s_lv += wlv;
+          if (sk != 0.0) a = b = 0;
         }
         int64_t tot64;
         const int32_t ex = (int32_t)block_exclusive_scan64<C::kBlock>(ng, scan_lds, &tot64);
