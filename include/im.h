@@ -180,7 +180,7 @@ int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, const int32_t*
                     void* stream);
 
 /*
- * RandGreedi local step (Alg. 3 partition step; Alg. 4 lines 1-2; Sec. 3.4 S3).
+ * RandGreedi local step (Alg. 3 partition step; Alg. 4, local greedy step; Sec. 3.4 S3).
  * Partitions V uniformly at random into m parts, part(v) = floor(draw(part,
  * v) * m / 2^32) with key part_seed, and runs the standard greedy above on
  * every part p with candidates V_p and the full universe, all m in one
@@ -196,7 +196,7 @@ int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const int32_t* m
 
 /*
  * Streaming max-k-cover at the receiver (Alg. 5), truncation (Sec. 3.3.2) and
- * the final choice of Alg. 4 (lines 5-6).
+ * the final choice of Alg. 4.
  *  Stream: T = ceil(alpha*k) (clamped to [1,k]); for t < T, for p < m, the
  *   item lseeds[p][t] if t < lcount[p], carrying the full S(x).
  *  Buckets: l = max |S(x)| over the stream; B = max(1, ceil(ln k / ln(1+delta)));

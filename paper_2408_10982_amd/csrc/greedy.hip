@@ -15,7 +15,7 @@
 // The RandGreedi form runs all m partitions in the same launch: counts are
 // laid out partition by partition, each partition keeps its own covered flags
 // over the full universe of samples, and a covered sample only decrements the
-// members of the partition that covered it (Alg. 4 lines 1-2, Sec. 3.4 S3).
+// members of the partition that covered it (Alg. 4, local greedy step; Sec. 3.4 S3).
 #include <algorithm>
 #include <vector>
 
@@ -30,7 +30,7 @@ constexpr int kApplyBlock = 256;
 static_assert(kMaxParts <= kApplyBlock, "one apply thread per partition");
 constexpr int kRecountBlock = 256;
 constexpr int kRecountUnroll = 4;  // elements per lane per step of the recount
-constexpr int kRecountPicks = 8;   // picks that may rebuild the counts
+constexpr int kRecountPicks = 2;   // picks that may rebuild the counts
 // Entries of S(v*) per wavefront chunk in the apply pass: a newly covered
 // sample is walked by the whole wavefront, so small chunks spread the walks of
 // a pick over many wavefronts.
@@ -38,6 +38,12 @@ constexpr int kRecountPicks = 8;   // picks that may rebuild the counts
 #define IM_APPLY_ENTRIES 4
 #endif
 constexpr int kApplyEntries = IM_APPLY_ENTRIES;
+#ifndef IM_AGG_BLOCKS_PER_CU
+#define IM_AGG_BLOCKS_PER_CU 1
+#endif
+#ifndef IM_AGG_CU_DIV
+#define IM_AGG_CU_DIV 1
+#endif
 
 __device__ __forceinline__ int64_t part_lo(const CoverArgs& A, int p) {
   return A.pbase ? A.pbase[p] : 0;
@@ -248,6 +254,102 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   }
 }
 
+// Pick `it`, step 2, for a plain one-partition cover (positions = vertices).
+// The members of newly covered samples repeat heavily (a high-count vertex
+// sits in thousands of the samples one pick covers), and device atomics on
+// one cache line serialize, so each workgroup takes a contiguous slice of
+// S(v*), folds the decrements of its fresh samples into an LDS hash table
+// (vertex -> amount) and then applies one atomic per distinct vertex.  A
+// vertex that finds no slot within kAggProbe probes is decremented directly.
+// The counts reached are the same as with one atomic per member.
+#ifndef IM_AGG_BLOCK
+#define IM_AGG_BLOCK 1024
+#endif
+#ifndef IM_AGG_BITS
+#define IM_AGG_BITS 12
+#endif
+constexpr int kAggBlock = IM_AGG_BLOCK;
+constexpr int kAggBits = IM_AGG_BITS;  // 2^12 slots: 32 KB of LDS
+constexpr int kAggSlots = 1 << kAggBits;
+constexpr int kAggProbe = 8;
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void agg_decrement(uint32_t* hkey, uint32_t* hval, uint32_t* cnt,
+                                              uint32_t u) {
+  uint32_t h = (u * 0x9E3779B1u) >> (32 - kAggBits);
+  for (int q = 0; q < kAggProbe; ++q) {
+    const uint32_t old = atomicCAS(&hkey[h], kAggEmpty, u);
+    if (old == kAggEmpty || old == u) {
+      atomicAdd(&hval[h], 1u);
+      return;
+    }
+    h = (h + 1) & (kAggSlots - 1);
+  }
+  atomicSub(&cnt[u], 1u);
+}
+
+__global__ __launch_bounds__(kAggBlock) void k_cover_apply_one(CoverArgs A, int it) {
+  __shared__ uint32_t hkey[kAggSlots];
+  __shared__ uint32_t hval[kAggSlots];
+  const int tid = threadIdx.x, lane = lane_id();
+  const unsigned long long key = A.gmax[it];
+  if (*A.done || key_count(key) == 0) {  // nothing left to gain (uniform)
+    if (blockIdx.x == 0 && tid == 0) *A.done = 1;
+    return;
+  }
+  const uint32_t v = key_vertex(key);
+  if (blockIdx.x == 0 && tid == 0) {
+    A.seeds[it] = (int32_t)v;
+    A.gains[it] = (int64_t)key_count(key);
+  }
+  const int64_t base = A.inc_off[v], tot = A.inc_off[v + 1] - base;
+  const bool decrement = !recount_pick(A, it);
+  if (!decrement) {  // mark only; k_cover_recount rebuilds the counts
+    const int64_t gtid = (int64_t)blockIdx.x * kAggBlock + tid;
+    const int64_t gthreads = (int64_t)gridDim.x * kAggBlock;
+    for (int64_t pos = gtid; pos < A.n; pos += gthreads) A.cnt[pos] = 0u;
+    for (int64_t f = gtid; f < tot; f += gthreads) A.covered[A.inc_mem[base + f]] = 1;
+    return;
+  }
+  const int64_t per = (tot + gridDim.x - 1) / gridDim.x;
+  const int64_t e0 = min(tot, (int64_t)blockIdx.x * per), e1 = min(tot, e0 + per);
+  if (e0 >= e1) return;  // uniform over the block
+  for (int j = tid; j < kAggSlots; j += kAggBlock) {
+    hkey[j] = kAggEmpty;
+    hval[j] = 0u;
+  }
+  __syncthreads();
+  const int wv = tid / kWave;
+  const int64_t nchunks = (e1 - e0 + kApplyEntries - 1) / kApplyEntries;
+  for (int64_t c = wv; c < nchunks; c += kAggBlock / kWave) {
+    const int64_t f = e0 + c * kApplyEntries + lane;
+    bool fresh = false;
+    int64_t ma = 0, mb = 0;
+    if (lane < kApplyEntries && f < e1) {
+      const int32_t smp = A.inc_mem[base + f];
+      const uint8_t was = A.covered[smp];
+      ma = A.off[smp];
+      mb = A.off[smp + 1];
+      if (!was) {  // each sample occurs once in S(v), so no race
+        A.covered[smp] = 1;
+        fresh = true;
+      }
+    }
+    unsigned long long todo = __ballot(fresh);
+    while (todo) {
+      const int src = __ffsll(todo) - 1;
+      todo &= todo - 1;
+      const int64_t a = __shfl(ma, src, kWave), b = __shfl(mb, src, kWave);
+      for (int64_t t = a + lane; t < b; t += kWave) agg_decrement(hkey, hval, A.cnt, (uint32_t)A.mem[t]);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < kAggSlots; j += kAggBlock) {
+    const uint32_t d = hval[j];
+    if (d) atomicSub(&A.cnt[hkey[j]], d);
+  }
+}
+
 // One-partition cover after its first pick: cnt[v] = |S(v) minus covered| for
 // every v, without per-member atomics.  Each wavefront takes an equal slice of
 // the covering-subset elements and walks it 64 vertices at a time (their
@@ -418,16 +520,21 @@ int launch_cover(CoverArgs& A, hipStream_t s) {
   IM_HIP(hipGetLastError());
   const unsigned arg_blocks = (unsigned)std::max<int64_t>(((int64_t)A.n + kArgTile - 1) / kArgTile, 1);
   const unsigned apply_blocks = (unsigned)di.num_cus * 4;
-  // A plain one-partition cover rebuilds all counts after an early pick that
-  // covers at least count / 64 samples (a member decrement per device atomic
-  // costs more there than one pass over the covering subsets: at 2^20
-  // weighted-cascade sets the first pick's 12 M decrements take 0.74 ms, a
-  // recount 0.1 ms); the decision is taken on the device from the pick's gain.
+  const unsigned agg_blocks = (unsigned)(di.num_cus * IM_AGG_BLOCKS_PER_CU / IM_AGG_CU_DIV);
+  // A plain one-partition cover rebuilds all counts after one of its first
+  // kRecountPicks picks if that pick covers at least count / 64 samples (at
+  // 2^20 weighted-cascade sets the first pick newly covers 41 K samples
+  // holding 12 M members, the second 7 K holding 0.9 M; a recount is one pass
+  // over the covering subsets, 0.1 ms); the decision is taken on the device
+  // from the pick's gain.  Its other picks use the aggregated apply.
   const bool can_recount = A.m == 1 && !A.order && !A.pos_of && !A.sbase && !A.local_ids;
   A.recount_min = can_recount ? std::max<int64_t>(1, A.count / 64) : 0;
   for (int it = 0; it < A.k; ++it) {
     k_cover_argmax<<<dim3(arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
-    k_cover_apply<<<dim3(apply_blocks), dim3(kApplyBlock), 0, s>>>(A, it);
+    if (can_recount)
+      k_cover_apply_one<<<dim3(agg_blocks), dim3(kAggBlock), 0, s>>>(A, it);
+    else
+      k_cover_apply<<<dim3(apply_blocks), dim3(kApplyBlock), 0, s>>>(A, it);
     if (can_recount && it < kRecountPicks)
       k_cover_recount<<<dim3((unsigned)di.num_cus * 8), dim3(kRecountBlock), 0, s>>>(A, it);
   }

@@ -1,6 +1,6 @@
 // stream.hip -- streaming max-k-cover at the receiver with truncation, and the
 // final choice between the streamed and the best local solution
-// (im_stream_cover; Alg. 5, Sec. 3.3.2, Alg. 4 lines 5-6).
+// (im_stream_cover; Alg. 5, Sec. 3.3.2, Alg. 4, final choice).
 //
 // Bucket state is bit-sliced: one 64-bit word per sample whose bit b says
 // "covered in bucket b", so every streamed set is read once for all buckets.
