@@ -368,8 +368,10 @@ def bench_serve(args, im, W, torch):
         server = S.Server(graphs, seed=seed, slots=args.slots, hbm_budget=160 << 30)
         qs = [S.Query(qid=j, graph=name, k=k, eps=eps, arrival=float(arr[j]))
               for j, (name, k, eps) in enumerate(spec)]
-        done = S.run_arrivals(server, qs)
-        server.close()
+        try:
+            done = S.run_arrivals(server, qs)
+        finally:
+            server.close()
         for q, p in zip(done, plain):
             assert q.result["seeds"] == p["seeds"] and q.result["coverage"] == p["coverage"]
         served_pt = S.latency_summary(done)

@@ -48,7 +48,8 @@ typedef enum {
   IM_OK = 0,
   IM_EINVAL = -1,  /* invalid argument; nothing was enqueued or written */
   IM_ERANGE = -2,  /* output capacity too small; the needed size is returned */
-  IM_ENOMEM = -3,  /* device scratch allocation failed */
+  IM_ENOMEM = -3,  /* device scratch allocation failed, or a sampling arena stayed
+                      short after its retries (the detail is in im_last_error()) */
   IM_EDEVICE = -4  /* a HIP call failed (the HIP error is in im_last_error()) */
 } im_status;
 
@@ -90,7 +91,8 @@ typedef struct {
 
 /* Library version string. */
 const char* im_version(void);
-/* Text of the last HIP error seen by the calling thread ("" if none). */
+/* Text of the calling thread's last error: a failed HIP call, scratch
+ * allocation or arena ("" if none). */
 const char* im_last_error(void);
 /* Releases the library's device scratch for every stream of the current
  * device.  The caller must ensure no call is in flight. */

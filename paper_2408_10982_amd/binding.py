@@ -115,7 +115,7 @@ def lib():
 
 def _check(status: int, where: str):
     if status != IM_OK:
-        detail = lib().im_last_error().decode() if status == IM_EDEVICE else ""
+        detail = lib().im_last_error().decode() if status in (IM_EDEVICE, IM_ENOMEM) else ""
         raise ImError(status, where, detail)
 
 

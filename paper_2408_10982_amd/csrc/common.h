@@ -9,6 +9,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <string>
+
 #include "../../include/im.h"
 
 namespace im {
@@ -165,8 +167,9 @@ __device__ __forceinline__ uint32_t key_count(uint64_t key) { return (uint32_t)(
 // ----------------------------------------------------------------- host side
 namespace im {
 
-// Per-thread last HIP error text.
+// Per-thread last error text (im_last_error).
 void set_error(hipError_t e, const char* where);
+void set_error_text(const std::string& text);
 
 #define IM_HIP(call)                                   \
   do {                                                 \

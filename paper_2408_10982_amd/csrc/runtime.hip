@@ -14,6 +14,8 @@ void set_error(hipError_t e, const char* where) {
   g_last_error = std::string(where) + ": " + hipGetErrorString(e);
 }
 
+void set_error_text(const std::string& text) { g_last_error = text; }
+
 namespace {
 struct ScratchBuf {
   void* ptr = nullptr;
@@ -52,7 +54,8 @@ int scratch_fresh(hipStream_t stream, int slot, size_t bytes, void** ptr, bool* 
       want = bytes;
       if (e != hipSuccess) {
         (void)hipGetLastError();
-        set_error(e, "hipMalloc(scratch)");
+        set_error_text("hipMalloc(scratch) of " + std::to_string(bytes) + " bytes: " +
+                       hipGetErrorString(e));
         return IM_ENOMEM;
       }
     }

@@ -164,6 +164,10 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 // small-set kernel runs best at 5 waves per SIMD (2.55-2.67 ms against 2.66
 // at 6, 2.78 at 4 and 2.99 at 7), with 4 draws per vertex per pass (2: 2.98,
 // 8: 2.71).
+// HBM per stream for the large-set workers' bitmaps and queues (GiB)
+#ifndef IM_BIG_BUDGET_GIB
+#define IM_BIG_BUDGET_GIB 16
+#endif
 #ifndef IM_UNROLL
 #define IM_UNROLL 2
 #endif
@@ -1416,16 +1420,18 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       const uint32_t nwords = (uint32_t)(((int64_t)max_n + 31) / 32);
       // workers each hold an n-bit bitmap and an n-entry queue
       const size_t per_worker = (size_t)nwords * 4 + (size_t)max_n * 4;
-      // up to kPerCu workers per CU, within a 32 GiB budget; the bitmaps are zero
+      // up to kPerCu workers per CU, within a budget of IM_BIG_BUDGET_GIB per
+      // stream (at 2^20 vertices 16 GiB holds 3.9 K workers, as fast as any
+      // larger number; 8 GiB is 40% slower); the bitmaps are zero
       // between uses (each set clears its own bits), so only a new buffer
       // needs clearing
       // one wavefront per set unless most sets were handed off
       const bool narrow = (uint64_t)nbig * 8 <= (uint64_t)cnt;
       const uint32_t max_workers =
           (uint32_t)di.num_cus * (narrow ? BigNarrow::kPerCu : BigWide::kPerCu);
-      uint32_t cap_workers = max_workers;
-      const size_t budget = (size_t)32 << 30;
-      while (cap_workers > 1 && (size_t)cap_workers * per_worker > budget) cap_workers >>= 1;
+      const size_t budget = (size_t)IM_BIG_BUDGET_GIB << 30;
+      const uint32_t cap_workers = (uint32_t)std::max<size_t>(
+          1, std::min<size_t>(max_workers, budget / per_worker));
       const uint32_t workers = std::min<uint32_t>(nbig, cap_workers);
       void* bp = nullptr;
       bool bfresh = false;
@@ -1461,7 +1467,11 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       if (timed) IM_HIP(hipEventElapsedTime(&ms_large, ev[2], ev[3]));
     }
     if (hc[1] <= arena_cap) break;
-    if (attempt == 2) return IM_ENOMEM;
+    if (attempt == 2) {
+      set_error_text("im_sample_rrr: arena still short after 3 passes (needed " +
+                     std::to_string(hc[1]) + " of " + std::to_string(arena_cap) + " entries)");
+      return IM_ENOMEM;
+    }
     // the sets are deterministic, the chunk slack is not: leave room for it
     arena_cap = hc[1] + hc[1] / 8 + slack;
   }

@@ -194,6 +194,7 @@ class Query:
     finished: float = 0.0
     result: dict = field(default_factory=dict)
     footprint: int = 0
+    error: BaseException | None = None  # set when its solve raised
 
 
 class Server:
@@ -263,16 +264,21 @@ class Server:
             q = got[0]
             q.admitted = time.perf_counter()
             g = self.graphs[q.graph]
-            with torch.cuda.stream(stream):
-                res = solve_pooled(g, self._pools(q.graph), q.k, q.eps, stream)
-            q.result = res
+            res = None
+            try:
+                with torch.cuda.stream(stream):
+                    res = solve_pooled(g, self._pools(q.graph), q.k, q.eps, stream)
+                q.result = res
+            except Exception as e:  # the query finishes with its error; the slot goes on
+                q.error = e
             q.finished = time.perf_counter()
             with self.cv:
                 self.adm.release(q.footprint)
                 self.done.append(q)
-                self.theta_seen[q.graph] = max(self.theta_seen.get(q.graph, 0), res["theta"])
-                if res["theta"]:
-                    self.avg_set[q.graph] = res["final_total"] / res["theta"]
+                if res is not None:
+                    self.theta_seen[q.graph] = max(self.theta_seen.get(q.graph, 0), res["theta"])
+                    if res["theta"]:
+                        self.avg_set[q.graph] = res["final_total"] / res["theta"]
                 self.cv.notify_all()
 
     def close(self):
@@ -294,7 +300,8 @@ class Server:
 
 def run_arrivals(server: Server, queries: list, t0: float | None = None):
     """Submits queries at their arrival offsets (seconds from t0) and waits
-    for all of them; returns the finished queries in id order."""
+    for all of them; returns the finished queries in id order.  Raises the
+    first failed query's error (by id) once all have finished."""
     t0 = time.perf_counter() if t0 is None else t0
     for q in sorted(queries, key=lambda q: q.arrival):
         dt = t0 + q.arrival - time.perf_counter()
@@ -305,7 +312,12 @@ def run_arrivals(server: Server, queries: list, t0: float | None = None):
     with server.cv:
         while len(server.done) < len(queries):
             server.cv.wait()
-    return sorted(server.done, key=lambda q: q.qid)
+    out = sorted(server.done, key=lambda q: q.qid)
+    failed = [q for q in out if q.error is not None]
+    if failed:
+        raise RuntimeError("%d of %d queries failed; query %d: %r" %
+                           (len(failed), len(out), failed[0].qid, failed[0].error)) from failed[0].error
+    return out
 
 
 def latency_summary(queries: list) -> dict:

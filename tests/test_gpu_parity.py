@@ -341,3 +341,29 @@ def test_serving_results_equal_alone(im):
             assert r["theta"] == a["theta"] and r["rounds"] == a["rounds"]
             assert r["lower_bound"] == a["lower_bound"]
             assert r["martingale_samples"] == a["martingale_samples"]
+
+
+def test_serving_failed_query_raises(im, monkeypatch):
+    """A query whose solve raises finishes with its error; the other queries
+    still finish, and run_arrivals then raises instead of waiting forever."""
+    _say("serving failure")
+    from paper_2408_10982_amd import serve as S
+    g = W.random_small_graph(2000, 9000, seed=23, p_hi=0.2)
+    prepared = {"ic": _prep(im, g)}
+    real = S.solve_pooled
+
+    def flaky(graph, pools, k, eps, stream):
+        if k == 7:
+            raise RuntimeError("planted failure")
+        return real(graph, pools, k, eps, stream)
+
+    monkeypatch.setattr(S, "solve_pooled", flaky)
+    server = S.Server(prepared, seed=5006, slots=2, hbm_budget=1 << 40)
+    qs = [S.Query(qid=j, graph="ic", k=k, eps=0.5, arrival=0.0) for j, k in enumerate((5, 7, 9))]
+    try:
+        with pytest.raises(RuntimeError, match="1 of 3 queries failed; query 1"):
+            S.run_arrivals(server, qs)
+    finally:
+        server.close()
+    assert qs[1].error is not None and not qs[1].result
+    assert qs[0].result["seeds"] and qs[2].result["seeds"]
