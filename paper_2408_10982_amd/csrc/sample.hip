@@ -77,11 +77,15 @@ struct SampleArgs {
   int32_t* __restrict__ len;     // per output position: size (-1 while on the large path)
   uint32_t* __restrict__ big_list;       // output positions handed to the large path
   struct Handoff* __restrict__ handoff;  // kMaxHandoff snapshots (IC)
+  uint32_t* __restrict__ dq;             // IC: work items left to the second launch
+                                         // (count entries)
   unsigned long long* __restrict__ ctr;  // [0] IC work, [1] cursor, [2] big count,
                                          // [3] examined, [4] live, [5] big work,
                                          // [6] big examined, [7] big live, [8] big total,
                                          // [9] examined in abandoned rounds,
-                                         // [10] sum of set sizes, [11] LT work
+                                         // [10] sum of set sizes, [11] LT work,
+                                         // [12] dq entries, [13] dq entries taken;
+                                         // [16] (own cache line) every IC item claimed
 };
 
 // The graph and random stream of one task, as the kernels use them.
@@ -178,6 +182,7 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 #define IM_BIG_WAVES_PER_EU 8
 #endif
 #define IM_IC_ATTR __attribute__((amdgpu_waves_per_eu(IM_IC_WAVES_PER_EU)))
+
 #define IM_BIG_ATTR __attribute__((amdgpu_waves_per_eu(IM_BIG_WAVES_PER_EU)))
 constexpr int kUnroll = IM_UNROLL;  // 4-edge groups per lane per iteration
 
@@ -442,263 +447,329 @@ __device__ bool tiny_set(const GView& G, uint32_t i, int32_t root, int32_t* list
   return true;
 }
 
+// The lane pass over work items [b, b + 64): every lane grows one set alone
+// (tiny_set).  Finished sets go to the arena; returns the mask of lanes whose
+// set is left to the wavefront path.
+__device__ __forceinline__ unsigned long long lane_pass(const SampleArgs& A, WaveLds& L, unsigned long long b,
+                                          unsigned long long* cpos, unsigned long long* cend,
+                                          unsigned long long* w_tot, unsigned long long* w_ex,
+                                          unsigned long long* w_lv) {
+  const int lane = lane_id();
+  const unsigned long long my = b + (unsigned long long)lane;
+  const bool have = my < A.count;
+  int32_t* list = L.hash + lane * kTiny;  // the hash is cleared per set below
+  bool done = false;
+  int32_t n = 0;
+  uint32_t t_ex = 0, t_lv = 0;
+  int64_t il = 0;
+  if (have) {
+    int tk;
+    uint32_t i;
+    locate_work(A, my, &tk, &i, &il);
+    const GView G = view_of(A.tasks[tk]);
+    const int32_t root = (int32_t)scale_draw(
+        draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream, 0u, i), G.n);
+    done = tiny_set(G, i, root, list, &n, &t_ex, &t_lv);
+  }
+  const int32_t sz = done ? n : 0;
+  const int32_t incl = wave_inclusive_scan(sz);
+  const unsigned long long tot = (unsigned long long)__shfl(incl, kWave - 1, kWave);
+  if (tot > 0) {
+    if (*cpos + tot > *cend) {
+      const unsigned long long want = max(tot, kChunk);
+      unsigned long long c = 0;
+      if (lane == 0) c = atomicAdd(&A.ctr[1], want);
+      *cpos = first_lane_u64(shfl_u64(c, 0));
+      *cend = *cpos + want;
+    }
+    const unsigned long long pos = *cpos;
+    *cpos += tot;
+    *w_tot += tot;
+    if (done) {
+      const unsigned long long mine = pos + (unsigned long long)(incl - sz);
+      if (pos + tot <= A.arena_cap)
+        for (int32_t k = 0; k < n; ++k) A.arena[mine + k] = list[k];
+      A.start[il] = (int64_t)mine;
+      A.len[il] = n;
+      *w_ex += t_ex;
+      *w_lv += t_lv;
+    }
+  }
+  return __ballot(have && !done);
+}
+
+// Per-wavefront counter sums of finished sets into the launch totals.
+__device__ __forceinline__ void flush_counts(const SampleArgs& A, unsigned long long w_ex,
+                                             unsigned long long w_lv, unsigned long long w_tot) {
+  w_ex = wave_sum(w_ex);
+  w_lv = wave_sum(w_lv);
+  if (lane_id() == 0) {
+    if (w_ex) atomicAdd(&A.ctr[3], w_ex);
+    if (w_lv) atomicAdd(&A.ctr[4], w_lv);
+    if (w_tot) atomicAdd(&A.ctr[10], w_tot);
+  }
+}
+
+
+// The wavefront path for one set (work item `item`): the whole wavefront
+// grows it with its visited set in LDS (kSmallH slots, kSmallCap members);
+// a set that outgrows it is handed to the large-set launch with a snapshot of
+// its state at the start of the overflowing round.
+// cpos/cend: the wavefront's reserved arena chunk; w_*: its running sums.
+__device__ __forceinline__ void wave_path(const SampleArgs& A, WaveLds& L,
+                                          unsigned long long item, unsigned long long& cpos,
+                                          unsigned long long& cend, unsigned long long& w_tot,
+                                          unsigned long long& w_ex, unsigned long long& w_lv) {
+  const int lane = lane_id();
+  int tk;
+  uint32_t i;
+  int64_t il;
+  locate_work(A, item, &tk, &i, &il);
+  const GView G = view_of(A.tasks[tk]);
+  const int32_t root =
+      (int32_t)scale_draw(draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream,
+                                0u, i),
+                          G.n);
+  for (int j = lane; j < kSmallH; j += kWave) L.hash[j] = kEmpty;
+  wave_sync();
+  if (lane == 0) {
+    L.hash[hash_slot(root, 9)] = root;
+    L.queue[0] = root;
+    L.tail = 1;
+    L.nst = 0;
+  }
+  wave_sync();
+  int32_t head = 0, tail = 1;
+  bool over = false;
+  uint32_t s_ex = 0, s_lv = 0;  // this set's draws / live edges, per lane
+  int32_t head0 = 0, tail0 = 1;
+  uint32_t ex0 = 0, lv0 = 0;
+  while (head < tail) {
+    head0 = head;  // snapshot for a hand-off
+    tail0 = tail;
+    ex0 = s_ex;
+    lv0 = s_lv;
+    const int32_t nf = min(tail - head, kWave);
+    int32_t a = 0, b = 0, ng = 0, v = 0;
+    double sk = 0.0;
+    if (lane < nf) {
+      v = L.queue[head + lane];
+      a = G.in_off[v];
+      b = G.in_off[v + 1];
+      if (G.skip) sk = G.skip[v];
+      if (sk == 0.0) {
+        if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
+        s_ex += (uint32_t)(b - a);
+      }
+    }
+    // run-length vertices: their geometric gaps, drawn across the wavefront
+    rl_walks(sk != 0.0, (uint32_t)v, a, b - a, sk, G.seed_lo, G.seed_hi, G.stream, i, L.gbase,
+             &s_ex, &s_lv, [&](int32_t e) { stage_push(L, G.in_src, e, &over); });
+    const int32_t inc = wave_inclusive_scan(ng);
+    const int32_t total = __shfl(inc, kWave - 1, kWave);
+    L.pre[lane] = inc;
+    L.gbase[lane] = (a >> 2) - (inc - ng);
+    L.ea[lane] = a;
+    L.eb[lane] = b;
+    head += nf;
+    wave_sync();
+    for (int32_t base = 0; base < total; base += kWave * kUnroll) {
+      // one owner for the whole chunk (a large in-edge list) skips the search
+      const int o_b = owner_of<kWave>(L.pre, base);
+      const bool uni = L.pre[o_b] >= min(total, base + kWave * kUnroll);
+      uint4 q[kUnroll];
+      uint32_t g[kUnroll];
+      int32_t ea[kUnroll], eb[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int32_t gi = base + u * kWave + lane;
+        ea[u] = eb[u] = 0;
+        g[u] = 0;
+        if (gi < total) {
+          const int o = uni ? o_b : owner_of<kWave>(L.pre, gi);
+          g[u] = (uint32_t)(L.gbase[o] + gi);
+          ea[u] = L.ea[o];
+          eb[u] = L.eb[o];
+          q[u] = reinterpret_cast<const uint4*>(G.thr)[g[u]];
+        }
+      }
+      uint32_t lm = 0;  // live words of this lane's groups, bit u * 4 + w
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (ea[u] < eb[u]) {
+          const uint4 r = philox4x32_10(make_uint4(g[u], i, kTagEdge, G.stream), G.seed_lo,
+                                        G.seed_hi);
+          const int32_t e0 = (int32_t)(g[u] << 2);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int32_t e = e0 + w;
+            const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
+            if (e >= ea[u] && e < eb[u] && (qw == 0xFFFFFFFFu || rw < qw)) lm |= 1u << (u * 4 + w);
+          }
+        }
+      }
+      {  // stage this iteration's live edges at wave-scanned positions
+        const int32_t c = __popc(lm);
+        const int32_t incl = wave_inclusive_scan(c);
+        const int32_t base = L.nst;
+        int32_t k = base + incl - c;
+        s_lv += (uint32_t)c;
+        while (lm) {
+          const int bit = __ffs(lm) - 1;
+          lm &= lm - 1;
+          uint32_t gb = g[0];
+#pragma unroll
+          for (int u = 1; u < kUnroll; ++u)
+            if ((bit >> 2) == u) gb = g[u];
+          const int32_t e = (int32_t)(gb << 2) + (bit & 3);
+          if (k < kStage)
+            L.stage[k] = e;
+          else
+            lds_insert(L, G.in_src[e], &over);
+          ++k;
+        }
+        wave_sync();
+        if (lane == kWave - 1) L.nst = base + incl;
+      }
+      stage_flush(L, G.in_src, lane, &over);
+      if (__any(over)) break;
+    }
+    stage_flush(L, G.in_src, lane, &over);  // the walks' edges when no groups ran
+    tail = L.tail;
+    if (__any(over) || tail > kSmallCap) {
+      over = true;
+      break;
+    }
+  }
+  if (over) {
+    const unsigned long long hex = wave_sum((unsigned long long)ex0);
+    const unsigned long long hlv = wave_sum((unsigned long long)lv0);
+    const unsigned long long redo = wave_sum((unsigned long long)(s_ex - ex0));
+    if (lane == 0 && redo) atomicAdd(&A.ctr[9], redo);
+    uint32_t slot = 0;
+    if (lane == 0) slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
+    slot = __shfl(slot, 0, kWave);
+    if (slot < kMaxHandoff) {
+      Handoff& H = A.handoff[slot];
+      for (int j = lane; j < tail0; j += kWave) H.mem[j] = L.queue[j];
+      if (lane == 0) {
+        H.head = head0;
+        H.tail = tail0;
+        H.ex = hex;
+        H.lv = hlv;
+      }
+    }
+    if (lane == 0) {
+      A.big_list[slot] = il;
+      A.len[il] = -1;
+    }
+    wave_sync();
+    return;
+  }
+  // sort queue[0, tail) ascending (bitonic over the next power of two)
+  int32_t P = 1;
+  while (P < tail) P <<= 1;
+  for (int j = tail + lane; j < P; j += kWave) L.queue[j] = 0x7FFFFFFF;
+  wave_sync();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < (P >> 1); t += kWave) {
+        const int i1 = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const int i2 = i1 | j;
+        const bool asc = (i1 & k) == 0;
+        const int32_t x = L.queue[i1], y = L.queue[i2];
+        if ((x > y) == asc) {
+          L.queue[i1] = y;
+          L.queue[i2] = x;
+        }
+      }
+      wave_sync();
+    }
+  }
+  if (cpos + (unsigned long long)tail > cend) {
+    const unsigned long long want = max((unsigned long long)tail, kChunk);
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(&A.ctr[1], want);
+    cpos = first_lane_u64(shfl_u64(b, 0));
+    cend = cpos + want;
+  }
+  const unsigned long long pos = cpos;
+  cpos += (unsigned long long)tail;
+  w_tot += (unsigned long long)tail;
+  if (pos + (unsigned long long)tail <= A.arena_cap)
+    for (int j = lane; j < tail; j += kWave) A.arena[pos + j] = L.queue[j];
+  if (lane == 0) {
+    A.start[il] = (int64_t)pos;
+    A.len[il] = tail;
+  }
+  w_ex += s_ex;
+  w_lv += s_lv;
+  wave_sync();
+}
+
+// IC sets, first launch: each wavefront claims 64 work items at a time
+// (ctr[0]), runs the lane pass over them and then the wavefront path over
+// the items the lane pass left, in order.  Once every item is claimed
+// (ctr[16] set by the first wavefront to find none), a wavefront appends the
+// items it has not started to A.dq (reserved on ctr[12]) and stops, so no
+// wavefront works through a long private backlog while others idle.
 __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(SampleArgs A) {
   __shared__ WaveLds lds_all[kSmallBlock / kWave];
   WaveLds& L = lds_all[threadIdx.x / kWave];
   const int lane = lane_id();
   unsigned long long w_ex = 0, w_lv = 0;  // per-lane sums of finished sets
   unsigned long long w_tot = 0;            // members written by this wave
-  unsigned long long batch = 0;           // first of the 64 claimed work items
-  unsigned long long defer = 0;           // items of the batch left to the wavefront path
   unsigned long long cpos = 0, cend = 0;  // reserved arena chunk
+  unsigned long long batch = 0, defer = 0;
   for (;;) {
     wave_sync();
     if (defer == 0) {
-      // claim 64 work items and run the lane pass over them (see tiny_set)
       unsigned long long b = 0;
       if (lane == 0) b = atomicAdd(&A.ctr[0], (unsigned long long)kWave);
       b = first_lane_u64(shfl_u64(b, 0));
-      if (b >= A.count) break;
-      batch = b;
-      const unsigned long long my = b + (unsigned long long)lane;
-      const bool have = my < A.count;
-      int32_t* list = L.hash + lane * kTiny;  // the hash is cleared per set below
-      bool done = false;
-      int32_t n = 0;
-      uint32_t t_ex = 0, t_lv = 0;
-      int64_t il = 0;
-      if (have) {
-        int tk;
-        uint32_t i;
-        locate_work(A, my, &tk, &i, &il);
-        const GView G = view_of(A.tasks[tk]);
-        const int32_t root = (int32_t)scale_draw(
-            draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream, 0u, i), G.n);
-        done = tiny_set(G, i, root, list, &n, &t_ex, &t_lv);
-      }
-      const int32_t sz = done ? n : 0;
-      const int32_t incl = wave_inclusive_scan(sz);
-      const unsigned long long tot = (unsigned long long)__shfl(incl, kWave - 1, kWave);
-      if (tot > 0) {
-        if (cpos + tot > cend) {
-          const unsigned long long want = max(tot, kChunk);
-          unsigned long long c = 0;
-          if (lane == 0) c = atomicAdd(&A.ctr[1], want);
-          cpos = first_lane_u64(shfl_u64(c, 0));
-          cend = cpos + want;
-        }
-        const unsigned long long pos = cpos;
-        cpos += tot;
-        w_tot += tot;
-        if (done) {
-          const unsigned long long mine = pos + (unsigned long long)(incl - sz);
-          if (pos + tot <= A.arena_cap)
-            for (int32_t k = 0; k < n; ++k) A.arena[mine + k] = list[k];
-          A.start[il] = (int64_t)mine;
-          A.len[il] = n;
-          w_ex += t_ex;
-          w_lv += t_lv;
-        }
-      }
-      defer = __ballot(have && !done);
-      continue;
-    }
-    // the wavefront path, one item left by the lane pass at a time
-    const int dl = __ffsll(defer) - 1;
-    defer &= defer - 1;
-    const unsigned long long item = batch + (unsigned long long)dl;
-    int tk;
-    uint32_t i;
-    int64_t il;
-    locate_work(A, item, &tk, &i, &il);
-    const GView G = view_of(A.tasks[tk]);
-    const int32_t root =
-        (int32_t)scale_draw(draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream,
-                                  0u, i),
-                            G.n);
-    for (int j = lane; j < kSmallH; j += kWave) L.hash[j] = kEmpty;
-    wave_sync();
-    if (lane == 0) {
-      L.hash[hash_slot(root, 9)] = root;
-      L.queue[0] = root;
-      L.tail = 1;
-      L.nst = 0;
-    }
-    wave_sync();
-    int32_t head = 0, tail = 1;
-    bool over = false;
-    uint32_t s_ex = 0, s_lv = 0;  // this set's draws / live edges, per lane
-    int32_t head0 = 0, tail0 = 1;
-    uint32_t ex0 = 0, lv0 = 0;
-    while (head < tail) {
-      head0 = head;  // snapshot for a hand-off
-      tail0 = tail;
-      ex0 = s_ex;
-      lv0 = s_lv;
-      const int32_t nf = min(tail - head, kWave);
-      int32_t a = 0, b = 0, ng = 0, v = 0;
-      double sk = 0.0;
-      if (lane < nf) {
-        v = L.queue[head + lane];
-        a = G.in_off[v];
-        b = G.in_off[v + 1];
-        if (G.skip) sk = G.skip[v];
-        if (sk == 0.0) {
-          if (a < b) ng = ((b - 1) >> 2) - (a >> 2) + 1;
-          s_ex += (uint32_t)(b - a);
-        }
-      }
-      // run-length vertices: their geometric gaps, drawn across the wavefront
-      rl_walks(sk != 0.0, (uint32_t)v, a, b - a, sk, G.seed_lo, G.seed_hi, G.stream, i, L.gbase,
-               &s_ex, &s_lv, [&](int32_t e) { stage_push(L, G.in_src, e, &over); });
-      const int32_t inc = wave_inclusive_scan(ng);
-      const int32_t total = __shfl(inc, kWave - 1, kWave);
-      L.pre[lane] = inc;
-      L.gbase[lane] = (a >> 2) - (inc - ng);
-      L.ea[lane] = a;
-      L.eb[lane] = b;
-      head += nf;
-      wave_sync();
-      for (int32_t base = 0; base < total; base += kWave * kUnroll) {
-        // one owner for the whole chunk (a large in-edge list) skips the search
-        const int o_b = owner_of<kWave>(L.pre, base);
-        const bool uni = L.pre[o_b] >= min(total, base + kWave * kUnroll);
-        uint4 q[kUnroll];
-        uint32_t g[kUnroll];
-        int32_t ea[kUnroll], eb[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          const int32_t gi = base + u * kWave + lane;
-          ea[u] = eb[u] = 0;
-          g[u] = 0;
-          if (gi < total) {
-            const int o = uni ? o_b : owner_of<kWave>(L.pre, gi);
-            g[u] = (uint32_t)(L.gbase[o] + gi);
-            ea[u] = L.ea[o];
-            eb[u] = L.eb[o];
-            q[u] = reinterpret_cast<const uint4*>(G.thr)[g[u]];
-          }
-        }
-        uint32_t lm = 0;  // live words of this lane's groups, bit u * 4 + w
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (ea[u] < eb[u]) {
-            const uint4 r = philox4x32_10(make_uint4(g[u], i, kTagEdge, G.stream), G.seed_lo,
-                                          G.seed_hi);
-            const int32_t e0 = (int32_t)(g[u] << 2);
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-              const int32_t e = e0 + w;
-              const uint32_t qw = pick_word(q[u], w), rw = pick_word(r, w);
-              if (e >= ea[u] && e < eb[u] && (qw == 0xFFFFFFFFu || rw < qw)) lm |= 1u << (u * 4 + w);
-            }
-          }
-        }
-        {  // stage this iteration's live edges at wave-scanned positions
-          const int32_t c = __popc(lm);
-          const int32_t incl = wave_inclusive_scan(c);
-          const int32_t base = L.nst;
-          int32_t k = base + incl - c;
-          s_lv += (uint32_t)c;
-          while (lm) {
-            const int bit = __ffs(lm) - 1;
-            lm &= lm - 1;
-            uint32_t gb = g[0];
-#pragma unroll
-            for (int u = 1; u < kUnroll; ++u)
-              if ((bit >> 2) == u) gb = g[u];
-            const int32_t e = (int32_t)(gb << 2) + (bit & 3);
-            if (k < kStage)
-              L.stage[k] = e;
-            else
-              lds_insert(L, G.in_src[e], &over);
-            ++k;
-          }
-          wave_sync();
-          if (lane == kWave - 1) L.nst = base + incl;
-        }
-        stage_flush(L, G.in_src, lane, &over);
-        if (__any(over)) break;
-      }
-      stage_flush(L, G.in_src, lane, &over);  // the walks' edges when no groups ran
-      tail = L.tail;
-      if (__any(over) || tail > kSmallCap) {
-        over = true;
+      if (b >= A.count) {
+        if (lane == 0) __hip_atomic_store(&A.ctr[16], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
-    }
-    if (over) {
-      const unsigned long long hex = wave_sum((unsigned long long)ex0);
-      const unsigned long long hlv = wave_sum((unsigned long long)lv0);
-      const unsigned long long redo = wave_sum((unsigned long long)(s_ex - ex0));
-      if (lane == 0 && redo) atomicAdd(&A.ctr[9], redo);
-      uint32_t slot = 0;
-      if (lane == 0) slot = (uint32_t)atomicAdd(&A.ctr[2], 1ull);
-      slot = __shfl(slot, 0, kWave);
-      if (slot < kMaxHandoff) {
-        Handoff& H = A.handoff[slot];
-        for (int j = lane; j < tail0; j += kWave) H.mem[j] = L.queue[j];
-        if (lane == 0) {
-          H.head = head0;
-          H.tail = tail0;
-          H.ex = hex;
-          H.lv = hlv;
-        }
-      }
-      if (lane == 0) {
-        A.big_list[slot] = il;
-        A.len[il] = -1;
-      }
-      wave_sync();
+      batch = b;
+      defer = lane_pass(A, L, b, &cpos, &cend, &w_tot, &w_ex, &w_lv);
       continue;
     }
-    // sort queue[0, tail) ascending (bitonic over the next power of two)
-    int32_t P = 1;
-    while (P < tail) P <<= 1;
-    for (int j = tail + lane; j < P; j += kWave) L.queue[j] = 0x7FFFFFFF;
-    wave_sync();
-    for (int k = 2; k <= P; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int t = lane; t < (P >> 1); t += kWave) {
-          const int i1 = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-          const int i2 = i1 | j;
-          const bool asc = (i1 & k) == 0;
-          const int32_t x = L.queue[i1], y = L.queue[i2];
-          if ((x > y) == asc) {
-            L.queue[i1] = y;
-            L.queue[i2] = x;
-          }
-        }
-        wave_sync();
-      }
+    unsigned long long ex = 0;
+    if (lane == 0) ex = __hip_atomic_load(&A.ctr[16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (first_lane_u64(shfl_u64(ex, 0))) {  // every item is claimed: leave the rest
+      const int nd = __popcll(defer);
+      unsigned long long s0 = 0;
+      if (lane == 0) s0 = atomicAdd(&A.ctr[12], (unsigned long long)nd);
+      s0 = first_lane_u64(shfl_u64(s0, 0));
+      if ((defer >> lane) & 1ull)
+        A.dq[s0 + (unsigned long long)__popcll(defer & ((1ull << lane) - 1ull))] =
+            (uint32_t)(batch + (unsigned long long)lane);
+      break;
     }
-    if (cpos + (unsigned long long)tail > cend) {
-      const unsigned long long want = max((unsigned long long)tail, kChunk);
-      unsigned long long b = 0;
-      if (lane == 0) b = atomicAdd(&A.ctr[1], want);
-      cpos = first_lane_u64(shfl_u64(b, 0));
-      cend = cpos + want;
-    }
-    const unsigned long long pos = cpos;
-    cpos += (unsigned long long)tail;
-    w_tot += (unsigned long long)tail;
-    if (pos + (unsigned long long)tail <= A.arena_cap)
-      for (int j = lane; j < tail; j += kWave) A.arena[pos + j] = L.queue[j];
-    if (lane == 0) {
-      A.start[il] = (int64_t)pos;
-      A.len[il] = tail;
-    }
-    w_ex += s_ex;
-    w_lv += s_lv;
-    wave_sync();
+    const int dl = __ffsll(defer) - 1;
+    defer &= defer - 1;
+    wave_path(A, L, batch + (unsigned long long)dl, cpos, cend, w_tot, w_ex, w_lv);
   }
-  w_ex = wave_sum(w_ex);
-  w_lv = wave_sum(w_lv);
-  if (lane == 0) {
-    if (w_ex) atomicAdd(&A.ctr[3], w_ex);
-    if (w_lv) atomicAdd(&A.ctr[4], w_lv);
-    if (w_tot) atomicAdd(&A.ctr[10], w_tot);
+  flush_counts(A, w_ex, w_lv, w_tot);
+}
+
+// IC sets, second launch: the items left in A.dq, one per wavefront at a time
+// (ctr[13]).
+__global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_rest(SampleArgs A) {
+  __shared__ WaveLds lds_all[kSmallBlock / kWave];
+  WaveLds& L = lds_all[threadIdx.x / kWave];
+  const int lane = lane_id();
+  unsigned long long w_ex = 0, w_lv = 0, w_tot = 0, cpos = 0, cend = 0;
+  const unsigned long long nq = A.ctr[12];  // final: the first launch is done
+  for (;;) {
+    unsigned long long d = 0;
+    if (lane == 0) d = atomicAdd(&A.ctr[13], 1ull);
+    d = first_lane_u64(shfl_u64(d, 0));
+    if (d >= nq) break;
+    wave_path(A, L, A.dq[d], cpos, cend, w_tot, w_ex, w_lv);
   }
+  flush_counts(A, w_ex, w_lv, w_tot);
 }
 
 // ------------------------------------------------------------------ large sets
@@ -1336,15 +1407,16 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
   // per-position metadata: start (i64), len (i32), big list (u32), counters,
   // hand-off snapshots
   const uint32_t nhand = (uint32_t)std::min<uint64_t>(cnt, kMaxHandoff);
-  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 128 + 256 +
-                            (size_t)nhand * sizeof(Handoff) + 64;
+  const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 256 + 256 +
+                            (size_t)nhand * sizeof(Handoff) + 64 + (size_t)cnt * 4 + 64;
   void* mp = nullptr;
   IM_TRY(scratch(s, kSlotSampleMeta, meta_bytes, &mp));
   unsigned long long* ctr = (unsigned long long*)mp;
-  int64_t* start = (int64_t*)((char*)mp + 128);
+  int64_t* start = (int64_t*)((char*)mp + 256);
   int32_t* lens = (int32_t*)(start + cnt);
   uint32_t* big_list = (uint32_t*)(lens + cnt);
   Handoff* handoff = (Handoff*)(((uintptr_t)(big_list + cnt) + 63) & ~(uintptr_t)63);
+  uint32_t* dq = (uint32_t*)(((uintptr_t)(handoff + nhand) + 63) & ~(uintptr_t)63);
 
   static thread_local int64_t last_total = 0;
   // room for the sets plus the unfilled tails of the per-wave arena chunks
@@ -1379,8 +1451,9 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
     A.len = lens;
     A.big_list = big_list;
     A.handoff = handoff;
+    A.dq = dq;
     A.ctr = ctr;
-    IM_HIP(hipMemsetAsync(ctr, 0, 128, s));
+    IM_HIP(hipMemsetAsync(ctr, 0, 256, s));
     if (timed) IM_HIP(hipEventRecord(ev[0], s));
     if (!task_ic.empty()) {
       SampleArgs Ai = A;
@@ -1390,6 +1463,8 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       Ai.count = (uint64_t)seg_ic.back();
       const int blocks = di.num_cus * 8;
       k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(Ai);
+      IM_HIP(hipGetLastError());
+      k_sample_ic_rest<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(Ai);
       IM_HIP(hipGetLastError());
     }
     if (!task_lt.empty()) {
