@@ -8,8 +8,7 @@ and greedy max-k-cover.  Default workload: R-MAT scale 20 (2^20 vertices,
 k = 100.  Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line on stdout.  `roofline` describes the dominant kernel
-(algorithmic bytes per launch over its event-timed duration; the IC main path
-is the pair k_sample_ic_small + k_sample_ic_rest, timed together); `cpu_baseline`
+(algorithmic bytes per launch over its event-timed duration); `cpu_baseline`
 times the single-threaded CPU oracle on a bounded sample of the same work.
 Progress goes to stderr.
 """
@@ -45,7 +44,7 @@ def sampling_bytes(sets, total, examined, live, run_length=True):
 # holds lines "traffic <kernel> bytes_per_launch=<B> source_sha256=<H>", taken
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled against a plain copy.
 # A figure counts only while the kernel's sources hash to H.
-MAIN_IC = "k_sample_ic_small+k_sample_ic_rest"   # one timed pair of launches
+MAIN_IC = "k_sample_ic_small"
 KERNEL_SOURCES = {
     MAIN_IC: ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],
     "k_sample_big": ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],

@@ -77,14 +77,11 @@ struct SampleArgs {
   int32_t* __restrict__ len;     // per output position: size (-1 while on the large path)
   uint32_t* __restrict__ big_list;       // output positions handed to the large path
   struct Handoff* __restrict__ handoff;  // kMaxHandoff snapshots (IC)
-  uint32_t* __restrict__ dq;             // IC: work items left to the second launch
-                                         // (count entries)
   unsigned long long* __restrict__ ctr;  // [0] IC work, [1] cursor, [2] big count,
                                          // [3] examined, [4] live, [5] big work,
                                          // [6] big examined, [7] big live, [8] big total,
                                          // [9] examined in abandoned rounds,
-                                         // [10] sum of set sizes, [11] LT work,
-                                         // [12] dq entries, [13] dq entries taken;
+                                         // [10] sum of set sizes, [11] LT work;
                                          // [16] (own cache line) every IC item claimed
 };
 
@@ -707,12 +704,13 @@ __device__ __forceinline__ void wave_path(const SampleArgs& A, WaveLds& L,
   wave_sync();
 }
 
-// IC sets, first launch: each wavefront claims 64 work items at a time
-// (ctr[0]), runs the lane pass over them and then the wavefront path over
-// the items the lane pass left, in order.  Once every item is claimed
-// (ctr[16] set by the first wavefront to find none), a wavefront appends the
-// items it has not started to A.dq (reserved on ctr[12]) and stops, so no
-// wavefront works through a long private backlog while others idle.
+// IC sets: each wavefront claims 64 work items at a time (ctr[0]), runs the
+// lane pass over them and then the wavefront path over the items the lane
+// pass left, in order.  Once every item is claimed (ctr[16], set by the first
+// wavefront to find none), a wavefront hands the items it has not started to
+// the large-set launch and stops, so no wavefront works through a long
+// private backlog while others idle; that launch takes its sets in list
+// order, the long handed-off sets first.
 __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(SampleArgs A) {
   __shared__ WaveLds lds_all[kSmallBlock / kWave];
   WaveLds& L = lds_all[threadIdx.x / kWave];
@@ -737,14 +735,32 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
     }
     unsigned long long ex = 0;
     if (lane == 0) ex = __hip_atomic_load(&A.ctr[16], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (first_lane_u64(shfl_u64(ex, 0))) {  // every item is claimed: leave the rest
-      const int nd = __popcll(defer);
-      unsigned long long s0 = 0;
-      if (lane == 0) s0 = atomicAdd(&A.ctr[12], (unsigned long long)nd);
-      s0 = first_lane_u64(shfl_u64(s0, 0));
-      if ((defer >> lane) & 1ull)
-        A.dq[s0 + (unsigned long long)__popcll(defer & ((1ull << lane) - 1ull))] =
-            (uint32_t)(batch + (unsigned long long)lane);
+    if (first_lane_u64(shfl_u64(ex, 0))) {
+      // every item is claimed: the sets not started go to the large-set
+      // launch, after the ones handed off so far, with a snapshot of just
+      // their root
+      uint32_t s0 = 0;
+      if (lane == 0) s0 = (uint32_t)atomicAdd(&A.ctr[2], (unsigned long long)__popcll(defer));
+      s0 = __shfl(s0, 0, kWave);
+      if ((defer >> lane) & 1ull) {
+        const uint32_t slot = s0 + (uint32_t)__popcll(defer & ((1ull << lane) - 1ull));
+        int tk;
+        uint32_t i;
+        int64_t il;
+        locate_work(A, batch + (unsigned long long)lane, &tk, &i, &il);
+        const GView G = view_of(A.tasks[tk]);
+        if (slot < kMaxHandoff) {
+          Handoff& H = A.handoff[slot];
+          H.mem[0] = (int32_t)scale_draw(
+              draw1(((uint64_t)G.seed_hi << 32) | G.seed_lo, kTagRoot, G.stream, 0u, i), G.n);
+          H.head = 0;
+          H.tail = 1;
+          H.ex = 0;
+          H.lv = 0;
+        }
+        A.big_list[slot] = (uint32_t)il;
+        A.len[il] = -1;
+      }
       break;
     }
     const int dl = __ffsll(defer) - 1;
@@ -754,23 +770,6 @@ __global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_small(Samp
   flush_counts(A, w_ex, w_lv, w_tot);
 }
 
-// IC sets, second launch: the items left in A.dq, one per wavefront at a time
-// (ctr[13]).
-__global__ __launch_bounds__(kSmallBlock) IM_IC_ATTR void k_sample_ic_rest(SampleArgs A) {
-  __shared__ WaveLds lds_all[kSmallBlock / kWave];
-  WaveLds& L = lds_all[threadIdx.x / kWave];
-  const int lane = lane_id();
-  unsigned long long w_ex = 0, w_lv = 0, w_tot = 0, cpos = 0, cend = 0;
-  const unsigned long long nq = A.ctr[12];  // final: the first launch is done
-  for (;;) {
-    unsigned long long d = 0;
-    if (lane == 0) d = atomicAdd(&A.ctr[13], 1ull);
-    d = first_lane_u64(shfl_u64(d, 0));
-    if (d >= nq) break;
-    wave_path(A, L, A.dq[d], cpos, cend, w_tot, w_ex, w_lv);
-  }
-  flush_counts(A, w_ex, w_lv, w_tot);
-}
 
 // ------------------------------------------------------------------ large sets
 struct BigArgs {
@@ -1408,7 +1407,7 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
   // hand-off snapshots
   const uint32_t nhand = (uint32_t)std::min<uint64_t>(cnt, kMaxHandoff);
   const size_t meta_bytes = (size_t)cnt * 8 + (size_t)cnt * 4 + (size_t)cnt * 4 + 256 + 256 +
-                            (size_t)nhand * sizeof(Handoff) + 64 + (size_t)cnt * 4 + 64;
+                            (size_t)nhand * sizeof(Handoff) + 64;
   void* mp = nullptr;
   IM_TRY(scratch(s, kSlotSampleMeta, meta_bytes, &mp));
   unsigned long long* ctr = (unsigned long long*)mp;
@@ -1416,7 +1415,6 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
   int32_t* lens = (int32_t*)(start + cnt);
   uint32_t* big_list = (uint32_t*)(lens + cnt);
   Handoff* handoff = (Handoff*)(((uintptr_t)(big_list + cnt) + 63) & ~(uintptr_t)63);
-  uint32_t* dq = (uint32_t*)(((uintptr_t)(handoff + nhand) + 63) & ~(uintptr_t)63);
 
   static thread_local int64_t last_total = 0;
   // room for the sets plus the unfilled tails of the per-wave arena chunks
@@ -1451,7 +1449,6 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
     A.len = lens;
     A.big_list = big_list;
     A.handoff = handoff;
-    A.dq = dq;
     A.ctr = ctr;
     IM_HIP(hipMemsetAsync(ctr, 0, 256, s));
     if (timed) IM_HIP(hipEventRecord(ev[0], s));
@@ -1463,8 +1460,6 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       Ai.count = (uint64_t)seg_ic.back();
       const int blocks = di.num_cus * 8;
       k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(Ai);
-      IM_HIP(hipGetLastError());
-      k_sample_ic_rest<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(Ai);
       IM_HIP(hipGetLastError());
     }
     if (!task_lt.empty()) {
