@@ -78,7 +78,10 @@ typedef struct {
   int64_t examined;        /* IC: in-edges examined; LT: binary-search probes
                               charged as ceil(log2(indeg+1)) per expanded vertex */
   int64_t live;            /* IC: live in-edges found; LT: in-edges taken */
-  int64_t large_sets;      /* sets finished by the large-set path */
+  int64_t large_sets;      /* sets finished by the large-set launch: those that
+                              outgrew the main launch's LDS tier, and those not yet
+                              started when its last batch was claimed (this part
+                              depends on timing; the sets themselves do not) */
   int64_t large_total;     /* ... their summed sizes */
   int64_t large_examined;  /* ... their examined count */
   int64_t large_live;      /* ... their live count */

@@ -52,8 +52,17 @@ struct BigCfg {
   static constexpr int kH = 1 << kBitsT;             // members kH / 2
   static constexpr int kCap = kH / 2;
   static constexpr int kPerCu = kPerCuT;             // workers per CU
+  // LDS pool of the hash, member list and stage; once a set is complete it
+  // holds the sort of up to kSortCap members (the 256-thread shape keeps its
+  // pool within the 20 KB that 8 workgroups per CU allow)
+  static constexpr int kSortCap = kBlockT >= 256 ? kH : (2 * kH < 2048 ? 2 * kH : 2048);
+  static constexpr int kPool =
+      kH + kCap + kStage > kSortCap ? kH + kCap + kStage : kSortCap;
 };
-using BigNarrow = BigCfg<64, 10, 24>;
+#ifndef IM_NARROW_BITS
+#define IM_NARROW_BITS 10
+#endif
+using BigNarrow = BigCfg<64, IM_NARROW_BITS, 24>;
 using BigWide = BigCfg<256, 11, 8>;
 constexpr uint32_t kMaxHandoff = 1u << 16;  // large sets that resume from a snapshot
 constexpr int kLtH = 2048;                  // per-lane HBM hash slots (LT)
@@ -865,13 +874,40 @@ __device__ __forceinline__ void big_push(int32_t e, int32_t* stage, int32_t* s_n
     set_insert<C>(S, in_src[e]);
 }
 
-// Every thread of the block must call.
+// Every thread of the block must call.  Each thread takes kFlushBatch staged
+// edges at a time: their sources are loaded together and, in HBM mode, their
+// bitmap atomics issued together before any result is used (a source seen
+// twice is appended once: the second atomicOr returns the bit set).
+#ifndef IM_FLUSH_BATCH
+#define IM_FLUSH_BATCH 8
+#endif
+constexpr int kFlushBatch = IM_FLUSH_BATCH;
 template <class C>
 __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
                                           const int32_t* __restrict__ in_src, const BigSet& S) {
   __syncthreads();
   const int32_t ns = min(*s_nst, C::kStage);
-  for (int32_t k = threadIdx.x; k < ns; k += C::kBlock) set_insert<C>(S, in_src[stage[k]]);
+  for (int32_t k0 = threadIdx.x; k0 < ns; k0 += kFlushBatch * C::kBlock) {
+    int32_t u[kFlushBatch];
+#pragma unroll
+    for (int q = 0; q < kFlushBatch; ++q) {
+      const int32_t k = k0 + q * C::kBlock;
+      u[q] = k < ns ? in_src[stage[k]] : -1;
+    }
+    if (S.lds) {
+#pragma unroll
+      for (int q = 0; q < kFlushBatch; ++q)
+        if (u[q] >= 0) set_insert<C>(S, u[q]);
+    } else {
+      uint32_t old[kFlushBatch];
+#pragma unroll
+      for (int q = 0; q < kFlushBatch; ++q)
+        old[q] = u[q] >= 0 ? atomicOr(&S.bm[u[q] >> 5], 1u << (u[q] & 31)) : 0u;
+#pragma unroll
+      for (int q = 0; q < kFlushBatch; ++q)
+        if (u[q] >= 0 && !(old[q] & (1u << (u[q] & 31)))) S.queue[atomicAdd(S.s_tail, 1)] = u[q];
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) *s_nst = 0;
   __syncthreads();
@@ -879,7 +915,8 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
 
 // One workgroup per large set: visited set and members in LDS while they fit
 // (sorted in LDS), else the worker's private bitmap and queue in HBM (sorted
-// in LDS up to C::kH members, else read in order from the bitmap).
+// in LDS up to C::kSortCap members, else read in order from the bitmap, a
+// pass over all n bits).
 template <class C>
 __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
   __shared__ int32_t pre[C::kBlock];
@@ -887,9 +924,10 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
   __shared__ int32_t ea[C::kBlock];
   __shared__ int32_t eb[C::kBlock];
   __shared__ int64_t scan_lds[C::kBlock / kWave + 1];
-  __shared__ int32_t mhash[C::kH];  // LDS-mode hash; sort buffer in HBM mode
-  __shared__ int32_t mq[C::kCap];
-  __shared__ int32_t stage[C::kStage];
+  __shared__ int32_t pool[C::kPool];  // LDS-mode hash | members | stage; sort buffer
+  int32_t* const mhash = pool;
+  int32_t* const mq = pool + C::kH;
+  int32_t* const stage = pool + C::kH + C::kCap;
   __shared__ int32_t s_nst;
   __shared__ int32_t s_tail;
   __shared__ int32_t s_over;
@@ -1075,10 +1113,10 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     __syncthreads();
     const unsigned long long pos = s_pos;
     const bool fits = pos + (unsigned long long)tail <= A.arena_cap;
-    if (S.lds || tail <= C::kH) {
+    if (S.lds || tail <= C::kSortCap) {
       // LDS mode: the members are in mq (tail <= C::kCap); HBM mode: copy them
-      // into the (now unused) hash array
-      int32_t* sorted = S.lds ? mq : mhash;
+      // into the (now unused) LDS pool
+      int32_t* sorted = S.lds ? mq : pool;
       int32_t P = 1;
       while (P < tail) P <<= 1;
       for (int j = t; j < P; j += C::kBlock)
