@@ -1341,8 +1341,12 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
 // ------------------------------------------------------------------ gather
 constexpr int kGatherBlock = 256;
 
-// One wavefront per set: copies it from the arena to its canonical place,
-// sorting it on the way when it was written unsorted (LT walks).
+constexpr int32_t kGatherLane = 16;  // sets up to this size are copied by one lane
+
+// Copies every set from the arena to its canonical place.  Sets written in
+// order (IC): one lane per set, 64 consecutive sets per wavefront, the few
+// longer than kGatherLane copied by the whole wavefront.  Sets written
+// unsorted (LT walks): one wavefront per set, sorting it on the way.
 __global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
                                                          const int64_t* __restrict__ start,
                                                          const int32_t* __restrict__ len,
@@ -1353,6 +1357,32 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
   __shared__ int32_t buf_all[kGatherBlock / kWave][kGatherSortCap];
   int32_t* buf = buf_all[threadIdx.x / kWave];
   const int lane = lane_id();
+  if (!sort_small) {
+    const uint64_t w0 = ((uint64_t)blockIdx.x * kGatherBlock + threadIdx.x) / kWave * kWave;
+    const uint64_t step = (uint64_t)gridDim.x * kGatherBlock;
+    for (uint64_t base = w0; base < count; base += step) {  // wavefront-uniform
+      const uint64_t sid = base + (uint64_t)lane;
+      int32_t L = 0;
+      int64_t a = 0, d = 0;
+      if (sid < count) {
+        L = len[sid];
+        a = start[sid];
+        d = off[sid];
+      }
+      const bool mine = L <= kGatherLane;
+      if (mine)
+        for (int32_t j = 0; j < L; ++j) mem[d + j] = arena[a + j];
+      unsigned long long todo = __ballot(!mine);
+      while (todo) {
+        const int src = __ffsll(todo) - 1;
+        todo &= todo - 1;
+        const int32_t Ls = __shfl(L, src, kWave);
+        const int64_t as = shfl_i64(a, src), ds = shfl_i64(d, src);
+        for (int32_t j = lane; j < Ls; j += kWave) mem[ds + j] = arena[as + j];
+      }
+    }
+    return;
+  }
   const uint32_t wid = (blockIdx.x * kGatherBlock + threadIdx.x) / kWave;
   const uint32_t nw = gridDim.x * (kGatherBlock / kWave);
   for (uint32_t s = wid; s < count; s += nw) {
