@@ -102,6 +102,35 @@ const char* im_last_error(void);
 int im_release(void);
 
 /*
+ * Launch-shape knobs (the batched and served paths' tile choices; the
+ * autotuner in the Python package sets them from measurements).  No setting
+ * changes any result: the sets, seeds, gains and coverage are the same bit
+ * for bit, only the time differs.  Process-wide; read at each call.
+ *   IM_TUNE_SAMPLE_BLOCKS  workgroups (4 wavefronts) per CU of the main IC
+ *                          sampling launch, 1..64 (default 8)
+ *   IM_TUNE_BIG_SHAPE      large-set launch: 1 one wavefront per set (24 per
+ *                          CU), 2 256 threads per set (8 per CU), 0 automatic
+ *                          (one wavefront unless more than 1/8 of the
+ *                          launch's sets were handed off) (default 0)
+ *   IM_TUNE_APPLY_BLOCKS   workgroups (1024 threads) per CU of the plain
+ *                          greedy's aggregated apply, 1..16 (default 1)
+ *   IM_TUNE_DENSE_RATIO    members per vertex above which the covering
+ *                          subsets take the dense form, >= 0 (0: always
+ *                          dense; default 256)
+ * value -1 restores the default.  Returns IM_EINVAL for an unknown key or a
+ * value outside its range (nothing changes then).  im_tune_get writes the
+ * value in effect.
+ */
+typedef enum {
+  IM_TUNE_SAMPLE_BLOCKS = 0,
+  IM_TUNE_BIG_SHAPE = 1,
+  IM_TUNE_APPLY_BLOCKS = 2,
+  IM_TUNE_DENSE_RATIO = 3
+} im_tune_key;
+int im_tune_set(int32_t key, int64_t value);
+int im_tune_get(int32_t key, int64_t* value);
+
+/*
  * Graph ingest (Sec. 2: the IC and LT diffusion models).
  * weight[e] is the IC probability p(u,v) in [0,1], or the LT weight w(u,v) >= 0
  * (the model assumes the in-weights of a vertex sum to 1).  Writes thr:

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libim.so")
 IM_OK, IM_EINVAL, IM_ERANGE, IM_ENOMEM, IM_EDEVICE = 0, -1, -2, -3, -4
 IC, LT = 0, 1
 SEL_GREEDY, SEL_GREEDIRIS = 0, 1
+TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO = 0, 1, 2, 3
 
 _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM",
            IM_EDEVICE: "IM_EDEVICE"}
@@ -26,7 +27,7 @@ _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM
 # every symbol the header declares
 EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
            "im_build_incidence", "im_greedy_cover", "im_randgreedi", "im_stream_cover",
-           "im_solve", "im_solve_batch", "im_imm_plan")
+           "im_solve", "im_solve_batch", "im_imm_plan", "im_tune_set", "im_tune_get")
 
 
 class ImError(RuntimeError):
@@ -107,6 +108,8 @@ def lib():
         L.im_solve_batch.argtypes = [C.POINTER(_Task), I32, P, P, P, P, C.POINTER(_BatchStats),
                                      P]
         L.im_imm_plan.argtypes = [I32, I32, D, C.POINTER(_ImmPlan)]
+        L.im_tune_set.argtypes = [I32, I64]
+        L.im_tune_get.argtypes = [I32, C.POINTER(C.c_int64)]
         for f in EXPORTS[2:]:
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -334,6 +337,17 @@ def sample_into(g: Graph, seed: int, stream_tag: int, first: int, count: int,
 
 def release():
     _check(lib().im_release(), "im_release")
+
+
+def tune_set(key: int, value: int):
+    """Sets a launch-shape knob (TUNE_*; -1 restores its default)."""
+    _check(lib().im_tune_set(key, value), "im_tune_set")
+
+
+def tune_get(key: int) -> int:
+    v = C.c_int64()
+    _check(lib().im_tune_get(key, C.byref(v)), "im_tune_get")
+    return int(v.value)
 
 
 def version() -> str:

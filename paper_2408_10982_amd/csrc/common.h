@@ -217,6 +217,9 @@ enum Slot {
   kSlotCount
 };
 
+// Launch-shape knob in effect (im_tune_set; the default when unset).
+int64_t tune(im_tune_key key);
+
 struct DeviceInfo {
   int device;
   int num_cus;

@@ -38,12 +38,6 @@ constexpr int kRecountPicks = 2;   // picks that may rebuild the counts
 #define IM_APPLY_ENTRIES 4
 #endif
 constexpr int kApplyEntries = IM_APPLY_ENTRIES;
-#ifndef IM_AGG_BLOCKS_PER_CU
-#define IM_AGG_BLOCKS_PER_CU 1
-#endif
-#ifndef IM_AGG_CU_DIV
-#define IM_AGG_CU_DIV 1
-#endif
 
 __device__ __forceinline__ int64_t part_lo(const CoverArgs& A, int p) {
   return A.pbase ? A.pbase[p] : 0;
@@ -520,7 +514,7 @@ int launch_cover(CoverArgs& A, hipStream_t s) {
   IM_HIP(hipGetLastError());
   const unsigned arg_blocks = (unsigned)std::max<int64_t>(((int64_t)A.n + kArgTile - 1) / kArgTile, 1);
   const unsigned apply_blocks = (unsigned)di.num_cus * 4;
-  const unsigned agg_blocks = (unsigned)(di.num_cus * IM_AGG_BLOCKS_PER_CU / IM_AGG_CU_DIV);
+  const unsigned agg_blocks = (unsigned)(di.num_cus * tune(IM_TUNE_APPLY_BLOCKS));
   // A plain one-partition cover rebuilds all counts after one of its first
   // kRecountPicks picks if that pick covers at least count / 64 samples (at
   // 2^20 weighted-cascade sets the first pick newly covers 41 K samples

@@ -395,11 +395,12 @@ static int64_t pair_budget(int64_t total) {
   return std::max<int64_t>(std::min<int64_t>(total, fit), (int64_t)1 << 24);
 }
 
-// Members per vertex above which a collection takes the dense form;
-// IM_INCIDENCE_DENSE_RATIO overrides it (0: always dense), for the tests.
+// Members per vertex above which a collection takes the dense form
+// (IM_TUNE_DENSE_RATIO); IM_INCIDENCE_DENSE_RATIO overrides it (0: always
+// dense), for the tests.
 static int64_t dense_ratio() {
   if (const char* env = getenv("IM_INCIDENCE_DENSE_RATIO")) return atoll(env);
-  return 256;
+  return tune(IM_TUNE_DENSE_RATIO);
 }
 
 int build_incidence(const IncSrc& S, int32_t nv, int64_t* inc_off, int32_t* inc_mem,

@@ -1,4 +1,5 @@
 // runtime.hip -- error text, per-stream scratch, device facts, device-wide scan.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
@@ -190,9 +191,35 @@ int exclusive_scan_u32_to_i64(const uint32_t* in, int64_t n, int64_t* out, hipSt
   return exclusive_scan_impl<uint32_t>(in, n, out, s);
 }
 
+namespace {
+constexpr int kTuneKeys = 4;
+constexpr int64_t kTuneDefault[kTuneKeys] = {8, 0, 1, 256};
+constexpr int64_t kTuneMin[kTuneKeys] = {1, 0, 1, 0};
+constexpr int64_t kTuneMax[kTuneKeys] = {64, 2, 16, (int64_t)1 << 40};
+std::atomic<int64_t> g_tune[kTuneKeys] = {{-1}, {-1}, {-1}, {-1}};
+}  // namespace
+
+int64_t tune(im_tune_key key) {
+  const int64_t v = g_tune[key].load(std::memory_order_relaxed);
+  return v < 0 ? kTuneDefault[key] : v;
+}
+
 }  // namespace im
 
 extern "C" {
+
+int im_tune_set(int32_t key, int64_t value) {
+  if (key < 0 || key >= im::kTuneKeys) return IM_EINVAL;
+  if (value != -1 && (value < im::kTuneMin[key] || value > im::kTuneMax[key])) return IM_EINVAL;
+  im::g_tune[key].store(value, std::memory_order_relaxed);
+  return IM_OK;
+}
+
+int im_tune_get(int32_t key, int64_t* value) {
+  if (key < 0 || key >= im::kTuneKeys || !value) return IM_EINVAL;
+  *value = im::tune((im_tune_key)key);
+  return IM_OK;
+}
 
 const char* im_version(void) { return "im-mi355x 0.1 (gfx950)"; }
 

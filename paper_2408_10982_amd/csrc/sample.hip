@@ -1526,7 +1526,7 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       Ai.seg_task = d_task_ic;
       Ai.nseg = (int32_t)task_ic.size();
       Ai.count = (uint64_t)seg_ic.back();
-      const int blocks = di.num_cus * 8;
+      const int blocks = di.num_cus * (int)tune(IM_TUNE_SAMPLE_BLOCKS);
       k_sample_ic_small<<<dim3(blocks), dim3(kSmallBlock), 0, s>>>(Ai);
       IM_HIP(hipGetLastError());
     }
@@ -1564,7 +1564,8 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       // between uses (each set clears its own bits), so only a new buffer
       // needs clearing
       // one wavefront per set unless most sets were handed off
-      const bool narrow = (uint64_t)nbig * 8 <= (uint64_t)cnt;
+      const int64_t shape = tune(IM_TUNE_BIG_SHAPE);
+      const bool narrow = shape == 1 || (shape == 0 && (uint64_t)nbig * 8 <= (uint64_t)cnt);
       const uint32_t max_workers =
           (uint32_t)di.num_cus * (narrow ? BigNarrow::kPerCu : BigWide::kPerCu);
       const size_t budget = (size_t)IM_BIG_BUDGET_GIB << 30;

@@ -57,3 +57,30 @@ def test_invalid_arguments_rejected_before_device_work():
     st = L.im_sample_rrr(None, ctypes.c_uint64(0), ctypes.c_uint32(0), ctypes.c_int64(0),
                          ctypes.c_int64(1), None, None, ctypes.c_int64(0), None, None, None)
     assert st == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_tune_knobs_validate_and_round_trip():
+    """Launch-shape knobs: defaults, range checks (nothing changes on a
+    rejected value), set/get, -1 restores the default.  Host only."""
+    L = ctypes.CDLL(LIB)
+    L.im_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    L.im_tune_get.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    v = ctypes.c_int64()
+
+    def get(key):
+        assert L.im_tune_get(key, ctypes.byref(v)) == 0
+        return v.value
+
+    defaults = {0: 8, 1: 0, 2: 1, 3: 256}
+    assert {k: get(k) for k in defaults} == defaults
+    for key, bad in ((0, 0), (0, 65), (1, 3), (2, 0), (2, 17), (3, -2), (4, 1), (-1, 1)):
+        assert L.im_tune_set(key, bad) == -1, (key, bad)
+    assert {k: get(k) for k in defaults} == defaults
+    assert L.im_tune_get(9, ctypes.byref(v)) == -1
+    assert L.im_tune_get(0, None) == -1
+    for key, good in ((0, 12), (1, 2), (2, 4), (3, 0)):
+        assert L.im_tune_set(key, good) == 0
+        assert get(key) == good
+        assert L.im_tune_set(key, -1) == 0
+        assert get(key) == defaults[key]

@@ -367,3 +367,42 @@ def test_serving_failed_query_raises(im, monkeypatch):
         server.close()
     assert qs[1].error is not None and not qs[1].result
     assert qs[0].result["seeds"] and qs[2].result["seeds"]
+
+
+def test_autotune_keeps_results(im):
+    """Every launch-shape knob setting gives the same sets, seeds, gains and
+    coverage (the tuner checks the signature at every trial; rmat14_wc hands
+    sets to the large-set launch), and the tuned result equals the oracle's."""
+    _say("autotune")
+    from paper_2408_10982_amd import autotune as AT
+    g = GRAPHS["rmat14_wc"]()
+    G = _prep(im, g)
+    count, k, seed = 20000, 30, 41
+
+    def run():
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = im.sample_rrr(G, seed, 0, 0, count)
+        io, imem = im.build_incidence(g.n, r)
+        s_, gn, ns, cv = im.greedy_cover(g.n, r, io, imem, k)
+        e1.record()
+        torch.cuda.synchronize()
+        n = int(_np(ns)[0])
+        sig = (_np(r.off).tobytes(), _np(r.mem).tobytes(), tuple(_np(s_)[:n].tolist()),
+               tuple(_np(gn)[:n].tolist()), int(_np(cv)[0]))
+        return e0.elapsed_time(e1), sig
+
+    try:
+        res = AT.tune(run, reps=1)
+        _, sig = run()
+    finally:
+        AT.reset()
+    assert set(res["settings"]) == set(AT.KNOBS)
+    assert len(res["trials"]) == 1 + sum(len(c) - 1 for _, c in AT.KNOBS.values())
+    assert AT.current() == {"sample_blocks": 8, "big_shape": 0, "apply_blocks": 1,
+                            "dense_ratio": 256}
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), seed, 0, 0, count)
+    oio, oim = O.incidence(g.n, o)
+    os_, og, oc = O.greedy(g.n, count, oio, oim, k)
+    assert sig[2] == tuple(os_.tolist()) and sig[3] == tuple(og.tolist()) and sig[4] == oc
+
