@@ -1119,8 +1119,22 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
       int32_t* sorted = S.lds ? mq : pool;
       int32_t P = 1;
       while (P < tail) P <<= 1;
-      for (int j = t; j < P; j += C::kBlock)
-        if (!S.lds || j >= tail) sorted[j] = j < tail ? queue[j] : 0x7FFFFFFF;
+      if (S.lds) {
+        for (int j = tail + t; j < P; j += C::kBlock) sorted[j] = 0x7FFFFFFF;
+      } else {  // the HBM queue's loads issued 8 at a time
+        constexpr int kU = 8;
+        for (int j0 = t; j0 < P; j0 += kU * C::kBlock) {
+          int32_t x[kU];
+#pragma unroll
+          for (int q = 0; q < kU; ++q) {
+            const int j = j0 + q * C::kBlock;
+            x[q] = j < tail ? queue[j] : 0x7FFFFFFF;
+          }
+#pragma unroll
+          for (int q = 0; q < kU; ++q)
+            if (j0 + q * C::kBlock < P) sorted[j0 + q * C::kBlock] = x[q];
+        }
+      }
       __syncthreads();
       for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -1139,6 +1153,8 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
       }
       if (fits)
         for (int j = t; j < tail; j += C::kBlock) A.arena[pos + j] = sorted[j];
+      if (!S.lds)  // clear the set's bits from the LDS copy of its members
+        for (int j = t; j < tail; j += C::kBlock) bm[sorted[j] >> 5] = 0u;
     } else {
       // members in ascending order straight from the bitmap
       const uint32_t per = (Bg.nwords + C::kBlock - 1) / C::kBlock;
@@ -1160,7 +1176,7 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
       }
     }
     __syncthreads();
-    if (!S.lds)
+    if (!S.lds && tail > C::kSortCap)  // (smaller sets were cleared above)
       for (int j = t; j < tail; j += C::kBlock) bm[queue[j] >> 5] = 0u;
     if (t == 0) {
       A.start[il] = (int64_t)pos;
