@@ -126,22 +126,55 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Cross-lane moves by DPP (register to register, no LDS): lane i reads lane
+// i - n of its row of 16 (row_shr:n, dpp_ctrl 0x110 + n) or the last lane of
+// row 0 / row 1 (row_bcast:15 = 0x142, row_bcast:31 = 0x143, for the rows in
+// RowMask); a lane without a source reads 0.  Every lane must be active.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, Ctrl, RowMask, 0xF, false);
+}
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = dpp_u32<Ctrl, RowMask>((uint32_t)v);
+  const uint32_t hi = dpp_u32<Ctrl, RowMask>((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+template <int Ctrl, int RowMask, typename T>
+__device__ __forceinline__ T dpp_move(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+  if constexpr (sizeof(T) == 4)
+    return (T)dpp_u32<Ctrl, RowMask>((uint32_t)v);
+  else
+    return (T)dpp_u64<Ctrl, RowMask>((uint64_t)v);
+}
+
+// Inclusive prefix sum over the wavefront's 64 lanes: within each row of 16
+// by shifts of 1, 2, 4, 8; then rows 1 and 3 add the last lane of rows 0 and
+// 2, and rows 2 and 3 add lane 31.  Every lane must be active.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T y = __shfl_up(x, d, kWave);
-    if (l >= d) x += y;
-  }
+  x += dpp_move<0x111, 0xF>(x);
+  x += dpp_move<0x112, 0xF>(x);
+  x += dpp_move<0x114, 0xF>(x);
+  x += dpp_move<0x118, 0xF>(x);
+  x += dpp_move<0x142, 0xA>(x);
+  x += dpp_move<0x143, 0xC>(x);
   return x;
 }
 
+// Sum over the wavefront, the same in every lane.  Every lane must be active.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
+  const T incl = wave_inclusive_scan(x);
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  } else {
+    const uint64_t u = (uint64_t)incl;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, kWave - 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), kWave - 1);
+    return (T)(((uint64_t)hi << 32) | lo);
+  }
 }
 
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {

@@ -36,6 +36,9 @@ namespace im {
 
 constexpr int kSmallBlock = 256;            // 4 waves, each its own sample
 constexpr int kSmallH = 512;                // LDS hash slots per wave
+#ifndef IM_TINY
+#define IM_TINY 16                          // members of a lane-pass set
+#endif
 constexpr int kSmallCap = 256;              // members before handing off
 constexpr int kStage = 128;                 // staged live in-edges per wave
 // Large sets: two shapes of the large-set kernel, chosen per launch.
@@ -264,10 +267,22 @@ __device__ __forceinline__ void rl_walks(bool rl, uint32_t v, int32_t a, int32_t
         step = 1 + (int64_t)fmin(g, (double)dego);  // any gap >= deg ends the walk alike
       }
       int64_t incl = step;  // inclusive prefix within the D lanes of a vertex
-#pragma unroll
-      for (int d = 1; d < D; d <<= 1) {
-        const int64_t y = __shfl_up(incl, d, kWave);
-        if (sub >= d) incl += y;
+      static_assert(D <= 16, "a vertex's draws stay inside one row of 16 lanes");
+      if constexpr (D > 1) {  // DPP row shifts: the D lanes never span two rows
+        const int64_t y = dpp_move<0x111, 0xF>(incl);
+        if (sub >= 1) incl += y;
+      }
+      if constexpr (D > 2) {
+        const int64_t y = dpp_move<0x112, 0xF>(incl);
+        if (sub >= 2) incl += y;
+      }
+      if constexpr (D > 4) {
+        const int64_t y = dpp_move<0x114, 0xF>(incl);
+        if (sub >= 4) incl += y;
+      }
+      if constexpr (D > 8) {
+        const int64_t y = dpp_move<0x118, 0xF>(incl);
+        if (sub >= 8) incl += y;
       }
       const int64_t p = poso + incl;
       const bool live = act && p <= (int64_t)dego - 1;
@@ -311,7 +326,8 @@ struct Handoff {
 
 // ------------------------------------------------------------------ IC small
 struct __align__(16) WaveLds {
-  int32_t hash[kSmallH];
+  // the wavefront path's hash (kSmallH slots); the lane pass's lists
+  int32_t hash[kSmallH > kWave * IM_TINY ? kSmallH : kWave * IM_TINY];
   int32_t queue[kSmallCap];
   int32_t pre[kWave];    // inclusive prefix of 4-edge group counts
   int32_t gbase[kWave];  // group id of a lane's first group minus its prefix start
@@ -380,7 +396,7 @@ __device__ __forceinline__ void stage_flush(WaveLds& L, const int32_t* __restric
 // same draws as the wavefront path; a set that grows past kTiny members, or
 // reaches a coin-drawn vertex with more than kTinyDeg in-edges, is left to the
 // wavefront path, which starts it over.
-constexpr int kTiny = kSmallH / kWave;  // 8: the lists of a wave fill its hash area
+constexpr int kTiny = IM_TINY;  // members per lane list; a wave's lists share its hash area
 constexpr int32_t kTinyDeg = 16;
 
 __device__ __forceinline__ bool tiny_add(int32_t* list, int32_t* n, int32_t u) {
