@@ -386,6 +386,9 @@ static int64_t pair_budget(int64_t total) {
     const long long b = atoll(env);
     if (b >= 1) return std::min<int64_t>(total, (int64_t)b);
   }
+  // up to 1 GiB of pairs needs no query of free memory (a driver call on
+  // every transpose otherwise)
+  if (total <= ((int64_t)1 << 27)) return std::max<int64_t>(total, (int64_t)1 << 24);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     (void)hipGetLastError();
