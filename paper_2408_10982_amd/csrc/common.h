@@ -177,13 +177,26 @@ __device__ __forceinline__ T wave_sum(T x) {
   }
 }
 
+// Maximum over the wavefront, the same in every lane (the DPP steps of
+// wave_inclusive_scan with max for +; 0, the shifted-in value, is max's
+// identity).  Every lane must be active.
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    uint64_t y = __shfl_xor(x, d, kWave);
-    x = y > x ? y : x;
-  }
-  return x;
+  uint64_t y;
+  y = dpp_u64<0x111, 0xF>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x112, 0xF>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x114, 0xF>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x118, 0xF>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x142, 0xA>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x143, 0xC>(x);
+  x = y > x ? y : x;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, kWave - 1);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), kWave - 1);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Argmax key: larger count first, then lower vertex id.

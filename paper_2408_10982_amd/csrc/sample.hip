@@ -399,11 +399,17 @@ __device__ __forceinline__ void stage_flush(WaveLds& L, const int32_t* __restric
 constexpr int kTiny = IM_TINY;  // members per lane list; a wave's lists share its hash area
 constexpr int32_t kTinyDeg = 16;
 
-__device__ __forceinline__ bool tiny_add(int32_t* list, int32_t* n, int32_t u) {
-  for (int32_t k = 0; k < *n; ++k)
-    if (list[k] == u) return true;
+// Adds u to the lane's list unless present; false if the list is full.
+// seen: bit (u mod 64) of every member, so most new members skip the scan.
+__device__ __forceinline__ bool tiny_add(int32_t* list, int32_t* n, unsigned long long* seen,
+                                         int32_t u) {
+  const unsigned long long bit = 1ull << (u & 63);
+  if (*seen & bit)
+    for (int32_t k = 0; k < *n; ++k)
+      if (list[k] == u) return true;
   if (*n == kTiny) return false;
   list[(*n)++] = u;
+  *seen |= bit;
   return true;
 }
 
@@ -415,6 +421,7 @@ __attribute__((noinline))
 __device__ bool tiny_set(const GView& G, uint32_t i, int32_t root, int32_t* list, int32_t* cnt,
                          uint32_t* ex, uint32_t* lv) {
   list[0] = root;
+  unsigned long long seen = 1ull << (root & 63);
   int32_t n = 1, h = 0;
   uint32_t e_ = 0, l_ = 0;
   while (h < n) {
@@ -432,7 +439,7 @@ __device__ bool tiny_set(const GView& G, uint32_t i, int32_t root, int32_t* list
         if (gap >= (double)(deg - 1 - pos)) break;
         pos += 1 + (int64_t)gap;
         ++l_;
-        if (!tiny_add(list, &n, G.in_src[a + pos])) return false;
+        if (!tiny_add(list, &n, &seen, G.in_src[a + pos])) return false;
       }
     } else if (a < b) {  // coins, 4-edge groups as in the wavefront path
       if (b - a > kTinyDeg) return false;
@@ -447,7 +454,7 @@ __device__ bool tiny_set(const GView& G, uint32_t i, int32_t root, int32_t* list
           const uint32_t qw = pick_word(q, w), rw = pick_word(r, w);
           if (e >= a && e < b && (qw == 0xFFFFFFFFu || rw < qw)) {
             ++l_;
-            if (!tiny_add(list, &n, G.in_src[e])) return false;
+            if (!tiny_add(list, &n, &seen, G.in_src[e])) return false;
           }
         }
       }
