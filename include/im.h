@@ -193,8 +193,10 @@ int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t
  * histograms: scratch holds 8 bytes per member, up to 40% of the free device
  * memory, and a larger collection is transposed in rounds of vertex-id ranges
  * (IM_INCIDENCE_PAIR_BUDGET, a member count, lowers that cap; the round split
- * synchronises `stream` once).  Denser collections use one global atomic per
- * member and pass.  Otherwise asynchronous.
+ * synchronises `stream` once).  Denser collections over at most 4 x 32768
+ * vertex ids count and place members in LDS tiles of 32768 ids (scratch 8
+ * bytes per vertex; IM_INCIDENCE_DENSE_TILES=0 turns that form off); wider
+ * ones take one global atomic per member and pass.  Otherwise asynchronous.
  */
 int im_build_incidence(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                        int64_t total, int64_t* inc_off, int32_t* inc_mem, void* stream);

@@ -107,7 +107,7 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   void* ip = nullptr;
   IM_TRY(scratch(s, kSlotBatchInc, (size_t)std::max<int64_t>(total, 1) * 4, &ip));
   int32_t* inc_mem = (int32_t*)ip;
-  const IncSrc src{off, S, mem, total, d_sb, d_vb, nt};
+  const IncSrc src{off, S, mem, total, d_sb, d_vb, nt, max_n};
   IM_TRY(build_incidence(src, (int32_t)V, inc_off, inc_mem, s));
   IM_HIP(hipEventRecord(ev[2], s));
   // greedy on every task at once

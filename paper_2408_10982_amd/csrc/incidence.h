@@ -18,6 +18,7 @@ struct IncSrc {
   const int64_t* sbase;
   const int64_t* vbase;
   int32_t ntasks;
+  int64_t vspan;  // most vertices of one task (nv with ntasks == 0); 0: not known
 };
 
 // S(v) for v in [0, nv): inc_off nv + 1 entries, inc_mem total entries.

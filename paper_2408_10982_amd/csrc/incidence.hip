@@ -22,7 +22,8 @@
 //
 // Dense collections (hundreds of members per vertex, where one workgroup per
 // bucket would leave most of the chip idle) use a degree histogram and a
-// scatter with one global atomic per member each.
+// scatter: counted in LDS tiles of vertex ids when every task spans a few
+// tiles at most, else with one global atomic per member each.
 #include <stdlib.h>
 
 #include <algorithm>
@@ -70,9 +71,8 @@ struct WalkLds {
 // clipped to [a, b), are consecutive in memory, so after one scan of their
 // sizes the lanes read the members coalesced and find each member's sample
 // by binary search over the 64 prefix sums.
-template <bool kTasks, typename F>
-__device__ __forceinline__ void walk_wave(const IncSrc& S, int64_t a, int64_t b, WalkLds& W,
-                                          F&& f) {
+template <bool kTasks, typename Lds, typename F>
+__device__ __forceinline__ void walk_wave(const IncSrc& S, int64_t a, int64_t b, Lds& W, F&& f) {
   if (a >= b) return;
   const int lane = lane_id();
   int64_t jg = first_lane_i64(last_leq(S.off, S.count, a));
@@ -89,7 +89,7 @@ __device__ __forceinline__ void walk_wave(const IncSrc& S, int64_t a, int64_t b,
     const int64_t all = __shfl(incl, kWave - 1, kWave);
     const int64_t first = __shfl(c0, 0, kWave);
     W.pre[lane] = incl;
-    if (kTasks) {
+    if constexpr (kTasks) {
       int64_t vbl = 0, sbl = 0;
       if (j < S.count) {
         const int64_t t = last_leq(S.sbase, S.ntasks, j);
@@ -109,8 +109,10 @@ __device__ __forceinline__ void walk_wave(const IncSrc& S, int64_t a, int64_t b,
         else
           lo = mid + 1;
       }
-      const int64_t v = (kTasks ? W.vb[lo] : 0) + (int64_t)S.mem[first + x];
-      f(v, jg + lo - (kTasks ? W.sb[lo] : 0));
+      if constexpr (kTasks)
+        f(W.vb[lo] + (int64_t)S.mem[first + x], jg + lo - W.sb[lo]);
+      else
+        f((int64_t)S.mem[first + x], jg + lo);
     }
     const int64_t last_end = __shfl(s1, kWave - 1, kWave);
     wave_sync();
@@ -346,8 +348,233 @@ __global__ __launch_bounds__(kAtomBlock) void k_task_incidence(IncSrc S,
   }
 }
 
+// ---- dense collections over small vertex ranges: LDS tiles
+// When no task spans more than a few tiles of kTileV consecutive vertex ids,
+// both passes count in LDS instead.  A work item is (task, slice of the
+// task's samples holding about L members, tile); items are numbered task by
+// task with the tile fastest, so the items that read one slice run at about
+// the same time and share its members in the caches.
+//   degree: the item counts the slice's members that fall in its tile with
+//     LDS atomics, then adds each nonzero count to deg: one device atomic per
+//     (item, vertex) instead of one per member;
+//   scatter: the item counts again, reserves a run of S(v) for each of its
+//     vertices with one device atomic, and walks the slice's samples placing
+//     their ids with LDS cursors.
+// The cursors are 32-bit offsets from the tile's first S(v); a tile whose
+// covering subsets hold 2^32 entries or more takes device atomics per member.
+constexpr int kTileBlock = 1024;
+constexpr int32_t kTileV = 32768;                  // vertices per tile: 128 KB of counters
+constexpr int kMaxTiles = 4;                       // tiles per task, at most, for this form
+constexpr int64_t kTileMembers = (int64_t)1 << 22; // members per slice, at least
+constexpr int64_t kMaxSlices = 4096;               // slices per collection, about
+
+struct TileItem {
+  int64_t s0;      // first sample of the task (sample ids in S(v) are task-local)
+  int64_t j0, j1;  // samples of the slice
+  int64_t v;       // first vertex of the tile, global
+  uint32_t lo;     // first vertex of the tile, task-local (the id the members hold)
+  uint32_t width;  // vertices in the tile
+};
+
+struct TileWalk {
+  int64_t pre[kWave];
+};
+
+__device__ __forceinline__ int64_t first_geq(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
+  while (lo < hi) {  // first i in [lo, hi) with a[i] >= x, else hi
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] >= x)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void task_bounds(const IncSrc& S, int32_t nv, int64_t t, int64_t* s0,
+                                            int64_t* s1, int64_t* v0, int64_t* v1) {
+  if (S.ntasks == 0) {
+    *s0 = 0;
+    *s1 = S.count;
+    *v0 = 0;
+    *v1 = nv;
+  } else {
+    *s0 = S.sbase[t];
+    *s1 = S.sbase[t + 1];
+    *v0 = S.vbase[t];
+    *v1 = S.vbase[t + 1];
+  }
+}
+
+// itm[t + 1] - itm[t] = items of task t (slices x tiles); one wavefront.
+__global__ __launch_bounds__(kWave) void k_tile_items(IncSrc S, int32_t nv, int64_t L,
+                                                      int64_t* __restrict__ itm) {
+  const int nt = S.ntasks > 0 ? S.ntasks : 1, lane = lane_id();
+  int64_t carry = 0;
+  for (int base = 0; base < nt; base += kWave) {
+    const int t = base + lane;
+    int64_t c = 0;
+    if (t < nt) {
+      int64_t s0, s1, v0, v1;
+      task_bounds(S, nv, t, &s0, &s1, &v0, &v1);
+      const int64_t m = S.off[s1] - S.off[s0];
+      c = ((m + L - 1) / L) * ((v1 - v0 + kTileV - 1) / kTileV);
+    }
+    const int64_t incl = wave_inclusive_scan(c);
+    if (t < nt) itm[t + 1] = carry + incl;
+    carry += __shfl(incl, kWave - 1, kWave);
+  }
+  if (lane == 0) itm[0] = 0;
+}
+
+__device__ __forceinline__ TileItem tile_item(const IncSrc& S, int32_t nv, int64_t L,
+                                              const int64_t* __restrict__ itm, int nt, int64_t i) {
+  const int64_t t = last_leq(itm, nt, i);
+  int64_t s0, s1, v0, v1;
+  task_bounds(S, nv, t, &s0, &s1, &v0, &v1);
+  const int64_t ntl = (v1 - v0 + kTileV - 1) / kTileV;
+  const int64_t r = i - itm[t], sl = r / ntl, tl = r - sl * ntl;
+  const int64_t m0 = S.off[s0], m1 = S.off[s1];
+  const int64_t nsl = (m1 - m0 + L - 1) / L;
+  TileItem it;
+  it.s0 = s0;
+  // sample j belongs to the slice that holds its first member
+  it.j0 = sl == 0 ? s0 : first_geq(S.off, s0, s1, m0 + sl * L);
+  it.j1 = sl == nsl - 1 ? s1 : first_geq(S.off, s0, s1, m0 + (sl + 1) * L);
+  it.lo = (uint32_t)(tl * kTileV);
+  it.v = v0 + it.lo;
+  it.width = (uint32_t)(v1 - it.v < kTileV ? v1 - it.v : kTileV);
+  return it;
+}
+
+// h[u] = members of the item's slice equal to lo + u, u < width.  Ends synchronised.
+__device__ __forceinline__ void tile_count(const IncSrc& S, const TileItem& it,
+                                           uint32_t* __restrict__ h) {
+  for (uint32_t k = threadIdx.x; k < it.width; k += kTileBlock) h[k] = 0;
+  __syncthreads();
+  const int64_t a = S.off[it.j0], b = S.off[it.j1];
+  auto add = [&](int32_t x) {
+    const uint32_t u = (uint32_t)x - it.lo;
+    if (u < it.width) atomicAdd(&h[u], 1u);
+  };
+  // 16-byte loads over the aligned middle, two per thread in flight
+  const int64_t q0 = (a + 3) >> 2, q1 = b >> 2;
+  if (q0 >= q1 || ((uintptr_t)S.mem & 15) != 0) {
+    for (int64_t m = a + threadIdx.x; m < b; m += kTileBlock) add(S.mem[m]);
+  } else {
+    for (int64_t m = a + threadIdx.x; m < q0 * 4; m += kTileBlock) add(S.mem[m]);
+    for (int64_t m = q1 * 4 + threadIdx.x; m < b; m += kTileBlock) add(S.mem[m]);
+    const int4* __restrict__ m4 = (const int4*)S.mem;
+    int64_t q = q0 + threadIdx.x;
+    for (; q + kTileBlock < q1; q += 2 * kTileBlock) {
+      const int4 x = m4[q], y = m4[q + kTileBlock];
+      add(x.x), add(x.y), add(x.z), add(x.w);
+      add(y.x), add(y.y), add(y.z), add(y.w);
+    }
+    if (q < q1) {
+      const int4 x = m4[q];
+      add(x.x), add(x.y), add(x.z), add(x.w);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTileBlock) void k_tile_degree(IncSrc S, int32_t nv, int64_t L,
+                                                            const int64_t* __restrict__ itm,
+                                                            uint32_t* __restrict__ deg) {
+  __shared__ uint32_t h[kTileV];
+  const int nt = S.ntasks > 0 ? S.ntasks : 1;
+  const int64_t n_items = itm[nt];
+  for (int64_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const TileItem it = tile_item(S, nv, L, itm, nt, i);
+    tile_count(S, it, h);
+    for (uint32_t k = threadIdx.x; k < it.width; k += kTileBlock) {
+      const uint32_t c = h[k];
+      if (c) atomicAdd(&deg[it.v + k], c);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kTileBlock) void k_tile_scatter(IncSrc S, int32_t nv, int64_t L,
+                                                             const int64_t* __restrict__ itm,
+                                                             uint32_t* __restrict__ fill,
+                                                             const int64_t* __restrict__ inc_off,
+                                                             int32_t* __restrict__ inc_mem) {
+  __shared__ uint32_t h[kTileV];
+  __shared__ TileWalk walk[kTileBlock / kWave];
+  const int nt = S.ntasks > 0 ? S.ntasks : 1;
+  const int64_t n_items = itm[nt];
+  const int nw = kTileBlock / kWave, w = threadIdx.x / kWave;
+  for (int64_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const TileItem it = tile_item(S, nv, L, itm, nt, i);
+    tile_count(S, it, h);
+    const int64_t cbase = inc_off[it.v];
+    const bool cursors = inc_off[it.v + it.width] - cbase < ((int64_t)1 << 32);
+    if (cursors) {
+      for (uint32_t k = threadIdx.x; k < it.width; k += kTileBlock) {
+        const uint32_t c = h[k];
+        if (c) {
+          const uint32_t pos = atomicAdd(&fill[it.v + k], c);
+          h[k] = (uint32_t)(inc_off[it.v + k] - cbase) + pos;
+        }
+      }
+      __syncthreads();
+    }
+    // each wavefront walks an equal share of the slice's members
+    const int64_t a = S.off[it.j0], len = S.off[it.j1] - a;
+    walk_wave<false>(S, a + len * w / nw, a + len * (w + 1) / nw, walk[w],
+                     [&](int64_t x, int64_t j) {
+                       const uint32_t u = (uint32_t)x - it.lo;
+                       if (u >= it.width) return;
+                       const int32_t id = (int32_t)(j - it.s0);
+                       if (cursors) {
+                         inc_mem[cbase + atomicAdd(&h[u], 1u)] = id;
+                       } else {
+                         const int64_t gv = it.v + u;
+                         inc_mem[inc_off[gv] + atomicAdd(&fill[gv], 1u)] = id;
+                       }
+                     });
+    __syncthreads();
+  }
+}
+
+static int64_t tile_limit() {  // IM_INCIDENCE_DENSE_TILES: tiles per task, at most (0: never)
+  if (const char* env = getenv("IM_INCIDENCE_DENSE_TILES")) return atoll(env);
+  return kMaxTiles;
+}
+
+static int build_incidence_tiled(const IncSrc& S, int32_t nv, int64_t* inc_off, int32_t* inc_mem,
+                                 hipStream_t s) {
+  const int nt = S.ntasks > 0 ? S.ntasks : 1;
+  const size_t bDeg = ((size_t)nv * 8 + 255) / 256 * 256;
+  void* p = nullptr;
+  IM_TRY(scratch(s, kSlotIncidence, bDeg + (size_t)(nt + 1) * 8, &p));
+  uint32_t* deg = (uint32_t*)p;
+  uint32_t* fill = deg + nv;
+  int64_t* itm = (int64_t*)((char*)p + bDeg);
+  IM_HIP(hipMemsetAsync(deg, 0, (size_t)nv * 8, s));
+  // IM_INCIDENCE_TILE_MEMBERS (>= 1) sets the slice length, to exercise many slices
+  int64_t L = std::max<int64_t>(kTileMembers, (S.total + kMaxSlices - 1) / kMaxSlices);
+  if (const char* env = getenv("IM_INCIDENCE_TILE_MEMBERS"))
+    if (atoll(env) >= 1) L = atoll(env);
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  const unsigned grid = (unsigned)di.num_cus;  // one 128 KB workgroup per CU
+  k_tile_items<<<dim3(1), dim3(kWave), 0, s>>>(S, nv, L, itm);
+  IM_HIP(hipGetLastError());
+  k_tile_degree<<<dim3(grid), dim3(kTileBlock), 0, s>>>(S, nv, L, itm, deg);
+  IM_HIP(hipGetLastError());
+  IM_TRY(exclusive_scan_u32_to_i64(deg, nv, inc_off, s));
+  k_tile_scatter<<<dim3(grid), dim3(kTileBlock), 0, s>>>(S, nv, L, itm, fill, inc_off, inc_mem);
+  IM_HIP(hipGetLastError());
+  return IM_OK;
+}
+
 static int build_incidence_dense(const IncSrc& S, int32_t nv, int64_t* inc_off,
                                  int32_t* inc_mem, hipStream_t s) {
+  if (S.vspan > 0 && (S.vspan + kTileV - 1) / kTileV <= tile_limit())
+    return build_incidence_tiled(S, nv, inc_off, inc_mem, s);
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotIncidence, (size_t)nv * 8, &p));
   uint32_t* deg = (uint32_t*)p;
@@ -488,6 +715,6 @@ extern "C" int im_build_incidence(int32_t n, int64_t count, const int64_t* off,
   if (n <= 0 || count < 0 || total < 0 || !off || !inc_off || (total > 0 && (!mem || !inc_mem)) ||
       count >= ((int64_t)1 << 31) || (total > 0 && count == 0))
     return IM_EINVAL;
-  const IncSrc S{off, count, mem, total, nullptr, nullptr, 0};
+  const IncSrc S{off, count, mem, total, nullptr, nullptr, 0, n};
   return build_incidence(S, n, inc_off, inc_mem, (hipStream_t)stream);
 }

@@ -149,18 +149,32 @@ def _segments_sorted(inc_off, inc_mem):
     return io, im_[np.lexsort((im_, seg))]
 
 
-@pytest.mark.parametrize("form", ["auto", "dense"])
+def _incidence_form(form, monkeypatch):
+    """"dense": one device atomic per member and pass; "tiled": LDS tiles of
+    vertex ids (ranges of at most 4 x 32768 ids, else the atomic form);
+    "tiled_slices": the same with slices of 997 members, so that items split
+    sets and many slices hold no set start."""
+    if form != "auto":
+        monkeypatch.setenv("IM_INCIDENCE_DENSE_RATIO", "0")
+    if form == "dense":
+        monkeypatch.setenv("IM_INCIDENCE_DENSE_TILES", "0")
+    if form == "tiled_slices":
+        monkeypatch.setenv("IM_INCIDENCE_TILE_MEMBERS", "997")
+
+
+@pytest.mark.parametrize("form", ["auto", "dense", "tiled", "tiled_slices"])
 @pytest.mark.parametrize("n,count,max_size,seed", [
     (5000, 4000, 40, 1),                 # one bucket of vertex ids, ragged tail
     (4096 * 4096 + 4099, 3000, 300, 2),  # ids wider than 4096 buckets of 2^12
     (70000, 1, 60000, 3),                # a single set spanning many chunks
+    (100000, 1500, 3000, 4),             # four LDS tiles of vertex ids, the last ragged
 ])
 def test_incidence_synthetic(im, n, count, max_size, seed, form, monkeypatch):
     """Covering subsets of synthetic collections (distinct ids per set, sizes
-    from 0 up), against the oracle's transpose; "dense" forces the atomic form."""
+    from 0 up), against the oracle's transpose, in each dense form (see
+    _incidence_form) and the automatic choice."""
     _say("incidence synthetic", n, count, max_size, form)
-    if form == "dense":
-        monkeypatch.setenv("IM_INCIDENCE_DENSE_RATIO", "0")
+    _incidence_form(form, monkeypatch)
     rng = np.random.default_rng(seed)
     sizes = rng.integers(0, max_size + 1, size=count)
     sizes[0] = max_size
@@ -170,7 +184,11 @@ def test_incidence_synthetic(im, n, count, max_size, seed, form, monkeypatch):
                          ).astype(np.int32)
     o = O.RRR(off=off, mem=mem, examined=0, live=0)
     oio, oim = O.incidence(n, o)
-    r = im.RRR(off=torch.from_numpy(off).cuda(), mem=torch.from_numpy(mem).cuda(),
+    dmem = torch.from_numpy(mem).cuda()
+    if seed == 1:  # members at an address that is not 16-byte aligned
+        dmem = torch.cat([torch.zeros(1, dtype=torch.int32, device="cuda"), dmem])[1:]
+        assert dmem.data_ptr() % 16 == 4
+    r = im.RRR(off=torch.from_numpy(off).cuda(), mem=dmem,
                total=int(off[-1]), examined=0, live=0, large_sets=0)
     io, imem = im.build_incidence(n, r)
     gio, gim = _segments_sorted(_np(io), _np(imem))
@@ -281,11 +299,14 @@ def test_solve_imm(im, name, k, eps, selector):
     assert got["coverage"] == exp["coverage"]
 
 
-def test_batch_matches_single_calls_and_oracle(im):
+@pytest.mark.parametrize("form", ["auto", "dense", "tiled_slices"])
+def test_batch_matches_single_calls_and_oracle(im, form, monkeypatch):
     """im_solve_batch: every task equals its own sample + incidence + greedy
     calls on the GPU and the oracle's standard greedy (mixed IC/LT, uneven
-    n, k and theta, including sets large enough for the large-set path)."""
-    _say("batch")
+    n, k and theta, including sets large enough for the large-set path), with
+    the covering subsets of the whole batch in each form."""
+    _say("batch", form)
+    _incidence_form(form, monkeypatch)
     specs = [("ic_sparse", 5, 0, 7, 3000), ("lt_small", 6, 1, 12, 4000), ("rmat12", 7, 0, 16, 5000),
              ("ic_dense", 8, 2, 3, 1500), ("lt_chain", 9, 0, 5, 700), ("ic_p1", 10, 0, 4, 400)]
     for j in range(4):
