@@ -5,7 +5,12 @@ A step is one pass of the whole path over one batch of synthetic input:
 RRR sampling of theta sets (root draw, IC reverse BFS), the covering subsets,
 and greedy max-k-cover.  Default workload: R-MAT scale 20 (2^20 vertices,
 2^24 edges), IC with weighted-cascade probabilities 1/indeg(v), theta = 2^20,
-k = 100.  Inputs are resident in HBM before the timed region starts.
+k = 100.  Inputs are resident in HBM before the timed region starts.  Steps
+alternate over --streams streams (3 by default), so that one step's covering
+subsets and greedy, a chain of small launches, run beside the next step's
+sampling; every step does all of its work, and ms_per_step_one_stream gives
+the rate without that overlap.  Per-phase and per-kernel times come from
+steps run one at a time on one stream.
 
 Prints one JSON line on stdout.  `roofline` describes the dominant kernel
 (algorithmic bytes per launch over its event-timed duration); `cpu_baseline`
@@ -105,6 +110,8 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.125)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="RRR sets the CPU oracle times (0: the whole workload)")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="configs 1-2: streams the steps alternate over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="config 4: keep the default launch shapes")
@@ -153,46 +160,60 @@ def main():
 
     cap = [max(4 * w.theta, 1 << 20)]
 
-    def step(record):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        ev[0].record()
-        r = im.sample_rrr(G, w.seed, 0, 0, w.theta, capacity=cap[0])
-        cap[0] = max(cap[0], r.total)
-        ev[1].record()
-        io, imem = im.build_incidence(g.n, r)
-        ev[2].record()
-        seeds, gains, nsel, cov = im.greedy_cover(g.n, r, io, imem, w.k)
-        ev[3].record()
+    # Step i runs on stream i mod S: its covering subsets and greedy (a chain
+    # of small launches) overlap the next step's sampling.  Every step does
+    # all of its work; each stream has its own library scratch.
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream()
+                                               for _ in range(max(args.streams, 1) - 1)]
+
+    def step(record, s):
+        with torch.cuda.stream(s):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            r = im.sample_rrr(G, w.seed, 0, 0, w.theta, capacity=cap[0])
+            cap[0] = max(cap[0], r.total)
+            ev[1].record()
+            io, imem = im.build_incidence(g.n, r)
+            ev[2].record()
+            seeds, gains, nsel, cov = im.greedy_cover(g.n, r, io, imem, w.k)
+            ev[3].record()
         if record is not None:
             record.append((r, ev, (seeds, gains, nsel, cov)))
         return r
 
-    for i in range(args.warmup):
-        step(None)
+    def timed(n_streams, steps, record):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            step(record, streams[i % n_streams])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    for i in range(max(args.warmup, len(streams))):
+        step(None, streams[i % len(streams)])
         torch.cuda.synchronize()
         log("warmup %d done" % i)
+    serial = []
+    ms_serial = 1e3 * timed(1, args.steps, serial) / args.steps
     recs = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step(recs)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    log("timed %d steps in %.3fs" % (args.steps, t_total))
+    t_total = timed(len(streams), args.steps, recs)
+    log("timed %d steps in %.3fs on %d streams (one stream: %.3f ms/step)" %
+        (args.steps, t_total, len(streams), ms_serial))
     ms_step = 1e3 * t_total / args.steps
 
     r0, _, out0 = recs[0]
     seeds0 = out0[0].cpu().tolist()
     cov0 = int(out0[3].item())
-    for r, ev, out in recs[1:]:  # every timed step computes the same result
+    for r, ev, out in recs[1:] + serial:  # every timed step computes the same result
         assert out[0].cpu().tolist() == seeds0 and int(out[3].item()) == cov0
-    ms_sample = sum(ev[0].elapsed_time(ev[1]) for _, ev, _ in recs) / len(recs)
-    ms_inc = sum(ev[1].elapsed_time(ev[2]) for _, ev, _ in recs) / len(recs)
-    ms_greedy = sum(ev[2].elapsed_time(ev[3]) for _, ev, _ in recs) / len(recs)
+    # per-phase and per-kernel times from the one-stream steps (no overlap)
+    ms_sample = sum(ev[0].elapsed_time(ev[1]) for _, ev, _ in serial) / len(serial)
+    ms_inc = sum(ev[1].elapsed_time(ev[2]) for _, ev, _ in serial) / len(serial)
+    ms_greedy = sum(ev[2].elapsed_time(ev[3]) for _, ev, _ in serial) / len(serial)
     st = r0.stats
-    ms_main = sum(r.stats["ms_main"] for r, _, _ in recs) / len(recs)
-    ms_large = sum(r.stats["ms_large"] for r, _, _ in recs) / len(recs)
-    ms_canon = sum(r.stats["ms_canon"] for r, _, _ in recs) / len(recs)
+    ms_main = sum(r.stats["ms_main"] for r, _, _ in serial) / len(serial)
+    ms_large = sum(r.stats["ms_large"] for r, _, _ in serial) / len(serial)
+    ms_canon = sum(r.stats["ms_canon"] for r, _, _ in serial) / len(serial)
 
     small_sets = w.theta - st["large_sets"]
     b_main = sampling_bytes(small_sets, st["total"] - st["large_total"],
@@ -231,6 +252,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
+        "streams": len(streams),
+        "ms_per_step_one_stream": round(ms_serial, 3),
         "config": {"workload": w.name, "graph": "R-MAT (0.57,0.19,0.19) scale %d, %d edges"
                    % (g.n.bit_length() - 1, g.num_edges),
                    "model": "IC weighted cascade" if args.config == 2 else "IC uniform [0,0.1)",
