@@ -840,6 +840,13 @@ static_assert(BigNarrow::kCap >= kSmallCap && BigWide::kCap >= kSmallCap,
               "a hand-off snapshot must fit the LDS tier");
 
 // The visited set and member list of the set a workgroup is growing.
+// The word of a worker's HBM bitmap that holds u, read at agent scope (past
+// the CU's L1, as the bitmap's atomics are performed in L2).  Bits only get
+// set while a set grows, so a set bit read here is final.
+__device__ __forceinline__ uint32_t bitmap_word(const uint32_t* bm, int32_t u) {
+  return __hip_atomic_load(&bm[u >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct BigSet {
   bool lds;             // LDS mode (block-uniform)
   int32_t* mhash;       // LDS: kH slots
@@ -880,6 +887,7 @@ __device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
     }
   } else {
     const uint32_t bit = 1u << (u & 31);
+    if (bitmap_word(S.bm, u) & bit) return;
     const uint32_t old = atomicOr(&S.bm[u >> 5], bit);
     if (!(old & bit)) S.queue[atomicAdd(S.s_tail, 1)] = u;
   }
@@ -923,9 +931,15 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
         if (u[q] >= 0) set_insert<C>(S, u[q]);
     } else {
       uint32_t old[kFlushBatch];
+      // a coherent load first: a source whose bit is already set (most of
+      // the live edges of a large set) costs a read instead of a device atomic
 #pragma unroll
       for (int q = 0; q < kFlushBatch; ++q)
-        old[q] = u[q] >= 0 ? atomicOr(&S.bm[u[q] >> 5], 1u << (u[q] & 31)) : 0u;
+        old[q] = u[q] >= 0 ? bitmap_word(S.bm, u[q]) : 0u;
+#pragma unroll
+      for (int q = 0; q < kFlushBatch; ++q)
+        if (u[q] >= 0 && !(old[q] & (1u << (u[q] & 31))))
+          old[q] = atomicOr(&S.bm[u[q] >> 5], 1u << (u[q] & 31));
 #pragma unroll
       for (int q = 0; q < kFlushBatch; ++q)
         if (u[q] >= 0 && !(old[q] & (1u << (u[q] & 31)))) S.queue[atomicAdd(S.s_tail, 1)] = u[q];
