@@ -64,35 +64,13 @@ struct WalkLds {
   int64_t pre[kWave];  // inclusive prefix of the group's clipped set sizes
   int64_t vb[kWave];   // vertex offset of the task of each lane's sample
   int64_t sb[kWave];   // sample offset of that task
-  uint32_t own[kWave]; // 1 + the lane whose sample starts at each position of a window
 };
-
-// Inclusive prefix maximum over the wavefront's 64 lanes (the DPP steps of
-// wave_inclusive_scan; the shifted-in 0 is the identity of max over unsigned
-// values).  Every lane must be active.
-__device__ __forceinline__ uint32_t wave_inclusive_max_u32(uint32_t x) {
-  uint32_t y;
-  y = dpp_u32<0x111, 0xF>(x);
-  x = y > x ? y : x;
-  y = dpp_u32<0x112, 0xF>(x);
-  x = y > x ? y : x;
-  y = dpp_u32<0x114, 0xF>(x);
-  x = y > x ? y : x;
-  y = dpp_u32<0x118, 0xF>(x);
-  x = y > x ? y : x;
-  y = dpp_u32<0x142, 0xA>(x);
-  x = y > x ? y : x;
-  y = dpp_u32<0x143, 0xC>(x);
-  x = y > x ? y : x;
-  return x;
-}
 
 // Calls f(vertex, sample) for every member in [a, b), the whole wavefront
 // together.  It takes 64 consecutive samples at a time; their member ranges,
 // clipped to [a, b), are consecutive in memory, so after one scan of their
-// sizes the lanes read the members coalesced, 64 positions at a time, and
-// find each member's sample by a prefix maximum over the window's sample
-// starts.
+// sizes the lanes read the members coalesced and find each member's sample
+// by binary search over the 64 prefix sums.
 template <bool kTasks, typename Lds, typename F>
 __device__ __forceinline__ void walk_wave(const IncSrc& S, int64_t a, int64_t b, Lds& W, F&& f) {
   if (a >= b) return;
@@ -122,29 +100,19 @@ __device__ __forceinline__ void walk_wave(const IncSrc& S, int64_t a, int64_t b,
       W.sb[lane] = sbl;
     }
     wave_sync();
-    // 64 positions at a time: the lanes whose (nonempty) sample starts in the
-    // window mark its start; the owner of a position is the last mark at or
-    // before it, a prefix maximum, else the owner carried from the window before
-    const int64_t st = incl - sz;
-    uint32_t carry = 0;
-    for (int64_t x0 = 0; x0 < all; x0 += kWave) {
-      W.own[lane] = 0u;
-      wave_sync();
-      if (sz > 0 && st >= x0 && st < x0 + kWave) W.own[st - x0] = (uint32_t)lane + 1u;
-      wave_sync();
-      uint32_t o = W.own[lane];
-      if (lane == 0 && o == 0u) o = carry;
-      o = wave_inclusive_max_u32(o);
-      carry = (uint32_t)__builtin_amdgcn_readlane((int)o, kWave - 1);
-      const int lo = (int)o - 1;
-      const int64_t x = x0 + lane;
-      if (x < all) {
-        if constexpr (kTasks)
-          f(W.vb[lo] + (int64_t)S.mem[first + x], jg + lo - W.sb[lo]);
+    for (int64_t x = lane; x < all; x += kWave) {
+      int lo = 0, hi = kWave - 1;  // first lane whose inclusive prefix exceeds x
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (W.pre[mid] > x)
+          hi = mid;
         else
-          f((int64_t)S.mem[first + x], jg + lo);
+          lo = mid + 1;
       }
-      wave_sync();
+      if constexpr (kTasks)
+        f(W.vb[lo] + (int64_t)S.mem[first + x], jg + lo - W.sb[lo]);
+      else
+        f((int64_t)S.mem[first + x], jg + lo);
     }
     const int64_t last_end = __shfl(s1, kWave - 1, kWave);
     wave_sync();
@@ -410,7 +378,6 @@ struct TileItem {
 
 struct TileWalk {
   int64_t pre[kWave];
-  uint32_t own[kWave];
 };
 
 __device__ __forceinline__ int64_t first_geq(const int64_t* a, int64_t lo, int64_t hi, int64_t x) {
