@@ -61,6 +61,10 @@ struct BigCfg {
   static constexpr int kSortCap = kBlockT >= 256 ? kH : (2 * kH < 2048 ? 2 * kH : 2048);
   static constexpr int kPool =
       kH + kCap + kStage > kSortCap ? kH + kCap + kStage : kSortCap;
+  // LDS bitmap tier: a set that outgrows the hash marks its members in a
+  // bitmap over the hash and member-list words when the graph has at most
+  // kBitsN vertices (the stage stays where it is)
+  static constexpr int kBitsN = (kH + kCap) * 32;
 };
 #ifndef IM_NARROW_BITS
 #define IM_NARROW_BITS 10
@@ -852,6 +856,7 @@ struct BigSet {
   int32_t* mhash;       // LDS: kH slots
   int32_t* mq;          // LDS: kCap members
   uint32_t* bm;         // HBM: n-bit bitmap
+  bool bits;            // bitmap in LDS (over mhash and mq) instead of bm (block-uniform)
   int32_t* queue;       // HBM: n members
   int32_t* s_tail;      // members so far
   int32_t* s_over;      // LDS mode only: a member did not fit
@@ -885,6 +890,10 @@ __device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
       }
       h = (h + 1) & (C::kH - 1);
     }
+  } else if (S.bits) {
+    const uint32_t bit = 1u << (u & 31);
+    const uint32_t old = atomicOr((uint32_t*)&S.mhash[u >> 5], bit);
+    if (!(old & bit)) S.queue[atomicAdd(S.s_tail, 1)] = u;
   } else {
     const uint32_t bit = 1u << (u & 31);
     if (bitmap_word(S.bm, u) & bit) return;
@@ -925,7 +934,7 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
       const int32_t k = k0 + q * C::kBlock;
       u[q] = k < ns ? in_src[stage[k]] : -1;
     }
-    if (S.lds) {
+    if (S.lds || S.bits) {
 #pragma unroll
       for (int q = 0; q < kFlushBatch; ++q)
         if (u[q] >= 0) set_insert<C>(S, u[q]);
@@ -951,9 +960,11 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
 }
 
 // One workgroup per large set: visited set and members in LDS while they fit
-// (sorted in LDS), else the worker's private bitmap and queue in HBM (sorted
-// in LDS up to C::kSortCap members, else read in order from the bitmap, a
-// pass over all n bits).
+// (sorted in LDS); past that, on graphs of at most C::kBitsN vertices, a
+// bitmap in LDS with the members queued in HBM (read in order from the
+// bitmap); otherwise the worker's private bitmap and queue in HBM (sorted in
+// LDS up to C::kSortCap members, else read in order from the bitmap, a pass
+// over all n bits).
 template <class C>
 __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs A, BigArgs Bg) {
   __shared__ int32_t pre[C::kBlock];
@@ -989,7 +1000,7 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     const uint64_t seed = ((uint64_t)G.seed_hi << 32) | G.seed_lo;
     const int32_t root = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
     unsigned long long s_ex = 0, s_lv = 0;
-    BigSet S{T.model == IM_IC, mhash, mq, bm, queue, &s_tail, &s_over};
+    BigSet S{T.model == IM_IC, mhash, mq, bm, false, queue, &s_tail, &s_over};
     if (T.model == IM_IC) {
       int32_t head = 0, tail = 1;
       for (int j = t; j < C::kH; j += C::kBlock) mhash[j] = kEmpty;
@@ -1096,11 +1107,22 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         tail = s_tail;
         const bool over = S.lds && s_over;
         __syncthreads();
-        if (over) {  // the level passed C::kCap members: redo it in HBM mode
+        if (over) {  // the level passed C::kCap members: redo it in a bitmap mode
+          S.bits = G.n <= C::kBitsN;
           for (int j = t; j < tail0; j += C::kBlock) {
             const int32_t u = mq[j];
             queue[j] = u;
-            atomicOr(&bm[u >> 5], 1u << (u & 31));
+            if (!S.bits) atomicOr(&bm[u >> 5], 1u << (u & 31));
+          }
+          if (S.bits) {  // the bitmap replaces the hash and member list in LDS
+            __syncthreads();
+            const int32_t nw = (G.n + 31) >> 5;
+            for (int j = t; j < nw; j += C::kBlock) mhash[j] = 0;
+            __syncthreads();
+            for (int j = t; j < tail0; j += C::kBlock) {
+              const int32_t u = queue[j];
+              atomicOr((uint32_t*)&mhash[u >> 5], 1u << (u & 31));
+            }
           }
           S.lds = false;
           head = head0;
@@ -1150,7 +1172,28 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     __syncthreads();
     const unsigned long long pos = s_pos;
     const bool fits = pos + (unsigned long long)tail <= A.arena_cap;
-    if (S.lds || tail <= C::kSortCap) {
+    if (S.bits) {
+      // members in ascending order straight from the LDS bitmap
+      const uint32_t nw = ((uint32_t)G.n + 31) >> 5;
+      const uint32_t per = (nw + C::kBlock - 1) / C::kBlock;
+      const uint32_t w0 = min((uint32_t)t * per, nw);
+      const uint32_t w1 = min(w0 + per, nw);
+      const uint32_t* lbm = (const uint32_t*)mhash;
+      int64_t cnt = 0;
+      for (uint32_t w = w0; w < w1; ++w) cnt += __popc(lbm[w]);
+      int64_t tot;
+      int64_t o = block_exclusive_scan64<C::kBlock>(cnt, scan_lds, &tot);
+      if (fits) {
+        for (uint32_t w = w0; w < w1; ++w) {
+          uint32_t x = lbm[w];
+          while (x) {
+            const int b = __ffs(x) - 1;
+            x &= x - 1;
+            A.arena[pos + o++] = (int32_t)((w << 5) + b);
+          }
+        }
+      }
+    } else if (S.lds || tail <= C::kSortCap) {
       // LDS mode: the members are in mq (tail <= C::kCap); HBM mode: copy them
       // into the (now unused) LDS pool
       int32_t* sorted = S.lds ? mq : pool;
@@ -1213,7 +1256,7 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
       }
     }
     __syncthreads();
-    if (!S.lds && tail > C::kSortCap)  // (smaller sets were cleared above)
+    if (!S.lds && !S.bits && tail > C::kSortCap)  // (smaller sets were cleared above)
       for (int j = t; j < tail; j += C::kBlock) bm[queue[j] >> 5] = 0u;
     if (t == 0) {
       A.start[il] = (int64_t)pos;
