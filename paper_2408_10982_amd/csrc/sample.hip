@@ -860,7 +860,6 @@ struct BigSet {
   int32_t* queue;       // HBM: n members
   int32_t* s_tail;      // members so far
   int32_t* s_over;      // LDS mode only: a member did not fit
-  int32_t* s_filt;      // HBM bitmap: read a word before its atomic (most sources already seen)
 };
 
 // Adds u to the set if it is new.  In LDS mode the member count is checked
@@ -897,7 +896,7 @@ __device__ __forceinline__ void set_insert(const BigSet& S, int32_t u) {
     if (!(old & bit)) S.queue[atomicAdd(S.s_tail, 1)] = u;
   } else {
     const uint32_t bit = 1u << (u & 31);
-    if (*S.s_filt && (bitmap_word(S.bm, u) & bit)) return;
+    if (bitmap_word(S.bm, u) & bit) return;
     const uint32_t old = atomicOr(&S.bm[u >> 5], bit);
     if (!(old & bit)) S.queue[atomicAdd(S.s_tail, 1)] = u;
   }
@@ -928,8 +927,6 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
                                           const int32_t* __restrict__ in_src, const BigSet& S) {
   __syncthreads();
   const int32_t ns = min(*s_nst, C::kStage);
-  const int32_t tail0 = *S.s_tail;  // (approximate: it only steers the filter)
-  const bool filt = *S.s_filt;
   for (int32_t k0 = threadIdx.x; k0 < ns; k0 += kFlushBatch * C::kBlock) {
     int32_t u[kFlushBatch];
 #pragma unroll
@@ -943,11 +940,11 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
         if (u[q] >= 0) set_insert<C>(S, u[q]);
     } else {
       uint32_t old[kFlushBatch];
-      // with the filter on, a coherent load first: a source whose bit is
-      // already set costs a read instead of a device atomic
+      // a coherent load first: a source whose bit is already set (most of
+      // the live edges of a large set) costs a read instead of a device atomic
 #pragma unroll
       for (int q = 0; q < kFlushBatch; ++q)
-        old[q] = u[q] >= 0 && filt ? bitmap_word(S.bm, u[q]) : 0u;
+        old[q] = u[q] >= 0 ? bitmap_word(S.bm, u[q]) : 0u;
 #pragma unroll
       for (int q = 0; q < kFlushBatch; ++q)
         if (u[q] >= 0 && !(old[q] & (1u << (u[q] & 31))))
@@ -958,11 +955,7 @@ __device__ __forceinline__ void big_flush(const int32_t* stage, int32_t* s_nst,
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    *s_nst = 0;
-    // filter the next flush if most of this one's sources were seen before
-    if (!S.lds && !S.bits && ns > 0) *S.s_filt = 2 * (ns - (*S.s_tail - tail0)) > ns;
-  }
+  if (threadIdx.x == 0) *s_nst = 0;
   __syncthreads();
 }
 
@@ -986,7 +979,6 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
   __shared__ int32_t s_nst;
   __shared__ int32_t s_tail;
   __shared__ int32_t s_over;
-  __shared__ int32_t s_filt;
   __shared__ uint32_t s_item;
   __shared__ unsigned long long s_pos;
   uint32_t* bm = Bg.bitmaps + (size_t)blockIdx.x * Bg.nwords;
@@ -1008,7 +1000,7 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
     const uint64_t seed = ((uint64_t)G.seed_hi << 32) | G.seed_lo;
     const int32_t root = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
     unsigned long long s_ex = 0, s_lv = 0;
-    BigSet S{T.model == IM_IC, mhash, mq, bm, false, queue, &s_tail, &s_over, &s_filt};
+    BigSet S{T.model == IM_IC, mhash, mq, bm, false, queue, &s_tail, &s_over};
     if (T.model == IM_IC) {
       int32_t head = 0, tail = 1;
       for (int j = t; j < C::kH; j += C::kBlock) mhash[j] = kEmpty;
@@ -1016,7 +1008,6 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         s_tail = 0;
         s_over = 0;
         s_nst = 0;
-        s_filt = 0;
       }
       __syncthreads();
       if (item < kMaxHandoff) {  // resume from the small path's snapshot
