@@ -422,11 +422,19 @@ def bench_serve(args, im, W, torch):
             done = S.run_arrivals(server, qs)
         finally:
             server.close()
+        # each rate starts cold: the closed server's streams keep their
+        # library scratch (up to 16 GiB of large-set workers each) until
+        # released, and its pools stay in torch's cache until emptied
+        pool_stats, max_in_flight = server.pool_stats(), server.max_in_flight
+        del server
+        torch.cuda.synchronize()
+        im.release()
+        torch.cuda.empty_cache()
         for q, p in zip(done, plain):
             assert q.result["seeds"] == p["seeds"] and q.result["coverage"] == p["coverage"]
         served_pt = S.latency_summary(done)
-        served_pt["max_in_flight"] = server.max_in_flight
-        served_pt["pools"] = server.pool_stats()
+        served_pt["max_in_flight"] = max_in_flight
+        served_pt["pools"] = pool_stats
         points.append({"lambda_frac_of_plain_saturation": frac if frac else "burst",
                        "lambda_qps": round(lam, 3) if frac else "burst",
                        "served": served_pt, "plain": plain_pt})
