@@ -398,6 +398,7 @@ def bench_serve(args, im, W, torch):
     mu = len(service) / sum(service)
     log("plain path: %.2f queries/s saturation (mean service %.3fs)" % (mu, 1 / mu))
     points = []
+    slot_streams = [torch.cuda.Stream() for _ in range(args.slots)]
     for frac in (0.5, 1.0, 1.2, None):
         if frac is None:  # burst: every query arrives at once (saturation)
             lam = float("inf")
@@ -415,20 +416,20 @@ def bench_serve(args, im, W, torch):
         plain_pt = {"queries_per_s": len(lat) / (fin - arr[0]),
                     "p50_s": lat_s[int(np.ceil(0.5 * len(lat))) - 1],
                     "p99_s": lat_s[int(np.ceil(0.99 * len(lat))) - 1]}
-        server = S.Server(graphs, seed=seed, slots=args.slots, hbm_budget=160 << 30)
+        server = S.Server(graphs, seed=seed, slots=args.slots, hbm_budget=160 << 30,
+                          streams=slot_streams)
         qs = [S.Query(qid=j, graph=name, k=k, eps=eps, arrival=float(arr[j]))
               for j, (name, k, eps) in enumerate(spec)]
         try:
             done = S.run_arrivals(server, qs)
         finally:
             server.close()
-        # each rate starts cold: the closed server's streams keep their
-        # library scratch (up to 16 GiB of large-set workers each) until
-        # released, and its pools stay in torch's cache until emptied
+        # each rate starts with empty pools; the slots' streams (and the
+        # library scratch they hold, up to 16 GiB of large-set workers each)
+        # carry over, as in a long-running server
         pool_stats, max_in_flight = server.pool_stats(), server.max_in_flight
         del server
         torch.cuda.synchronize()
-        im.release()
         torch.cuda.empty_cache()
         for q, p in zip(done, plain):
             assert q.result["seeds"] == p["seeds"] and q.result["coverage"] == p["coverage"]

@@ -202,9 +202,16 @@ class Server:
 
     graphs: name -> prepared Graph.  Pools are created on first use per
     (graph, stream).  slots: queries in flight at once.  hbm_budget: bytes
-    that admitted queries' footprint estimates may sum to."""
+    that admitted queries' footprint estimates may sum to.  streams: the
+    slots' streams (one per slot, default priority), to be reused across
+    servers: the library keeps scratch per stream, so a server on streams
+    that served before starts with that scratch in place; None creates new
+    ones."""
 
-    def __init__(self, graphs: dict, seed: int, slots: int = 4, hbm_budget: int = 64 << 30):
+    def __init__(self, graphs: dict, seed: int, slots: int = 4, hbm_budget: int = 64 << 30,
+                 streams=None):
+        if streams is not None and len(streams) != slots:
+            raise ValueError("streams: one per slot")
         B.lib()
         self.graphs = graphs
         self.seed = seed
@@ -219,7 +226,8 @@ class Server:
         self.theta_seen = {}       # graph -> largest final theta so far
         self.threads = [threading.Thread(target=self._worker, daemon=True)
                         for _ in range(slots)]
-        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.streams = (list(streams) if streams is not None else
+                        [torch.cuda.Stream() for _ in range(slots)])
         for j, t in enumerate(self.threads):
             t.slot = j
             t.start()
