@@ -84,6 +84,28 @@ def test_sample_rrr(im, name, first, count):
     assert (r.examined, r.live) == (o.examined, o.live)
 
 
+@pytest.mark.parametrize("n,shape", [(49152, 1), (49153, 1), (98304, 2), (98305, 2)])
+def test_sample_large_sets_bitmap_tiers(im, n, shape):
+    """Supercritical IC sets (up to ~30 % of the graph) grown by the large-set
+    launch in each shape (1: one wavefront per set, 2: 256 threads) on both
+    sides of the largest graph whose bitmap fits the LDS pool (49,152 and
+    98,304 vertices): LDS bitmap below, HBM bitmap with its read-before-atomic
+    above; every set equals the oracle's."""
+    _say("sample bitmap tiers", n, shape)
+    g = W.random_small_graph(n, 4 * n, seed=11, p_hi=0.6)
+    G = _prep(im, g)
+    im.tune_set(im.TUNE_BIG_SHAPE, shape)
+    try:
+        r = im.sample_rrr(G, seed=4242, stream_tag=0, first=0, count=200)
+    finally:
+        im.tune_set(im.TUNE_BIG_SHAPE, -1)
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), 4242, 0, 0, 200)
+    assert int(np.diff(o.off).max()) > 4096  # the sets do leave the LDS hash tier
+    assert np.array_equal(_np(r.off), o.off)
+    assert np.array_equal(_np(r.mem), o.mem)
+    assert (r.examined, r.live) == (o.examined, o.live)
+
+
 def test_sample_edge_cases(im):
     _say("sample edge cases")
     g = GRAPHS["ic_sparse"]()
