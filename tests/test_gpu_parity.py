@@ -361,7 +361,8 @@ def test_batch_matches_single_calls_and_oracle(im, form, monkeypatch):
 def test_serving_results_equal_alone(im):
     """Queries served together from shared, growing sample pools (3 slots on
     3 streams) return exactly what im_solve returns for each query alone;
-    with a one-byte HBM budget admission serialises them, same results."""
+    with a one-byte HBM budget admission serialises them, same results.  The
+    second server runs on the first one's streams (and their scratch)."""
     _say("serving")
     from paper_2408_10982_amd import serve as S
     gs = {"ic": W.random_small_graph(3000, 15000, seed=21, p_hi=0.2),
@@ -371,8 +372,11 @@ def test_serving_results_equal_alone(im):
     spec = [("ic" if j % 2 else "lt", int(rng.integers(3, 20)), float(rng.choice([0.5, 0.3])))
             for j in range(10)]
     alone = [im.solve(prepared[name], k, eps, seed=5005) for name, k, eps in spec]
+    streams = [torch.cuda.Stream() for _ in range(3)]  # shared by both servers
+    with pytest.raises(ValueError):
+        S.Server(prepared, seed=5005, slots=3, streams=streams[:2])
     for budget, expect_overlap in ((1 << 40, True), (1, False)):
-        server = S.Server(prepared, seed=5005, slots=3, hbm_budget=budget)
+        server = S.Server(prepared, seed=5005, slots=3, hbm_budget=budget, streams=streams)
         qs = [S.Query(qid=j, graph=name, k=k, eps=eps, arrival=0.0)
               for j, (name, k, eps) in enumerate(spec)]
         done = S.run_arrivals(server, qs)
