@@ -464,35 +464,76 @@ __global__ void k_partition(int32_t n, int32_t m, uint32_t s_lo, uint32_t s_hi,
 }
 
 // Counting sort of vertices by partition (stable in v): order, tile tables.
-__global__ void k_part_hist(int32_t n, const uint8_t* __restrict__ part,
-                            uint32_t* __restrict__ hist) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicAdd(&hist[part[v]], 1u);
+// The vertices of every partition in ascending id, by a stable counting
+// sort over chunks of kPartChunk vertices: count (a partition-major matrix
+// M[p][chunk] and the per-partition totals), an exclusive scan of M (the
+// place of each (partition, chunk) run), and a scatter that ranks each
+// vertex among the earlier ones of its chunk in the same partition.
+constexpr int kPartChunk = 8192;
+constexpr int kPartBlock = 256;
+
+__global__ __launch_bounds__(kPartBlock) void k_part_count(int32_t n, int32_t m,
+                                                           const uint8_t* __restrict__ part,
+                                                           int64_t nchunks,
+                                                           uint32_t* __restrict__ M,
+                                                           uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kMaxParts];
+  const int64_t c = blockIdx.x;
+  for (int q = threadIdx.x; q < m; q += kPartBlock) h[q] = 0u;
+  __syncthreads();
+  const int64_t v0 = c * kPartChunk, v1 = min((int64_t)n, v0 + kPartChunk);
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += kPartBlock) atomicAdd(&h[part[v]], 1u);
+  __syncthreads();
+  for (int q = threadIdx.x; q < m; q += kPartBlock) {
+    const uint32_t x = h[q];
+    M[(int64_t)q * nchunks + c] = x;
+    if (x) atomicAdd(&hist[q], x);
+  }
 }
 
-// One block per partition scans the vertex range in order, writing the
-// partition's vertices in ascending id (stable).
-__global__ __launch_bounds__(kGBlock) void k_part_order(int32_t n, const uint8_t* __restrict__ part,
-                                                        const int64_t* __restrict__ pbase,
-                                                        int32_t* __restrict__ order) {
-  __shared__ int64_t lds[kGBlock / kWave + 1];
-  const int p = blockIdx.x;
-  int64_t base = pbase[p];
-  for (int64_t v0 = 0; v0 < n; v0 += kGBlock) {
-    const int64_t v = v0 + threadIdx.x;
-    const int flag = (v < n && part[v] == (uint8_t)p) ? 1 : 0;
-    // block exclusive scan of flag
-    const int l = lane_id(), w = threadIdx.x / kWave;
-    int inc = wave_inclusive_scan(flag);
-    if (l == kWave - 1) lds[w] = inc;
+// One block per chunk, kPartBlock vertices per round in id order.  Lanes of a
+// wavefront with equal partition ids are found by one ballot per bit of the
+// id; a vertex's place is its run's start (Moff), the chunk's earlier rounds
+// (cur), the earlier wavefronts of this round (wc) and its rank among the
+// lanes below it.
+__global__ __launch_bounds__(kPartBlock) void k_part_scatter(int32_t n, int32_t m,
+                                                             const uint8_t* __restrict__ part,
+                                                             int64_t nchunks,
+                                                             const int64_t* __restrict__ Moff,
+                                                             int32_t* __restrict__ order) {
+  constexpr int kNW = kPartBlock / kWave;
+  __shared__ uint32_t cur[kMaxParts];
+  __shared__ uint32_t wc[kNW][kMaxParts];
+  const int64_t c = blockIdx.x;
+  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+  for (int q = t; q < kMaxParts; q += kPartBlock) cur[q] = 0u;
+  const int64_t v0 = c * kPartChunk, v1 = min((int64_t)n, v0 + kPartChunk);
+  for (int64_t vb = v0; vb < v1; vb += kPartBlock) {
+    for (int q = lane; q < kMaxParts; q += kWave) wc[w][q] = 0u;
     __syncthreads();
-    int64_t before = 0, tot = 0;
-    for (int j = 0; j < kGBlock / kWave; ++j) {
-      if (j < w) before += lds[j];
-      tot += lds[j];
+    const int64_t v = vb + t;
+    const bool valid = v < v1;
+    const uint32_t p = valid ? (uint32_t)part[v] : 0u;
+    unsigned long long same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long ones = __ballot(valid && ((p >> b) & 1u));
+      same &= ((p >> b) & 1u) ? ones : ~ones;
     }
-    if (flag) order[base + before + inc - 1] = (int32_t)v;
-    base += tot;
+    const uint32_t rank = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    if (valid && rank == 0u) wc[w][p] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t before = cur[p];
+      for (int j = 0; j < w; ++j) before += wc[j][p];
+      order[Moff[(int64_t)p * nchunks + c] + before + rank] = (int32_t)v;
+    }
+    __syncthreads();
+    for (int q = t; q < m; q += kPartBlock) {
+      uint32_t add = 0u;
+      for (int j = 0; j < kNW; ++j) add += wc[j][q];
+      cur[q] += add;
+    }
     __syncthreads();
   }
 }
@@ -591,9 +632,13 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   k_partition<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
       n, m, (uint32_t)part_seed, (uint32_t)(part_seed >> 32), part);
   IM_HIP(hipGetLastError());
-  // scratch: gmax(k*m) | done | pbase(m+1) | hist(m) | order(n) | pos_of(n) | cnt(n) | covered(m*count)
+  // scratch: gmax(k*m) | done | pbase(m+1) | hist(m) | order(n) | pos_of(n) | cnt(n) |
+  // covered(m*count) | M(m*nch) | Moff(m*nch+1)
+  const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
+  const size_t cells = (size_t)m * (size_t)nch;
   const size_t bytes = (size_t)m * k * 8 + 64 + 64 + (size_t)(m + 1) * 8 + (size_t)m * 4 + 64 +
-                       (size_t)n * 12 + (size_t)m * (size_t)count + 256;
+                       (size_t)n * 12 + (size_t)m * (size_t)count + 256 +
+                       (cells * 4 + 64) / 64 * 64 + (cells + 1) * 8 + 64;
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotLocal, bytes, &p));
   char* c = (char*)p;
@@ -612,9 +657,15 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   uint32_t* cnt = (uint32_t*)c;
   c += (size_t)n * 4;
   uint8_t* covered = (uint8_t*)c;
+  c += (size_t)m * (size_t)count;
+  c = (char*)(((uintptr_t)c + 63) / 64 * 64);
+  uint32_t* M = (uint32_t*)c;
+  c += (cells * 4 + 63) / 64 * 64;
+  int64_t* Moff = (int64_t*)c;
   IM_HIP(hipMemsetAsync(hist, 0, (size_t)m * 4, s));
-  k_part_hist<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, part, hist);
+  k_part_count<<<dim3((unsigned)nch), dim3(kPartBlock), 0, s>>>(n, m, part, nch, M, hist);
   IM_HIP(hipGetLastError());
+  IM_TRY(exclusive_scan_u32_to_i64(M, (int64_t)cells, Moff, s));
   std::vector<uint32_t> hh(m);
   IM_HIP(hipMemcpyAsync(hh.data(), hist, (size_t)m * 4, hipMemcpyDeviceToHost, s));
   IM_HIP(hipStreamSynchronize(s));
@@ -622,7 +673,7 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   hb[0] = 0;
   for (int q = 0; q < m; ++q) hb[q + 1] = hb[q] + hh[q];
   IM_HIP(hipMemcpyAsync(pbase, hb.data(), (size_t)(m + 1) * 8, hipMemcpyHostToDevice, s));
-  k_part_order<<<dim3(m), dim3(kGBlock), 0, s>>>(n, part, pbase, order);
+  k_part_scatter<<<dim3((unsigned)nch), dim3(kPartBlock), 0, s>>>(n, m, part, nch, Moff, order);
   IM_HIP(hipGetLastError());
   k_pos_of<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, order, pos_of);
   IM_HIP(hipGetLastError());
