@@ -71,6 +71,7 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
   __shared__ int32_t ns[kMaxBuckets];
   __shared__ long long csz[kMaxBuckets];
   __shared__ unsigned long long gain[kMaxBuckets];
+  __shared__ long long s_thr[kMaxBuckets];
   __shared__ unsigned long long s_accept;
   __shared__ int32_t s_live;
   const int tid = threadIdx.x, lane = lane_id();
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
   if (tid < kMaxBuckets) {
     ns[tid] = 0;
     csz[tid] = 0;
+    s_thr[tid] = tid < A.B ? A.thr[tid] : 0;
   }
   const uint64_t all = A.B >= 64 ? ~0ull : ((1ull << A.B) - 1ull);
   __syncthreads();
@@ -89,11 +91,9 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
       const int32_t x = A.lseeds[(int64_t)p * A.k + t];
       const int64_t a = A.inc_off[x], b = A.inc_off[x + 1];
       if (tid < kMaxBuckets) gain[tid] = 0;
-      if (tid == 0) {
-        uint64_t open = 0;
-        for (int q = 0; q < A.B; ++q)
-          if (ns[q] < A.k) open |= 1ull << q;
-        s_live = open != 0;
+      if (tid < kWave) {  // wavefront 0, lane q: bucket q still open
+        const unsigned long long open = __ballot(tid < A.B && ns[tid] < A.k);
+        if (tid == 0) s_live = open != 0ull;
       }
       __syncthreads();
       const int32_t live = s_live;
@@ -113,17 +113,16 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
       }
       if (acc) atomicAdd(&gain[lane], acc);
       __syncthreads();
-      if (tid == 0) {
-        uint64_t acc_mask = 0;
-        for (int q = 0; q < A.B; ++q) {
-          if (ns[q] < A.k && (long long)gain[q] >= A.thr[q]) {
-            acc_mask |= 1ull << q;
-            A.bseeds[(int64_t)q * A.k + ns[q]] = x;
-            ns[q] += 1;
-            csz[q] += (long long)gain[q];
-          }
+      if (tid < kWave) {  // wavefront 0, lane q decides bucket q (buckets are independent)
+        const int q = tid;
+        const bool take = q < A.B && ns[q] < A.k && (long long)gain[q] >= s_thr[q];
+        if (take) {
+          A.bseeds[(int64_t)q * A.k + ns[q]] = x;
+          ns[q] += 1;
+          csz[q] += (long long)gain[q];
         }
-        s_accept = acc_mask;
+        const unsigned long long acc_mask = __ballot(take);
+        if (tid == 0) s_accept = acc_mask;
       }
       __syncthreads();
       const uint64_t acc_mask = s_accept;
