@@ -79,8 +79,10 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
   if (tid < kMaxBuckets) {
     ns[tid] = 0;
     csz[tid] = 0;
+    gain[tid] = 0;
     s_thr[tid] = tid < A.B ? A.thr[tid] : 0;
   }
+  if (tid == 0) s_live = A.B > 0;
   const uint64_t all = A.B >= 64 ? ~0ull : ((1ull << A.B) - 1ull);
   __syncthreads();
   int32_t slen = 0;
@@ -90,15 +92,9 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
       ++slen;
       const int32_t x = A.lseeds[(int64_t)p * A.k + t];
       const int64_t a = A.inc_off[x], b = A.inc_off[x + 1];
-      if (tid < kMaxBuckets) gain[tid] = 0;
-      if (tid < kWave) {  // wavefront 0, lane q: bucket q still open
-        const unsigned long long open = __ballot(tid < A.B && ns[tid] < A.k);
-        if (tid == 0) s_live = open != 0ull;
-      }
-      __syncthreads();
-      const int32_t live = s_live;
-      __syncthreads();
-      if (!live) continue;  // every bucket is full: nothing can change
+      // s_live: some bucket still open (set at the last decision, read after
+      // the barrier that ended it)
+      if (!s_live) continue;  // every bucket is full: nothing can change
       unsigned long long acc = 0;  // lane q: uncovered count of bucket q in this wave
       for (int64_t base = a; base < b; base += kSBlock) {
         const int64_t e = base + tid;
@@ -121,8 +117,13 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
           ns[q] += 1;
           csz[q] += (long long)gain[q];
         }
+        gain[q] = 0;  // for the next set
         const unsigned long long acc_mask = __ballot(take);
-        if (tid == 0) s_accept = acc_mask;
+        const unsigned long long open = __ballot(q < A.B && ns[q] < A.k);
+        if (tid == 0) {
+          s_accept = acc_mask;
+          s_live = open != 0ull;
+        }
       }
       __syncthreads();
       const uint64_t acc_mask = s_accept;
