@@ -107,7 +107,8 @@ int im_release(void);
  * changes any result: the sets, seeds, gains and coverage are the same bit
  * for bit, only the time differs.  Process-wide; read at each call.
  *   IM_TUNE_SAMPLE_BLOCKS  workgroups (4 wavefronts) per CU of the main IC
- *                          sampling launch, 1..64 (default 8)
+ *                          sampling launch, 1..64 (default 5: as many as are
+ *                          resident at once, so none starts late)
  *   IM_TUNE_BIG_SHAPE      large-set launch: 1 one wavefront per set (24 per
  *                          CU), 2 256 threads per set (8 per CU), 0 automatic
  *                          (one wavefront unless more than 1/8 of the

@@ -17,7 +17,7 @@ from . import binding as B
 
 # knob name -> (C ABI key, candidate values)
 KNOBS = {
-    "sample_blocks": (B.TUNE_SAMPLE_BLOCKS, (4, 6, 8, 12, 16)),
+    "sample_blocks": (B.TUNE_SAMPLE_BLOCKS, (4, 5, 6, 8, 12)),
     "big_shape": (B.TUNE_BIG_SHAPE, (0, 1, 2)),
     "apply_blocks": (B.TUNE_APPLY_BLOCKS, (1, 2, 4)),
     "dense_ratio": (B.TUNE_DENSE_RATIO, (64, 256, 4096)),

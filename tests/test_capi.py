@@ -72,7 +72,7 @@ def test_tune_knobs_validate_and_round_trip():
         assert L.im_tune_get(key, ctypes.byref(v)) == 0
         return v.value
 
-    defaults = {0: 8, 1: 0, 2: 1, 3: 256}
+    defaults = {0: 5, 1: 0, 2: 1, 3: 256}
     assert {k: get(k) for k in defaults} == defaults
     for key, bad in ((0, 0), (0, 65), (1, 3), (2, 0), (2, 17), (3, -2), (4, 1), (-1, 1)):
         assert L.im_tune_set(key, bad) == -1, (key, bad)

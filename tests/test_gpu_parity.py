@@ -446,7 +446,7 @@ def test_autotune_keeps_results(im):
         AT.reset()
     assert set(res["settings"]) == set(AT.KNOBS)
     assert len(res["trials"]) == 1 + sum(len(c) - 1 for _, c in AT.KNOBS.values())
-    assert AT.current() == {"sample_blocks": 8, "big_shape": 0, "apply_blocks": 1,
+    assert AT.current() == {"sample_blocks": 5, "big_shape": 0, "apply_blocks": 1,
                             "dense_ratio": 256}
     o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), seed, 0, 0, count)
     oio, oim = O.incidence(g.n, o)
