@@ -74,6 +74,9 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
   __shared__ long long s_thr[kMaxBuckets];
   __shared__ unsigned long long s_accept;
   __shared__ int32_t s_live;
+  __shared__ int32_t px[kSBlock];  // the next kSBlock stream entries: vertex,
+  __shared__ int64_t pa[kSBlock];  // and the range of S(x) (pb = -1: no entry,
+  __shared__ int64_t pb[kSBlock];  // past that partition's local count)
   const int tid = threadIdx.x, lane = lane_id();
   for (int64_t j = tid; j < A.count; j += kSBlock) A.masks[j] = 0ull;
   if (tid < kMaxBuckets) {
@@ -86,12 +89,33 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
   const uint64_t all = A.B >= 64 ? ~0ull : ((1ull << A.B) - 1ull);
   __syncthreads();
   int32_t slen = 0;
-  for (int t = 0; t < A.T; ++t) {
-    for (int p = 0; p < A.m; ++p) {
-      if (t >= A.lcount[p]) continue;  // uniform
+  // stream order: position t of every partition p in turn, entry j = t * m + p;
+  // each chunk of kSBlock entries is looked up by the whole block at once
+  const int64_t n_entries = (int64_t)A.T * A.m;
+  for (int64_t j0 = 0; j0 < n_entries; j0 += kSBlock) {
+    {
+      const int64_t j = j0 + tid;
+      int32_t x = -1;
+      int64_t a = 0, b = -1;
+      if (j < n_entries) {
+        const int t = (int)(j / A.m), p = (int)(j % A.m);
+        if (t < A.lcount[p]) {
+          x = A.lseeds[(int64_t)p * A.k + t];
+          a = A.inc_off[x];
+          b = A.inc_off[x + 1];
+        }
+      }
+      px[tid] = x;
+      pa[tid] = a;
+      pb[tid] = b;
+    }
+    __syncthreads();
+    const int n_in = (int)min((int64_t)kSBlock, n_entries - j0);
+    for (int jj = 0; jj < n_in; ++jj) {
+      if (pb[jj] < 0) continue;  // uniform
       ++slen;
-      const int32_t x = A.lseeds[(int64_t)p * A.k + t];
-      const int64_t a = A.inc_off[x], b = A.inc_off[x + 1];
+      const int32_t x = px[jj];
+      const int64_t a = pa[jj], b = pb[jj];
       // s_live: some bucket still open (set at the last decision, read after
       // the barrier that ended it)
       if (!s_live) continue;  // every bucket is full: nothing can change
@@ -131,6 +155,7 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
         for (int64_t e = a + tid; e < b; e += kSBlock) A.masks[A.inc_mem[e]] |= acc_mask;
       __syncthreads();
     }
+    __syncthreads();  // every entry of the chunk read before the next chunk
   }
   if (tid == 0) {
     int bs = 0;
