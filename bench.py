@@ -1,21 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the influence-maximization hot path on one MI355X.
 
-A step is one pass of the whole path over one batch of synthetic input:
-RRR sampling of theta sets (root draw, IC reverse BFS), the covering subsets,
-and greedy max-k-cover.  Default workload: R-MAT scale 20 (2^20 vertices,
-2^24 edges), IC with weighted-cascade probabilities 1/indeg(v), theta = 2^20,
-k = 100.  Inputs are resident in HBM before the timed region starts.  Steps
-alternate over --streams streams (3 by default), so that one step's covering
-subsets and greedy, a chain of small launches, run beside the next step's
-sampling; every step does all of its work, and ms_per_step_one_stream gives
-the rate without that overlap.  Per-phase and per-kernel times come from
-steps run one at a time on one stream.
+Default workload (the paper's method end to end, every step of the path):
+R-MAT scale 22 (2^22 vertices, 2^26 edges), LT with uniform in-weights
+normalised per vertex, IMM with epsilon = 0.13 and k = 100, GreediRIS
+selection with m = 64 partitions, delta = 0.077 and truncation alpha = 0.125.
+A step is one whole im_solve: the martingale rounds (sampling, covering
+subsets, RandGreedi local greedy over the 64 partitions, streaming bucket
+cover, final choice, the lower-bound test), then theta fresh samples and the
+same selection on them.  Inputs are resident in HBM before the timed region.
+The same run also times alpha = 1 and the plain IC weighted-cascade workload
+(R-MAT scale 20, theta = 2^20, greedy k = 100) and reports them as extra keys.
 
 Prints one JSON line on stdout.  `roofline` describes the dominant kernel
-(algorithmic bytes per launch over its event-timed duration); `cpu_baseline`
-times the single-threaded CPU oracle on a bounded sample of the same work.
-Progress goes to stderr.
+(algorithmic bytes per launch over its event-timed duration, from HIP events
+the library records on the solve's stream); `cpu_baseline` times the
+single-threaded CPU oracle on the same solve.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -45,6 +45,14 @@ def sampling_bytes(sets, total, examined, live, run_length=True):
     return 8 * sets + (20 if run_length else 12) * total + 4 * examined + 4 * live
 
 
+def lt_sampling_bytes(sets, total, examined):
+    """Algorithmic bytes of LT sampling: per set its offset (8 B); per member
+    its two in-CSR offsets read (8 B), the kept edge's source read (4 B) and
+    its id written (4 B); per binary-search probe one threshold (4 B; the
+    examined counter charges ceil(log2(indeg + 1)) probes per expanded vertex)."""
+    return 8 * sets + 16 * total + 4 * examined
+
+
 # Measured HBM traffic per launch of a kernel: profiles/traffic_<workload>.md
 # holds lines "traffic <kernel> bytes_per_launch=<B> source_sha256=<H>", taken
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE passes scaled against a plain copy.
@@ -53,6 +61,7 @@ MAIN_IC = "k_sample_ic_small"
 KERNEL_SOURCES = {
     MAIN_IC: ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],
     "k_sample_big": ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],
+    "k_sample_lt": ["csrc/common.h", "csrc/sample.h", "csrc/sample.hip"],
 }
 
 
@@ -103,16 +112,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5])
     ap.add_argument("--tasks", type=int, default=256)
     ap.add_argument("--queries", type=int, default=24)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--alpha", type=float, default=0.125)
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="RRR sets the CPU oracle times (0: the whole workload)")
+                    help="configs 1-2: RRR sets the CPU oracle times (0: the whole workload)")
     ap.add_argument("--streams", type=int, default=3,
                     help="configs 1-2: streams the steps alternate over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="config 3: skip the alpha = 1 and weighted-cascade extra keys")
     ap.add_argument("--no-autotune", action="store_true",
                     help="config 4: keep the default launch shapes")
     ap.add_argument("--tune-tasks", type=int, default=32,
@@ -133,6 +144,16 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    try:
+        run(args, im, W, torch)
+    finally:
+        # hand the library's scratch back while the runtime is whole, so that
+        # exit-time teardown frees no HIP memory of ours
+        torch.cuda.synchronize()
+        im.release()
+
+
+def run(args, im, W, torch):
     if args.calibrate_copy:
         nbytes = 1 << 30
         src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -156,8 +177,21 @@ def main():
     G = im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
     torch.cuda.synchronize()
     if args.config == 3:
-        return bench_imm(args, w, G, im, torch)
+        return bench_imm(args, w, G, im, W, torch)
+    out = run_plain(args, w, G, im, torch)
+    if not args.no_cpu_baseline:
+        n_cpu = args.cpu_sample if args.cpu_sample > 0 else w.theta
+        log("cpu baseline: oracle on %d sets" % n_cpu)
+        out["cpu_baseline"] = cpu_baseline(w, min(n_cpu, w.theta))
+    print(json.dumps(out), flush=True)
 
+
+def run_plain(args, w, G, im, torch, steps=None, warmup=None):
+    """Configs 1-2: a step samples theta sets, builds the covering subsets and
+    runs greedy; steps alternate over --streams streams."""
+    g = w.graph
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     cap = [max(4 * w.theta, 1 << 20)]
 
     # Step i runs on stream i mod S: its covering subsets and greedy (a chain
@@ -181,25 +215,25 @@ def main():
             record.append((r, ev, (seeds, gains, nsel, cov)))
         return r
 
-    def timed(n_streams, steps, record):
+    def timed(n_streams, nsteps, record):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for i in range(steps):
+        for i in range(nsteps):
             step(record, streams[i % n_streams])
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
-    for i in range(max(args.warmup, len(streams))):
+    for i in range(max(warmup, len(streams))):
         step(None, streams[i % len(streams)])
         torch.cuda.synchronize()
         log("warmup %d done" % i)
     serial = []
-    ms_serial = 1e3 * timed(1, args.steps, serial) / args.steps
+    ms_serial = 1e3 * timed(1, steps, serial) / steps
     recs = []
-    t_total = timed(len(streams), args.steps, recs)
+    t_total = timed(len(streams), steps, recs)
     log("timed %d steps in %.3fs on %d streams (one stream: %.3f ms/step)" %
-        (args.steps, t_total, len(streams), ms_serial))
-    ms_step = 1e3 * t_total / args.steps
+        (steps, t_total, len(streams), ms_serial))
+    ms_step = 1e3 * t_total / steps
 
     r0, _, out0 = recs[0]
     seeds0 = out0[0].cpu().tolist()
@@ -239,13 +273,13 @@ def main():
                              "frac": round(alu_tops / INT_PEAK_TOPS, 4)}}
 
     value = w.theta / (ms_step * 1e-3)
-    out = {
+    return {
         "metric": "RRR sets/s through sampling + max-k-cover (bit-exact)",
         "value": round(value, 1),
         "unit": "RRR sets/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -256,7 +290,8 @@ def main():
         "ms_per_step_one_stream": round(ms_serial, 3),
         "config": {"workload": w.name, "graph": "R-MAT (0.57,0.19,0.19) scale %d, %d edges"
                    % (g.n.bit_length() - 1, g.num_edges),
-                   "model": "IC weighted cascade" if args.config == 2 else "IC uniform [0,0.1)",
+                   "model": "IC weighted cascade" if w.name == "rmat20_ic_wc"
+                   else "IC uniform [0,0.1)",
                    "theta": w.theta, "k": w.k, "selector": "greedy"},
         "sampling_sets_per_s": round(w.theta / (ms_sample * 1e-3), 1),
         "cover_ms": round(ms_inc + ms_greedy, 3),
@@ -270,11 +305,6 @@ def main():
                    "coverage": cov0, "seeds_head": seeds0[:8]},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
-        n_cpu = args.cpu_sample if args.cpu_sample > 0 else w.theta
-        log("cpu baseline: oracle on %d sets" % n_cpu)
-        out["cpu_baseline"] = cpu_baseline(w, min(n_cpu, w.theta))
-    print(json.dumps(out), flush=True)
 
 
 def bench_batch(args, im, W, torch):
@@ -463,51 +493,116 @@ def bench_serve(args, im, W, torch):
     print(json.dumps(out), flush=True)
 
 
-def bench_imm(args, w, G, im, torch):
+def solve_steps(im, G, w, alpha, steps, warmup, torch):
+    """Times `steps` whole solves after `warmup` untimed ones; every timed
+    solve must give the same seeds.  Returns (seconds per solve, results)."""
+    kw = dict(selector=im.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha, seed=w.seed,
+              part_seed=w.part_seed)
+    for i in range(warmup):
+        res = im.solve(G, w.k, w.eps, **kw)
+        log("alpha %g warmup %d: theta=%d rounds=%d coverage=%d sample launches %d passes %d"
+            % (alpha, i, res["theta"], res["rounds"], res["coverage"], res["sample_launches"],
+               res["sample_passes"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [im.solve(G, w.k, w.eps, **kw) for _ in range(steps)]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    for o in outs[1:]:
+        assert o["seeds"] == outs[0]["seeds"] and o["theta"] == outs[0]["theta"]
+    return dt, outs
+
+
+def bench_imm(args, w, G, im, W, torch):
     """LT + IMM + GreediRIS: a step is one whole im_solve (martingale rounds,
     final sampling, RandGreedi local greedy over m partitions, streaming
     bucket cover with truncation, final choice)."""
-    kw = dict(selector=im.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=args.alpha, seed=w.seed,
-              part_seed=w.part_seed)
-    for i in range(args.warmup):
-        res = im.solve(G, w.k, w.eps, **kw)
-        log("warmup %d: theta=%d rounds=%d coverage=%d" % (i, res["theta"], res["rounds"],
-                                                           res["coverage"]))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    outs = [im.solve(G, w.k, w.eps, **kw) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt, outs = solve_steps(im, G, w, args.alpha, args.steps, args.warmup, torch)
     res = outs[0]
-    for o in outs[1:]:
-        assert o["seeds"] == res["seeds"] and o["theta"] == res["theta"]
     samples = res["theta"] + res["martingale_samples"]
+    mean = lambda key: sum(o[key] for o in outs) / len(outs)  # noqa: E731
+    # the dominant kernel: the LT walk launch, one per sampling pass
+    passes = res["sample_passes"]
+    b_launch = lt_sampling_bytes(res["sampled_sets"], res["sampled_total"],
+                                 res["sampled_examined"]) / passes
+    ms_launch = mean("ms_sample_main") / passes
+    achieved = b_launch / (ms_launch * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic(w.name, "k_sample_lt"), "kernel": "k_sample_lt",
+                "algorithmic_bytes": int(b_launch), "kernel_ms": round(ms_launch, 4),
+                "launches_per_step": passes}
+    ms_solve = dt * 1e3
     out = {
         "metric": "RRR sets/s through IMM with GreediRIS selection (bit-exact)",
         "value": round(samples / dt, 1), "unit": "RRR sets/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_solve, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": w.name, "graph": "R-MAT (0.57,0.19,0.19) scale 22, %d edges"
                    % G.num_edges, "model": "LT, uniform weights normalised per vertex",
-                   "k": w.k, "eps": w.eps, "m": w.m, "delta": w.delta, "alpha": args.alpha},
+                   "k": w.k, "eps": w.eps, "selector": "GreediRIS", "m": w.m,
+                   "delta": w.delta, "alpha": args.alpha},
         "theta": res["theta"], "martingale_samples": res["martingale_samples"],
         "rounds": res["rounds"], "coverage": res["coverage"], "bucket": res["bucket"],
         "streamed_solution_chosen": res["global_won"], "final_sum_rrr": res["final_total"],
         "seeds_head": res["seeds"][:8],
+        "sampling_sets_per_s": round(res["sampled_sets"] /
+                                     ((mean("ms_sample_main") + mean("ms_sample_large") +
+                                       mean("ms_sample_gather")) * 1e-3), 1),
+        "cover_ms": round(mean("ms_select"), 3),
+        "breakdown_ms": {"sample_main_kernel": round(mean("ms_sample_main"), 3),
+                         "sample_large_kernel": round(mean("ms_sample_large"), 3),
+                         "sample_gather": round(mean("ms_sample_gather"), 3),
+                         "select_all_rounds": round(mean("ms_select"), 3)},
+        "counts": {"sampled_sets": res["sampled_sets"], "sampled_sum_rrr": res["sampled_total"],
+                   "probes": res["sampled_examined"], "edges_taken": res["sampled_live"],
+                   "sample_launches": res["sample_launches"], "sample_passes": passes},
+        "roofline": roofline,
     }
+    if not args.no_extra:
+        dt1, outs1 = solve_steps(im, G, w, 1.0, args.steps, 1, torch)
+        r1 = outs1[0]
+        out["alpha_1"] = {"ms_per_step": round(dt1 * 1e3, 3),
+                          "value": round((r1["theta"] + r1["martingale_samples"]) / dt1, 1),
+                          "coverage": r1["coverage"], "bucket": r1["bucket"],
+                          "streamed_solution_chosen": r1["global_won"],
+                          "cover_ms": round(sum(o["ms_select"] for o in outs1) / len(outs1), 3),
+                          "seeds_head": r1["seeds"][:8]}
+        log("alpha 1: %.3f ms per solve" % (dt1 * 1e3))
+        w2 = W.config(2)
+        g2 = w2.graph
+        G2 = im.prepare_graph(g2.in_off, g2.in_src, g2.weight, g2.model)
+        torch.cuda.synchronize()
+        o2 = run_plain(args, w2, G2, im, torch, steps=20, warmup=5)
+        out["rmat20_ic_wc"] = {k: o2[k] for k in ("value", "unit", "ms_per_step",
+                                                  "ms_per_step_one_stream", "streams",
+                                                  "sampling_sets_per_s", "cover_ms",
+                                                  "breakdown_ms", "roofline")}
+        out["rmat20_ic_wc"]["config"] = o2["config"]
+        out["rmat20_ic_wc"]["coverage"] = o2["counts"]["coverage"]
+        del G2, w2, g2
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         import oracle as O
         g = w.graph
         thr = O.thresholds(g.model, g.in_off, g.weight)
-        ns = 200000
+        log("cpu baseline: the oracle's whole IMM + GreediRIS solve")
         t1 = time.perf_counter()
-        O.sample(g.model, g.in_off, g.in_src, thr, w.seed, 1, 0, ns)
+        ores = O.imm(g.model, g.in_off, g.in_src, thr, w.k, w.eps, seed=w.seed,
+                     selector=O.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=args.alpha,
+                     part_seed=w.part_seed, lazy=True)
         d1 = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": ns / d1, "unit": "RRR sets/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "LT sampling of final-stream sets 0..%d only "
-                                         "(no selection); %.1f s" % (ns - 1, d1)}
+        same = (ores["seeds"].tolist() == res["seeds"] and ores["theta"] == res["theta"] and
+                ores["coverage"] == res["coverage"])
+        out["cpu_baseline"] = {
+            "value": round((ores["theta"] + ores["martingale_samples"]) / d1, 1),
+            "unit": "RRR sets/s", "cores": 1, "kind": "oracle",
+            "sample": "the whole solve of this workload (IMM rounds, %d + %d samples, local "
+                      "lazy greedy over %d partitions, streaming cover, final choice); %.1f s; "
+                      "same seeds, theta and coverage as the GPU: %s"
+                      % (ores["martingale_samples"], ores["theta"], w.m, d1, same)}
+        assert same, "the oracle's solve differs from the GPU's"
     print(json.dumps(out), flush=True)
 
 

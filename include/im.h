@@ -283,7 +283,20 @@ typedef struct {
   int64_t martingale_samples;  /* samples drawn in the martingale rounds */
   int32_t bucket;              /* b* of the last GreediRIS selection, else -1 */
   int32_t global_won;          /* 1 if the streamed solution won, 0 if local, -1 n/a */
+  int32_t stream_len;          /* seeds streamed in the last GreediRIS selection, else 0 */
   int64_t final_total;         /* sum of set sizes of the final samples */
+  /* Sampling and selection tally of the whole call (martingale rounds and
+   * final samples).  Each pool extension samples its new sets once; the
+   * counters are exact (as im_sample_stats), the times are device times of
+   * the launches from HIP events on `stream`. */
+  int32_t sample_launches;     /* sampling calls (pool extensions) */
+  int32_t sample_passes;       /* main sampling launches (> launches only if a
+                                  staging arena was short and a call sampled again) */
+  int64_t sampled_sets, sampled_total, sampled_examined, sampled_live;
+  double ms_sample_main;       /* main sampling launches (LT walks, or small IC sets) */
+  double ms_sample_large;      /* large-set launches */
+  double ms_sample_gather;     /* copies into the canonical pools */
+  double ms_select;            /* covering subsets + selection, every round */
 } im_solve_result;
 
 /*

@@ -60,7 +60,13 @@ class _SolveResult(C.Structure):
     _fields_ = [("nsel", C.c_int32), ("coverage", C.c_int64), ("theta", C.c_int64),
                 ("rounds", C.c_int32), ("lower_bound", C.c_double),
                 ("martingale_samples", C.c_int64), ("bucket", C.c_int32),
-                ("global_won", C.c_int32), ("final_total", C.c_int64)]
+                ("global_won", C.c_int32), ("stream_len", C.c_int32),
+                ("final_total", C.c_int64),
+                ("sample_launches", C.c_int32), ("sample_passes", C.c_int32),
+                ("sampled_sets", C.c_int64), ("sampled_total", C.c_int64),
+                ("sampled_examined", C.c_int64), ("sampled_live", C.c_int64),
+                ("ms_sample_main", C.c_double), ("ms_sample_large", C.c_double),
+                ("ms_sample_gather", C.c_double), ("ms_select", C.c_double)]
 
 
 class _ImmPlan(C.Structure):

@@ -30,6 +30,32 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
                  int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
                  im_sample_stats* stats, bool sort_all, hipStream_t s);
 
+// Where phase 1 of a sampling call left its sets (the stream's staging arena
+// and per-position metadata), and the call's exact counters.
+struct ArenaRun {
+  uint64_t cnt = 0;
+  const int32_t* arena = nullptr;
+  const int64_t* start = nullptr;
+  const int32_t* lens = nullptr;
+  bool sort = false;
+  int32_t passes = 0;  // main launches run (more than 1: the arena was short)
+  int64_t total = 0, examined = 0, live = 0;
+  int64_t large_sets = 0, large_total = 0, large_examined = 0, large_live = 0;
+  int64_t redo_examined = 0;
+  double ms_main = 0.0, ms_large = 0.0;  // only when timed
+};
+
+// Phase 1: samples every task into the stream's arena and writes the
+// canonical offsets (off, count_total + 1 entries).  expect: a guess of the
+// member total used to size the arena (0: none).  Synchronises s.
+int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
+                    int64_t* off, int64_t expect, bool sort_all, bool timed, ArenaRun* R,
+                    hipStream_t s);
+// Phase 2: copies the sets into mem (R.total entries at off).  The stream's
+// arena must be untouched since phase 1.  ms (optional) gets the device time
+// and then the call waits for the copy.
+int gather_arena(const ArenaRun& R, const int64_t* off, int32_t* mem, double* ms, hipStream_t s);
+
 int graph_ok(const im_graph* g);
 TaskDesc task_of(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t first,
                  int64_t count, int64_t sample_base);

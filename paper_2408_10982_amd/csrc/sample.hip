@@ -1514,21 +1514,23 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
 }
 
 // ------------------------------------------------------------------ host
-// Samples every task of a table into one canonical CSR over output positions
-// (task t's sets at [sample_base, sample_base + count)).  IC tasks share one
-// main launch, LT tasks another; both hand oversized sets to one large-path
-// launch.  sort_all: sort every set on the gather (needed when IC and LT
-// tasks share the output); otherwise only LT sets are sorted there.
-int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
-                 int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
-                 im_sample_stats* stats, bool sort_all, hipStream_t s) {
+// Phase 1 of sampling every task of a table into one canonical CSR over output
+// positions (task t's sets at [sample_base, sample_base + count)).  IC tasks
+// share one main launch, LT tasks another; both hand oversized sets to one
+// large-path launch.  The sets land in the stream's staging arena; the
+// exclusive scan of their sizes is written to off.  R records where they are
+// for gather_arena.  sort_all: sort every set on the gather (needed when IC
+// and LT tasks share the output); otherwise only LT sets are sorted there.
+// expect: a guess of the member total (0: none), used to size the arena.
+int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
+                    int64_t* off, int64_t expect, bool sort_all, bool timed, ArenaRun* R,
+                    hipStream_t s) {
+  *R = ArenaRun{};
   DeviceInfo di;
   IM_TRY(device_info(&di));
   if (count_total == 0) {
     IM_HIP(hipMemsetAsync(off, 0, sizeof(int64_t), s));
     IM_HIP(hipStreamSynchronize(s));
-    *total = 0;
-    if (stats) *stats = im_sample_stats{};
     return IM_OK;
   }
   if (count_total >= ((int64_t)1 << 32)) return IM_EINVAL;
@@ -1581,15 +1583,17 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
   Handoff* handoff = (Handoff*)(((uintptr_t)(big_list + cnt) + 63) & ~(uintptr_t)63);
 
   static thread_local int64_t last_total = 0;
-  // room for the sets plus the unfilled tails of the per-wave arena chunks
+  // room for the sets plus the unfilled tails of the per-wave arena chunks;
+  // with no better guess, 64 members per set (one pass is worth more than
+  // the memory: an arena that turns out short means sampling again)
   const uint64_t slack = (uint64_t)di.num_cus * 32 * 4 * kChunk;
+  const int64_t guess = expect > 0 ? expect + expect / 8
+                                   : std::min<int64_t>(count_total * 64, (int64_t)1 << 30);
   uint64_t arena_cap =
-      (uint64_t)std::max<int64_t>(std::max<int64_t>(capacity, last_total), count_total * 2) +
-      slack;
+      (uint64_t)std::max<int64_t>(std::max<int64_t>(guess, last_total), count_total * 2) + slack;
   unsigned long long hc[16] = {0};
   // device times of the launches, only when statistics are requested
-  hipEvent_t ev[6] = {};
-  const bool timed = stats != nullptr;
+  hipEvent_t ev[4] = {};
   if (timed)
     for (auto& e : ev) IM_HIP(hipEventCreate(&e));
   struct EvGuard {
@@ -1597,12 +1601,12 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
     bool on;
     ~EvGuard() {
       if (on)
-        for (int j = 0; j < 6; ++j) (void)hipEventDestroy(e[j]);
+        for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[j]);
     }
   } ev_guard{ev, timed};
-  float ms_main = 0.f, ms_large = 0.f, ms_canon = 0.f;
+  float ms_main = 0.f, ms_large = 0.f;
+  void* ap = nullptr;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    void* ap = nullptr;
     IM_TRY(scratch(s, kSlotSampleArena, arena_cap * sizeof(int32_t), &ap));
     SampleArgs A{};
     A.tasks = d_tasks;
@@ -1701,6 +1705,7 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
       IM_HIP(hipStreamSynchronize(s));
       if (timed) IM_HIP(hipEventElapsedTime(&ms_large, ev[2], ev[3]));
     }
+    R->passes = attempt + 1;
     if (hc[1] <= arena_cap) break;
     if (attempt == 2) {
       set_error_text("im_sample_rrr: arena still short after 3 passes (needed " +
@@ -1711,39 +1716,92 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
     arena_cap = hc[1] + hc[1] / 8 + slack;
   }
   const int64_t tot = (int64_t)hc[10];
-  last_total = tot;
-  if (timed) IM_HIP(hipEventRecord(ev[4], s));
+  last_total = std::max<int64_t>(tot, 0);
   IM_TRY(exclusive_scan_i32_to_i64(lens, (int64_t)cnt, off, s));
-  *total = tot;
-  auto fill_stats = [&]() {
-    if (!stats) return;
-    stats->total = tot;
-    stats->examined = (int64_t)(hc[3] + hc[6]);
-    stats->live = (int64_t)(hc[4] + hc[7]);
-    stats->large_sets = (int64_t)hc[2];
-    stats->large_total = (int64_t)hc[8];
-    stats->large_examined = (int64_t)hc[6];
-    stats->large_live = (int64_t)hc[7];
-    stats->redo_examined = (int64_t)hc[9];
-    stats->ms_main = ms_main;
-    stats->ms_large = ms_large;
-    stats->ms_canon = ms_canon;
-  };
-  if (tot > capacity) {
+  R->cnt = cnt;
+  R->arena = (const int32_t*)ap;
+  R->start = start;
+  R->lens = lens;
+  R->sort = sort_all || any_lt;
+  R->total = tot;
+  R->examined = (int64_t)(hc[3] + hc[6]);
+  R->live = (int64_t)(hc[4] + hc[7]);
+  R->large_sets = (int64_t)hc[2];
+  R->large_total = (int64_t)hc[8];
+  R->large_examined = (int64_t)hc[6];
+  R->large_live = (int64_t)hc[7];
+  R->redo_examined = (int64_t)hc[9];
+  R->ms_main = ms_main;
+  R->ms_large = ms_large;
+  return IM_OK;
+}
+
+// Phase 2: copies every set of R from the arena to mem at the offsets written
+// by phase 1 (sorting the sets that need it).  The arena must be untouched
+// since phase 1 (same stream, no other sampling in between).
+int gather_arena(const ArenaRun& R, const int64_t* off, int32_t* mem, double* ms, hipStream_t s) {
+  if (ms) *ms = 0.0;
+  if (R.cnt == 0) return IM_OK;
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  hipEvent_t ev[2] = {};
+  const bool timed = ms != nullptr;
+  if (timed)
+    for (auto& e : ev) IM_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    bool on;
+    ~EvGuard() {
+      if (on)
+        for (int j = 0; j < 2; ++j) (void)hipEventDestroy(e[j]);
+    }
+  } ev_guard{ev, timed};
+  if (timed) IM_HIP(hipEventRecord(ev[0], s));
+  const int gblocks = (int)std::min<int64_t>(((int64_t)R.cnt + 3) / 4, (int64_t)di.num_cus * 16);
+  k_gather<<<dim3(std::max(gblocks, 1)), dim3(kGatherBlock), 0, s>>>(
+      (uint32_t)R.cnt, R.start, R.lens, off, R.arena, mem, R.sort ? 1 : 0);
+  IM_HIP(hipGetLastError());
+  if (timed) {
+    IM_HIP(hipEventRecord(ev[1], s));
+    IM_HIP(hipEventSynchronize(ev[1]));
+    float t = 0.f;
+    IM_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+    *ms = t;
+  }
+  return IM_OK;
+}
+
+static void fill_stats(const ArenaRun& R, double ms_canon, im_sample_stats* stats) {
+  if (!stats) return;
+  stats->total = R.total;
+  stats->examined = R.examined;
+  stats->live = R.live;
+  stats->large_sets = R.large_sets;
+  stats->large_total = R.large_total;
+  stats->large_examined = R.large_examined;
+  stats->large_live = R.large_live;
+  stats->redo_examined = R.redo_examined;
+  stats->ms_main = R.ms_main;
+  stats->ms_large = R.ms_large;
+  stats->ms_canon = ms_canon;
+}
+
+int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
+                 int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
+                 im_sample_stats* stats, bool sort_all, hipStream_t s) {
+  ArenaRun R;
+  IM_TRY(sample_to_arena(h_tasks, ntasks, count_total, max_n, off, capacity, sort_all,
+                         stats != nullptr, &R, s));
+  *total = R.total;
+  if (R.total > capacity) {
     IM_HIP(hipStreamSynchronize(s));
-    fill_stats();
+    fill_stats(R, 0.0, stats);
     return IM_ERANGE;
   }
-  void* ap = nullptr;
-  IM_TRY(scratch(s, kSlotSampleArena, arena_cap * sizeof(int32_t), &ap));
-  const int gblocks = (int)std::min<int64_t>(((int64_t)cnt + 3) / 4, (int64_t)di.num_cus * 16);
-  k_gather<<<dim3(std::max(gblocks, 1)), dim3(kGatherBlock), 0, s>>>(
-      (uint32_t)cnt, start, lens, off, (const int32_t*)ap, mem, (sort_all || any_lt) ? 1 : 0);
-  IM_HIP(hipGetLastError());
-  if (timed) IM_HIP(hipEventRecord(ev[5], s));
+  double ms_canon = 0.0;
+  IM_TRY(gather_arena(R, off, mem, stats ? &ms_canon : nullptr, s));
   IM_HIP(hipStreamSynchronize(s));
-  if (timed) IM_HIP(hipEventElapsedTime(&ms_canon, ev[4], ev[5]));
-  fill_stats();
+  fill_stats(R, ms_canon, stats);
   return IM_OK;
 }
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "common.h"
+#include "sample.h"
 
 namespace im {
 
@@ -48,8 +49,19 @@ static int grow(void** p, size_t old_bytes, size_t new_bytes, hipStream_t s) {
   return IM_OK;
 }
 
+// Device times and exact counters of the sampling and selection calls of
+// one im_solve.
+struct SolveTally {
+  int32_t launches = 0, passes = 0;
+  int64_t sets = 0, total = 0, examined = 0, live = 0;
+  double ms_main = 0.0, ms_large = 0.0, ms_gather = 0.0, ms_select = 0.0;
+};
+
+// Extends the pool to sets [0, want).  The new sets are sampled once into
+// the staging arena; if the pool's member buffer is too small it grows and
+// the sets are then copied in (sampling is never repeated for capacity).
 static int pool_extend(Pool& P, const im_graph* g, uint64_t seed, uint32_t tag, int64_t want,
-                       hipStream_t s) {
+                       double mean_hint, SolveTally* tally, hipStream_t s) {
   if (want <= P.count) return IM_OK;
   if (want + 1 > P.cap_sets) {
     int64_t nc = std::max<int64_t>(want + 1, P.cap_sets * 2);
@@ -58,32 +70,36 @@ static int pool_extend(Pool& P, const im_graph* g, uint64_t seed, uint32_t tag, 
   }
   if (P.count == 0) IM_HIP(hipMemsetAsync(P.off, 0, 8, s));
   const int64_t add = want - P.count;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    if (P.cap_mem - P.total < add * 4) {
-      int64_t nc = std::max<int64_t>(P.total + add * 8, P.cap_mem * 2);
-      IM_TRY(grow((void**)&P.mem, (size_t)P.total * 4, (size_t)nc * 4, s));
-      P.cap_mem = nc;
-    }
-    int64_t tot = 0;
-    int st = im_sample_rrr(g, seed, tag, P.count, add, P.off + P.count, P.mem + P.total,
-                           P.cap_mem - P.total, &tot, nullptr, s);
-    if (st == IM_ERANGE) {
-      int64_t nc = std::max<int64_t>(P.total + tot + tot / 4, P.cap_mem * 2);
-      IM_TRY(grow((void**)&P.mem, (size_t)P.total * 4, (size_t)nc * 4, s));
-      P.cap_mem = nc;
-      continue;
-    }
-    IM_TRY(st);
-    if (P.total > 0) {
-      k_add_base<<<dim3((unsigned)((add + 1 + 255) / 256)), dim3(256), 0, s>>>(P.off + P.count,
-                                                                             add + 1, P.total);
-      IM_HIP(hipGetLastError());
-    }
-    P.total += tot;
-    P.count = want;
-    return IM_OK;
+  const TaskDesc T = task_of(g, seed, tag, P.count, add, 0);
+  ArenaRun R;
+  const int64_t expect = mean_hint > 0.0 ? (int64_t)(mean_hint * (double)add) : 0;
+  IM_TRY(sample_to_arena(&T, 1, add, g->n, P.off + P.count, expect, false, true, &R, s));
+  if (P.cap_mem - P.total < R.total) {
+    const int64_t nc = std::max<int64_t>(P.total + R.total + R.total / 4, P.cap_mem * 2);
+    IM_TRY(grow((void**)&P.mem, (size_t)P.total * 4, (size_t)std::max<int64_t>(nc, 1) * 4, s));
+    P.cap_mem = nc;
   }
-  return IM_ENOMEM;
+  double ms_g = 0.0;
+  IM_TRY(gather_arena(R, P.off + P.count, P.mem + P.total, &ms_g, s));
+  if (P.total > 0) {
+    k_add_base<<<dim3((unsigned)((add + 1 + 255) / 256)), dim3(256), 0, s>>>(P.off + P.count,
+                                                                           add + 1, P.total);
+    IM_HIP(hipGetLastError());
+  }
+  P.total += R.total;
+  P.count = want;
+  if (tally) {
+    tally->launches += 1;
+    tally->passes += R.passes;
+    tally->sets += add;
+    tally->total += R.total;
+    tally->examined += R.examined;
+    tally->live += R.live;
+    tally->ms_main += R.ms_main;
+    tally->ms_large += R.ms_large;
+    tally->ms_gather += ms_g;
+  }
+  return IM_OK;
 }
 
 struct Selection {
@@ -92,11 +108,21 @@ struct Selection {
   int64_t coverage = 0;
   int32_t bucket = -1;
   int32_t global_won = -1;
+  int32_t stream_len = 0;
 };
 
 static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o,
-                     Selection* out, hipStream_t s) {
+                     Selection* out, SolveTally* tally, hipStream_t s) {
   void *pio = nullptr, *pim = nullptr, *pout = nullptr;
+  hipEvent_t ev[2];
+  for (auto& e : ev) IM_HIP(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int j = 0; j < 2; ++j) (void)hipEventDestroy(e[j]);
+    }
+  } ev_guard{ev};
+  IM_HIP(hipEventRecord(ev[0], s));
   IM_TRY(scratch(s, kSlotSolveIncOff, (size_t)(n + 1) * 8, &pio));
   IM_TRY(scratch(s, kSlotSolveInc, (size_t)std::max<int64_t>(P.total, 1) * 4, &pim));
   int64_t* inc_off = (int64_t*)pio;
@@ -129,6 +155,7 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
     IM_TRY(im_stream_cover(n, P.count, inc_off, inc_mem, k, m, lseeds, lcount, lcover, o->delta,
                            o->alpha, d_seeds, d_nsel, d_cov, d_info, s));
   }
+  IM_HIP(hipEventRecord(ev[1], s));
   int32_t h_nsel = 0, h_info[4] = {-1, 0, -1, 0};
   int64_t h_cov = 0;
   IM_HIP(hipMemcpyAsync(out->seeds.data(), d_seeds, (size_t)k * 4, hipMemcpyDeviceToHost, s));
@@ -137,11 +164,15 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
   if (o->selector != IM_SEL_GREEDY)
     IM_HIP(hipMemcpyAsync(h_info, d_info, 16, hipMemcpyDeviceToHost, s));
   IM_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  IM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+  if (tally) tally->ms_select += ms;
   out->nsel = h_nsel;
   out->coverage = h_cov;
   if (o->selector != IM_SEL_GREEDY) {
     out->bucket = h_info[0];
     out->global_won = h_info[2];
+    out->stream_len = h_info[3];
   }
   return IM_OK;
 }
@@ -202,6 +233,8 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   double lb = 1.0;
   int64_t theta;
   Selection sel;
+  SolveTally tally;
+  double mean = 0.0;  // mean set size seen so far (sizes the next arena)
   if (o->theta > 0) {
     theta = o->theta;
   } else {
@@ -210,8 +243,9 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
     for (int32_t i = 1; i <= rounds; ++i) {
       if (i > 1) th *= 2;
       if (th >= ((int64_t)1 << 31)) return IM_ERANGE;
-      IM_TRY(pool_extend(P, g, o->seed, 0u, th, s));
-      IM_TRY(select_on(P, n, k, o, &sel, s));
+      IM_TRY(pool_extend(P, g, o->seed, 0u, th, mean, &tally, s));
+      mean = (double)P.total / (double)P.count;
+      IM_TRY(select_on(P, n, k, o, &sel, &tally, s));
       res->rounds = i;
       const double x = nd / ldexp(1.0, i);
       if (nd * (double)sel.coverage / (double)th >= (1.0 + eps_p) * x) {
@@ -224,8 +258,8 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   }
   if (theta >= ((int64_t)1 << 31)) return IM_ERANGE;
   Pool F;
-  IM_TRY(pool_extend(F, g, o->seed, 1u, theta, s));
-  IM_TRY(select_on(F, n, k, o, &sel, s));
+  IM_TRY(pool_extend(F, g, o->seed, 1u, theta, mean, &tally, s));
+  IM_TRY(select_on(F, n, k, o, &sel, &tally, s));
   for (int32_t j = 0; j < k; ++j) seeds[j] = sel.seeds[j];
   res->nsel = sel.nsel;
   res->coverage = sel.coverage;
@@ -233,6 +267,17 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   res->lower_bound = lb;
   res->bucket = sel.bucket;
   res->global_won = sel.global_won;
+  res->stream_len = sel.stream_len;
   res->final_total = F.total;
+  res->sample_launches = tally.launches;
+  res->sample_passes = tally.passes;
+  res->sampled_sets = tally.sets;
+  res->sampled_total = tally.total;
+  res->sampled_examined = tally.examined;
+  res->sampled_live = tally.live;
+  res->ms_sample_main = tally.ms_main;
+  res->ms_sample_large = tally.ms_large;
+  res->ms_sample_gather = tally.ms_gather;
+  res->ms_select = tally.ms_select;
   return IM_OK;
 }

@@ -25,6 +25,7 @@ constexpr int kMaxBuckets = 64;
 struct StreamArgs {
   int64_t count;
   int32_t k, m, T, B;
+  int32_t empty;  // every streamed S(x) is empty (l = 0): no bucket takes anything
   const int64_t* __restrict__ inc_off;
   const int32_t* __restrict__ inc_mem;
   const int32_t* __restrict__ lseeds;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(kSBlock) void k_stream(StreamArgs A) {
     gain[tid] = 0;
     s_thr[tid] = tid < A.B ? A.thr[tid] : 0;
   }
-  if (tid == 0) s_live = A.B > 0;
+  if (tid == 0) s_live = A.B > 0 && !A.empty;
   const uint64_t all = A.B >= 64 ? ~0ull : ((1ull << A.B) - 1ull);
   __syncthreads();
   int32_t slen = 0;
@@ -225,6 +226,7 @@ extern "C" int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off,
   A.m = m;
   A.T = T;
   A.B = B;
+  A.empty = hl[0] == 0 ? 1 : 0;
   A.inc_off = inc_off;
   A.inc_mem = inc_mem;
   A.lseeds = lseeds;

@@ -69,14 +69,19 @@ def test_config2_sampling_and_greedy(im):
     assert np.all(np.diff(gl) <= 0) and gl.sum() == int(cov.item())
 
 
+@pytest.fixture(scope="module")
+def c3(im):
+    w = W.config(3)
+    g = w.graph
+    return w, im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
+
+
 @pytest.mark.parametrize("alpha", [1.0, 0.125])
-def test_config3_imm_greediris(im, alpha):
+def test_config3_imm_greediris(im, c3, alpha):
     print("[case] config 3 full size alpha=%s" % alpha, flush=True)
     exp = _golden(3)
     run = exp["runs"][repr(alpha)]
-    w = W.config(3)
-    g = w.graph
-    G = im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
+    w, G = c3
     got = im.solve(G, w.k, w.eps, selector=im.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha,
                    seed=w.seed, part_seed=w.part_seed)
     assert got["theta"] == run["theta"]

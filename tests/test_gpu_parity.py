@@ -303,6 +303,56 @@ def test_stream_cover(im, name, count, k, m, delta, alpha):
     assert int(_np(cov)[0]) == fc
 
 
+def test_stream_cover_long_stream_with_gaps(im):
+    """A stream longer than one 1024-entry lookup chunk (m * T = 1280, the
+    last chunk partial) where most partitions pick fewer than T seeds (few
+    candidates each), so the stream has holes."""
+    _say("stream long", 80, 16)
+    g = GRAPHS["ic_sparse"]()
+    count, k, m = 300, 16, 80
+    G, r, io, imem, o, oio, oim = _pipeline(im, g, count, 43)
+    part, ls, lg, lc, lv = im.randgreedi(g.n, r, io, imem, k, m, part_seed=91)
+    lc_h = _np(lc)
+    assert m * k > 1024 and lc_h.min() < k  # shape of the case itself
+    seeds, nsel, cov, info = im.stream_cover(g.n, count, io, imem, ls, lc, lv, k, 0.077, 1.0)
+    opart = O.partition(g.n, m, 91)
+    ols, olg, olc, olv = O.local_greedy(g.n, count, oio, oim, opart, m, k)
+    assert np.array_equal(lc_h, olc)
+    gs, gc, gb, gnb = O.stream_cover(g.n, count, oio, oim, ols, olg, olc, k, 0.077, 1.0)
+    fs, fc, won = O.final_select(ols, olc, olv, gs, gc)
+    ns = int(_np(nsel)[0])
+    inf = _np(info)
+    assert (inf[0], inf[1], inf[2], inf[3]) == (gb, gnb, int(won), int(olc.sum()))
+    assert ns == len(fs) and np.array_equal(_np(seeds)[:ns], fs)
+    assert int(_np(cov)[0]) == fc
+
+
+def test_stream_cover_all_streamed_sets_empty(im):
+    """Every streamed S(x) empty (l = 0): no bucket takes a seed, the result
+    is empty with coverage 0, as in the oracle."""
+    _say("stream empty")
+    n, count, k, m = 12, 5, 3, 2
+    inc_off = np.zeros(n + 1, np.int64)
+    inc_mem = np.zeros(0, np.int32)
+    ls = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    lc = np.array([3, 2], np.int32)
+    lg = np.zeros((m, k), np.int64)
+    lv = np.zeros(m, np.int64)
+    dev = "cuda"
+    seeds, nsel, cov, info = im.stream_cover(
+        n, count, torch.from_numpy(inc_off).to(dev), torch.zeros(1, dtype=torch.int32,
+                                                                device=dev),
+        torch.from_numpy(ls).to(dev), torch.from_numpy(lc).to(dev),
+        torch.from_numpy(lv).to(dev), k, 0.077, 1.0)
+    gs, gc, gb, gnb = O.stream_cover(n, count, inc_off, inc_mem, ls, lg, lc, k, 0.077, 1.0)
+    fs, fc, won = O.final_select(ls, lc, lv, gs, gc)
+    assert len(fs) == 0 and fc == 0
+    assert int(_np(nsel)[0]) == 0 and int(_np(cov)[0]) == 0
+    assert np.all(_np(seeds) == -1)
+    inf = _np(info)
+    assert (inf[0], inf[1], inf[2], inf[3]) == (gb, gnb, int(won), 5)
+
+
 @pytest.mark.parametrize("name,k,eps,selector", [
     ("ic_sparse", 5, 0.5, O.SEL_GREEDY), ("lt_small", 8, 0.4, O.SEL_GREEDIRIS),
     ("rmat12", 16, 0.5, O.SEL_GREEDY), ("rmat12", 16, 0.5, O.SEL_GREEDIRIS)])
