@@ -217,6 +217,25 @@ int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, const int32_t*
                     void* stream);
 
 /*
+ * im_greedy_cover without any device allocation, for callers that cannot
+ * allocate device memory: code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, operation and outputs as
+ * im_greedy_cover (bit-identical results).  Its scratch -- 64 + 8*round_up(k,8)
+ * + 4n + count bytes: argmax keys, per-vertex counts, covered flags -- lives
+ * in a fixed 64 MiB device array that each GPU the library runs on holds
+ * until the process ends; a call needing more returns IM_ENOMEM (the sizes
+ * are in im_last_error()) before any device work.  The array is looked up
+ * once per device (hipGetSymbolAddress) on the first call there.  Every call
+ * on one GPU shares that GPU's array and reinitialises it on `stream`, so
+ * calls that overlap on one GPU (different streams, or concurrent host
+ * threads) race and must not be issued.  Asynchronous; no memset nodes.
+ */
+int im_greedy_cover_static(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
+                           int64_t total, const int64_t* inc_off, const int32_t* inc_mem,
+                           int32_t k, int32_t* seeds, int64_t* gains, int32_t* nsel,
+                           int64_t* coverage, void* stream);
+
+/*
  * RandGreedi local step (Alg. 3 partition step; Alg. 4, local greedy step; Sec. 3.4 S3).
  * Partitions V uniformly at random into m parts, part(v) = floor(draw(part,
  * v) * m / 2^32) with key part_seed, and runs the standard greedy above on

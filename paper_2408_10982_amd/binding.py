@@ -26,7 +26,7 @@ _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM
 
 # every symbol the header declares
 EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
-           "im_build_incidence", "im_greedy_cover", "im_randgreedi", "im_stream_cover",
+           "im_build_incidence", "im_greedy_cover", "im_greedy_cover_static", "im_randgreedi", "im_stream_cover",
            "im_solve", "im_solve_batch", "im_imm_plan", "im_tune_set", "im_tune_get")
 
 
@@ -107,6 +107,7 @@ def lib():
                                     C.POINTER(C.c_int64), C.POINTER(_Stats), P]
         L.im_build_incidence.argtypes = [I32, I64, P, P, I64, P, P, P]
         L.im_greedy_cover.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
+        L.im_greedy_cover_static.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
         L.im_randgreedi.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, U64, P, P, P, P, P, P]
         L.im_stream_cover.argtypes = [I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P, P]
         L.im_solve.argtypes = [C.POINTER(_Graph), I32, D, C.POINTER(_SolveOpts), P,
@@ -240,6 +241,21 @@ def greedy_cover(n: int, rrr: RRR, inc_off, inc_mem, k: int, stream=None):
                                _ptr(inc_off), _ptr(inc_mem), k, _ptr(seeds), _ptr(gains),
                                _ptr(nsel), _ptr(cov), _stream(stream))
     _check(st, "im_greedy_cover")
+    return seeds, gains, nsel, cov
+
+
+def greedy_cover_static(n: int, rrr: RRR, inc_off, inc_mem, k: int, stream=None):
+    """im_greedy_cover_static: the same greedy with the library's fixed scratch
+    (no device allocation).  Returns (seeds, gains, nsel, coverage) device tensors."""
+    dev = rrr.off.device
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    gains = torch.empty(k, dtype=torch.int64, device=dev)
+    nsel = torch.empty(1, dtype=torch.int32, device=dev)
+    cov = torch.empty(1, dtype=torch.int64, device=dev)
+    st = lib().im_greedy_cover_static(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
+                                      _ptr(inc_off), _ptr(inc_mem), k, _ptr(seeds), _ptr(gains),
+                                      _ptr(nsel), _ptr(cov), _stream(stream))
+    _check(st, "im_greedy_cover_static")
     return seeds, gains, nsel, cov
 
 

@@ -17,6 +17,8 @@
 // over the full universe of samples, and a covered sample only decrements the
 // members of the partition that covered it (Alg. 4, local greedy step; Sec. 3.4 S3).
 #include <algorithm>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -703,4 +705,93 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   // the host copy of hb must outlive the async copy
   IM_HIP(hipStreamSynchronize(s));
   return IM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// The same standard greedy with its scratch in a fixed device array, for
+// callers that cannot allocate device memory (code under stream capture,
+// tight serving loops).  Every device holds its own copy of the array for the
+// life of the process; its device address is looked up once per device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// file scope, outside namespace im (whose scratch() is the per-stream buffer)
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace im {
+
+constexpr int kMaxStaticDevices = 64;
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxStaticDevices] = {};
+
+static int static_scratch(void** out) {
+  int dev = 0;
+  IM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxStaticDevices) {
+    set_error_text("im_greedy_cover_static: device ordinal " + std::to_string(dev) +
+                   " beyond the table of " + std::to_string(kMaxStaticDevices));
+    return IM_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    // the array's name is a host-side stand-in; kernels get this address
+    IM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(::scratch)));
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return IM_OK;
+}
+
+__global__ void k_fill_i64(int64_t* __restrict__ x, int64_t n, int64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+}  // namespace im
+
+extern "C" int im_greedy_cover_static(int32_t n, int64_t count, const int64_t* off,
+                                      const int32_t* mem, int64_t total, const int64_t* inc_off,
+                                      const int32_t* inc_mem, int32_t k, int32_t* seeds,
+                                      int64_t* gains, int32_t* nsel, int64_t* coverage,
+                                      void* stream) {
+  if (n <= 0 || count < 0 || count >= ((int64_t)1 << 31) || total < 0 || k <= 0 || !off ||
+      !inc_off || !seeds || !gains || !nsel || !coverage || (total > 0 && (!mem || !inc_mem)))
+    return IM_EINVAL;
+  // same layout as im_greedy_cover: done | gmax (k) | cnt (n) | covered (count)
+  const size_t gbytes = ((size_t)k * 8 + 63) / 64 * 64;
+  const size_t bytes = 64 + gbytes + (size_t)n * 4 + (size_t)count;
+  if (bytes > kStaticScratchBytes) {
+    set_error_text("im_greedy_cover_static: n = " + std::to_string(n) + ", count = " +
+                   std::to_string(count) + ", k = " + std::to_string(k) + " need " +
+                   std::to_string(bytes) + " bytes of scratch; the fixed buffer holds " +
+                   std::to_string(kStaticScratchBytes));
+    return IM_ENOMEM;
+  }
+  void* p = nullptr;
+  IM_TRY(static_scratch(&p));
+  hipStream_t s = (hipStream_t)stream;
+  char* c = (char*)p;
+  CoverArgs A{};
+  A.n = n;
+  A.m = 1;
+  A.count = count;
+  A.k = k;
+  A.off = off;
+  A.mem = mem;
+  A.inc_off = inc_off;
+  A.inc_mem = inc_mem;
+  A.done = (int32_t*)c;
+  c += 64;
+  A.gmax = (unsigned long long*)c;
+  c += gbytes;
+  A.cnt = (uint32_t*)c;
+  c += (size_t)n * 4;
+  A.covered = (uint8_t*)c;
+  A.seeds = seeds;
+  A.gains = gains;
+  A.nsel = nsel;
+  A.cover = coverage;
+  // gains start at zero (a fill kernel: no memset node if the caller captures)
+  k_fill_i64<<<dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s>>>(gains, k, 0);
+  IM_HIP(hipGetLastError());
+  return launch_cover(A, s);
 }
