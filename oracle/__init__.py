@@ -21,7 +21,7 @@ _HDR = os.path.join(_HERE, "im_oracle.h")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 IC, LT = 0, 1
-SEL_GREEDY, SEL_GREEDIRIS = 0, 1
+SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
 TAG_ROOT, TAG_EDGE, TAG_VERT, TAG_PART = 0, 1, 2, 3
 
 
@@ -65,7 +65,7 @@ class _ImmResult(C.Structure):
     _fields_ = [("nsel", C.c_int32), ("coverage", C.c_int64), ("theta", C.c_int64),
                 ("rounds_run", C.c_int32), ("lb", C.c_double),
                 ("martingale_samples", C.c_int64), ("bucket", C.c_int32),
-                ("global_won", C.c_int)]
+                ("global_won", C.c_int), ("stream_len", C.c_int32)]
 
 
 def lib():
@@ -88,6 +88,12 @@ def lib():
         L.or_log.argtypes = [C.c_double]
         L.or_log.restype = C.c_double
         L.or_ic_skip_table.argtypes = [C.c_int32, P, P, P]
+        L.or_rl_factor.argtypes = [C.c_uint32]
+        L.or_rl_factor.restype = C.c_double
+        L.or_rl_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.or_rl_uniform.restype = C.c_double
+        L.or_rl_gap.argtypes = [C.c_double, C.c_double]
+        L.or_rl_gap.restype = C.c_int64
         L.or_rrr_free.argtypes = [C.POINTER(_Rrr)]
         L.or_incidence.argtypes = [C.c_int32, C.c_int64, P, P, P, P]
         L.or_coverage.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, P]
@@ -104,6 +110,8 @@ def lib():
         L.or_bucket_thresholds.argtypes = [C.c_int64, C.c_int32, C.c_double, C.c_int32, P]
         L.or_stream_cover.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, C.c_int32, P, P,
                                       P, C.c_double, C.c_double, P, P, P, P, P]
+        L.or_greedi_offline.argtypes = [C.c_int32, C.c_int64, P, P, C.c_int32, C.c_int32, P, P,
+                                        C.c_double, C.c_int, P, P, P, P]
         L.or_final_select.argtypes = [C.c_int32, C.c_int32, P, P, P, P, C.c_int32,
                                       C.c_int64, P, P, P]
         L.or_imm_parameters.argtypes = [C.c_int32, C.c_int32, C.c_double,
@@ -174,6 +182,21 @@ def ic_skip_table(in_off, thr) -> np.ndarray:
     out = np.zeros(n, np.float64)
     lib().or_ic_skip_table(n, _p(in_off), _p(thr), _p(out))
     return out
+
+
+def rl_factor(q: int) -> float:
+    """1 / ln(1 - q/2^32): the run-length table entry of threshold q."""
+    return float(lib().or_rl_factor(int(q)))
+
+
+def rl_uniform(seed: int, stream: int, i: int, v: int, j: int) -> float:
+    """U on (0, 1] of draw pair j of (sample i, vertex v)."""
+    return float(lib().or_rl_uniform(seed, stream, i, v, j))
+
+
+def rl_gap(u: float, factor: float) -> int:
+    """floor(ln U * factor): dead in-edges before the next live one."""
+    return int(lib().or_rl_gap(float(u), float(factor)))
 
 
 def _skip_arg(model, in_off, thr, skip):
@@ -311,6 +334,23 @@ def stream_cover(n: int, count: int, inc_off, inc_mem, lseeds, lgains, lcount, k
                           delta, alpha, _p(seeds), C.byref(nsel), C.byref(cov), C.byref(b),
                           C.byref(nb))
     return seeds[:nsel.value].copy(), int(cov.value), int(b.value), int(nb.value)
+
+
+def greedi_offline(n: int, count: int, inc_off, inc_mem, lseeds, lcount, k: int,
+                   alpha: float = 1.0, lazy: bool = True):
+    """Alg. 4 global step (offline): returns (seeds int32[gsel], gains, C(S_g))."""
+    inc_off = _c(inc_off, np.int64)
+    inc_mem = _c(inc_mem, np.int32)
+    ls = _c(lseeds, np.int32)
+    lc = _c(lcount, np.int32)
+    m = lc.shape[0]
+    gs = np.zeros(k, np.int32)
+    gg = np.zeros(k, np.int64)
+    gsel = C.c_int32()
+    gcov = C.c_int64()
+    lib().or_greedi_offline(n, count, _p(inc_off), _p(inc_mem), m, k, _p(ls), _p(lc), alpha,
+                            int(lazy), _p(gs), _p(gg), C.byref(gsel), C.byref(gcov))
+    return gs[:gsel.value].copy(), gg[:gsel.value].copy(), int(gcov.value)
 
 
 def final_select(lseeds, lcount, lcover, gseeds, gcover: int):

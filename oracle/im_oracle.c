@@ -140,13 +140,21 @@ void or_ic_skip_table(int32_t n, const int32_t* in_off, const uint32_t* thr, dou
         break;
       }
     if (!same) continue;
-    double keep = (4294967296.0 - (double)q) * 2.3283064365386963e-10; /* (2^32 - q) 2^-32 */
-    skip[v] = 1.0 / or_log(keep);
+    skip[v] = or_rl_factor(q);
   }
 }
 
-/* Uniform on (0, 1] from 53 bits of draw pair j of (sample i, vertex v). */
-static double skip_uniform(uint64_t seed, uint32_t stream, uint32_t i, uint32_t v, uint32_t j) {
+double or_rl_factor(uint32_t q) {
+  double keep = (4294967296.0 - (double)q) * 2.3283064365386963e-10; /* (2^32 - q) 2^-32 */
+  return 1.0 / or_log(keep);
+}
+
+int64_t or_rl_gap(double u, double factor) {
+  /* in-edges skipped before the next live one: floor(ln U / ln(1 - p)) */
+  return (int64_t)floor(or_log(u) * factor);
+}
+
+double or_rl_uniform(uint64_t seed, uint32_t stream, uint32_t i, uint32_t v, uint32_t j) {
   uint32_t ctr[4] = {v, i, 0x80000000u | (j >> 1), stream};
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   uint32_t out[4];
@@ -214,9 +222,9 @@ static int32_t sample_ic_one(int32_t n, const int32_t* in_off, const int32_t* in
       int64_t pos = -1;
       for (uint32_t j = 0;; ++j) {
         ++*examined;
-        double g = floor(or_log(skip_uniform(seed, stream, i, (uint32_t)v, j)) * skip[v]);
-        if (g >= (double)(deg - 1 - pos)) break; /* past the last in-edge */
-        pos += 1 + (int64_t)g;
+        int64_t g = or_rl_gap(or_rl_uniform(seed, stream, i, (uint32_t)v, j), skip[v]);
+        if (g >= deg - 1 - pos) break; /* past the last in-edge */
+        pos += 1 + g;
         ++*live;
         int32_t u = in_src[in_off[v] + pos];
         if (mark[u] != stamp) {
@@ -614,6 +622,36 @@ void or_stream_cover(int32_t n, int64_t count, const int64_t* inc_off, const int
   free(csz);
 }
 
+void or_greedi_offline(int32_t n, int64_t count, const int64_t* inc_off, const int32_t* inc_mem,
+                       int32_t m, int32_t k, const int32_t* lseeds, const int32_t* lcount,
+                       double alpha, int lazy, int32_t* gseeds, int64_t* ggains, int32_t* gsel,
+                       int64_t* gcover) {
+  (void)n;
+  int32_t T = or_trunc_len(k, alpha);
+  /* the union of the gathered local solutions, ascending ids */
+  int32_t* cand = (int32_t*)malloc(((size_t)m * (size_t)T + 1) * sizeof(int32_t));
+  int32_t nc = 0;
+  for (int32_t p = 0; p < m; ++p)
+    for (int32_t t = 0; t < T && t < lcount[p]; ++t) cand[nc++] = lseeds[(int64_t)p * k + t];
+  qsort(cand, (size_t)nc, sizeof(int32_t), cmp_i32);
+  int32_t u = 0; /* the parts are disjoint, so this only guards repeated input */
+  for (int32_t c = 0; c < nc; ++c)
+    if (u == 0 || cand[c] != cand[u - 1]) cand[u++] = cand[c];
+  uint8_t* cov = (uint8_t*)calloc((size_t)count + 1, 1);
+  int32_t t = lazy ? greedy_lazy_on(cand, u, inc_off, inc_mem, cov, k, gseeds, ggains)
+                   : greedy_plain_on(cand, u, inc_off, inc_mem, cov, k, gseeds, ggains);
+  int64_t c = 0;
+  for (int32_t j = 0; j < t; ++j) c += ggains[j];
+  for (int32_t j = t; j < k; ++j) {
+    gseeds[j] = -1;
+    ggains[j] = 0;
+  }
+  *gsel = t;
+  *gcover = c;
+  free(cov);
+  free(cand);
+}
+
 int or_final_select(int32_t m, int32_t k, const int32_t* lseeds, const int32_t* lcount,
                     const int64_t* lcover, const int32_t* gseeds, int32_t gsel, int64_t gcover,
                     int32_t* seeds, int32_t* nsel, int64_t* coverage) {
@@ -689,7 +727,8 @@ static int pool_extend(pool_t* P, int model, int32_t n, const int32_t* in_off,
 
 /* one SelectSeeds call on the pool; seeds receives up to k ids */
 static void select_on(const pool_t* P, int32_t n, const or_imm_opts* opt, int32_t* seeds,
-                      int32_t* nsel, int64_t* coverage, int32_t* bucket, int* gwon) {
+                      int32_t* nsel, int64_t* coverage, int32_t* bucket, int* gwon,
+                      int32_t* slen) {
   int32_t k = opt->k;
   int64_t* inc_off = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
   int32_t* inc_mem = (int32_t*)malloc((size_t)(P->total + 1) * sizeof(int32_t));
@@ -697,6 +736,7 @@ static void select_on(const pool_t* P, int32_t n, const or_imm_opts* opt, int32_
   int64_t* gains = (int64_t*)malloc((size_t)k * sizeof(int64_t));
   *bucket = -1;
   *gwon = -1;
+  *slen = 0;
   if (opt->selector == OR_SEL_GREEDY) {
     greedy_entry(opt->lazy, n, P->count, inc_off, inc_mem, k, seeds, gains, nsel, coverage);
   } else {
@@ -711,9 +751,18 @@ static void select_on(const pool_t* P, int32_t n, const or_imm_opts* opt, int32_
     int64_t gcov;
     or_partition(n, m, opt->part_seed, part);
     or_local_greedy(n, P->count, inc_off, inc_mem, part, m, k, opt->lazy, ls, lg, lc, lv);
-    or_stream_cover(n, P->count, inc_off, inc_mem, m, k, ls, lg, lc, opt->delta, opt->alpha,
-                    gs, &gsel, &gcov, bucket, &nb);
+    if (opt->selector == OR_SEL_RANDGREEDI) {
+      int64_t* gg = (int64_t*)malloc((size_t)k * sizeof(int64_t));
+      or_greedi_offline(n, P->count, inc_off, inc_mem, m, k, ls, lc, opt->alpha, opt->lazy, gs,
+                        gg, &gsel, &gcov);
+      free(gg);
+    } else {
+      or_stream_cover(n, P->count, inc_off, inc_mem, m, k, ls, lg, lc, opt->delta, opt->alpha,
+                      gs, &gsel, &gcov, bucket, &nb);
+    }
     *gwon = or_final_select(m, k, ls, lc, lv, gs, gsel, gcov, seeds, nsel, coverage);
+    int32_t T = or_trunc_len(k, opt->alpha); /* the stream: first T picks of each part */
+    for (int32_t p = 0; p < m; ++p) *slen += lc[p] < T ? lc[p] : T;
     free(part); free(ls); free(lg); free(lc); free(lv); free(gs);
   }
   free(gains);
@@ -728,7 +777,7 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
   or_imm_parameters(n, opt->k, opt->eps, &prm);
   double nd = (double)n;
   double lb = 1.0;
-  int32_t nsel = 0, bucket = -1;
+  int32_t nsel = 0, bucket = -1, slen = 0;
   int64_t cov = 0;
   int gwon = -1;
   int64_t theta;
@@ -741,7 +790,7 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
       if (i > 1) th *= 2;
       if (pool_extend(&P, opt->model, n, in_off, in_src, thr, skip, opt->seed, 0u, th))
         return -1;
-      select_on(&P, n, opt, seeds, &nsel, &cov, &bucket, &gwon);
+      select_on(&P, n, opt, seeds, &nsel, &cov, &bucket, &gwon, &slen);
       res->rounds_run = i;
       double x = nd / ldexp(1.0, i);
       if (nd * (double)cov / (double)th >= (1.0 + prm.eps_prime) * x) {
@@ -756,7 +805,7 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
   }
   pool_t F = {0, 0, NULL, NULL};
   if (pool_extend(&F, opt->model, n, in_off, in_src, thr, skip, opt->seed, 1u, theta)) return -1;
-  select_on(&F, n, opt, seeds, &nsel, &cov, &bucket, &gwon);
+  select_on(&F, n, opt, seeds, &nsel, &cov, &bucket, &gwon, &slen);
   free(F.off);
   free(F.mem);
   res->nsel = nsel;
@@ -765,5 +814,6 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
   res->lb = lb;
   res->bucket = bucket;
   res->global_won = gwon;
+  res->stream_len = slen;
   return 0;
 }

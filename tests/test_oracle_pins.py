@@ -647,3 +647,167 @@ def test_skip_membership_matches_exact_enumeration():
             f = hits[v, t] / cnt[t]
             sd = math.sqrt(max(mu * (1 - mu), 1e-12) / cnt[t])
             assert abs(f - mu) < 5 * sd + 1e-9, (v, t, f, mu)
+
+
+# ------------------------------------------- run-length form: exact and in law
+def _wc_thresholds():
+    """Thresholds the run-length form sees: weighted cascade p = fp32(1/d) for
+    in-degrees 2 .. 2^20, plus extremes (tiny q, q near 2^32 - 2, the largest
+    fp32 below 1)."""
+    ds = [2, 3, 4, 5, 7, 10, 16, 31, 100, 1000, 4096, 65536, 1 << 20]
+    qs = [int(x) for x in O.ic_thresholds(np.float32(1.0) / np.array(ds, np.float32))]
+    qs += [1, 2, 1000, 2 ** 31 + 1, 2 ** 32 - 2 ** 8, 2 ** 32 - 3, 2 ** 32 - 2]
+    return qs
+
+
+def test_run_length_gap_equals_exact_quotient():
+    """G = floor(ln U / ln(1 - q/2^32)) for >= 10^5 (U, q) pairs, with ln
+    evaluated in 60-digit decimal arithmetic (correctly rounded), against the
+    oracle's own gap step (the fixed fp64 log and the table factor).  Equal
+    everywhere except where the exact quotient lies within 1e-12 (relative)
+    of an integer, where either neighbour is accepted; such ties are counted."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    rng = np.random.default_rng(2024)
+    qs = _wc_thresholds()
+    N = 100000
+    bits = rng.integers(0, 2 ** 53, N, dtype=np.int64)
+    bits[:4] = [0, 1, 2 ** 53 - 1, 2 ** 52]  # U = 2^-53, 2^-52, 1, just above 1/2
+    qi = rng.integers(0, len(qs), N)
+    two53 = Decimal(2 ** 53)
+    two32 = Decimal(2 ** 32)
+    ln_keep = {q: ((two32 - Decimal(q)) / two32).ln() for q in qs}
+    factor = {q: O.rl_factor(q) for q in qs}
+    ties = 0
+    for b, j in zip(bits.tolist(), qi.tolist()):
+        q = qs[j]
+        u = (b + 1) * 2.0 ** -53  # exact in fp64
+        g = O.rl_gap(u, factor[q])
+        x = (Decimal(b + 1) / two53).ln() / ln_keep[q]
+        exact = int(x.to_integral_value(rounding="ROUND_FLOOR"))
+        if g != exact:
+            near = abs(x - x.to_integral_value()) <= Decimal("1e-12") * max(Decimal(1), abs(x))
+            assert near, (b, q, g, exact, x)
+            assert abs(g - exact) == 1
+            ties += 1
+    assert O.rl_gap(1.0, factor[qs[0]]) == 0
+    assert ties <= 5, ties
+
+
+@pytest.mark.parametrize("p", [0.5, 1.0 / 16, 1.0 / 1000])
+def test_run_length_gaps_are_geometric(p):
+    """The gaps the oracle generates from its own draws (U of draw pairs j
+    over many samples and vertices) follow Geometric(p): Pr[G = g] =
+    (1-p)^g p, by a chi-square goodness-of-fit over bins of equal mass."""
+    from scipy.stats import chisquare
+    q = int(O.ic_thresholds(np.array([p], np.float32))[0])
+    pq = q / 2 ** 32
+    f = O.rl_factor(q)
+    G = np.array([O.rl_gap(O.rl_uniform(77, 0, i, v, j), f)
+                  for i in range(50) for v in range(40) for j in range(40)], np.int64)
+    # bins of about equal probability: edges at geometric quantiles
+    nb = 40
+    edges = np.unique(np.floor(np.log1p(-np.arange(1, nb) / nb) / math.log1p(-pq)).astype(int))
+    cdf = lambda g: 1.0 - (1.0 - pq) ** (g + 1)  # noqa: E731  Pr[G <= g]
+    lo = np.concatenate([[0], edges + 1])
+    hi = np.concatenate([edges, [np.iinfo(np.int64).max]])
+    probs = np.array([cdf(h) if h < np.iinfo(np.int64).max else 1.0 for h in hi]) - \
+        np.array([cdf(l - 1) if l > 0 else 0.0 for l in lo])
+    obs = np.array([np.count_nonzero((G >= l) & (G <= h)) for l, h in zip(lo, hi)])
+    assert obs.sum() == G.size and abs(probs.sum() - 1) < 1e-12
+    assert chisquare(obs, probs * G.size).pvalue > 1e-3
+    assert abs(G.mean() - (1 - pq) / pq) < 5 * math.sqrt((1 - pq) / pq ** 2 / G.size)
+
+
+def test_run_length_and_coin_forms_agree_in_law():
+    """One weighted-cascade graph sampled 10^5 times with one coin per in-edge
+    and 10^5 times with run-length gaps (different draws, same law): the set
+    sizes and the per-vertex membership counts pass two-sample chi-square
+    tests."""
+    from scipy.stats import chi2_contingency
+    g = W.make_graph("rmat", W.IC, scale=12, num_edges=1 << 16, graph_seed=61, weight_seed=62,
+                     weights="wc")
+    thr = O.ic_thresholds(g.weight)
+    assert np.count_nonzero(O.ic_skip_table(g.in_off, thr)) > g.n // 4
+    N = 100000
+    a = O.sample(O.IC, g.in_off, g.in_src, thr, 501, 0, 0, N, skip=None)
+    b = O.sample(O.IC, g.in_off, g.in_src, thr, 502, 0, 0, N)
+    sa, sb = np.diff(a.off), np.diff(b.off)
+    top = 12
+    ha = np.bincount(np.minimum(sa, top), minlength=top + 1)[1:]
+    hb = np.bincount(np.minimum(sb, top), minlength=top + 1)[1:]
+    assert chi2_contingency(np.vstack([ha, hb]))[1] > 1e-3
+    ma = np.bincount(a.mem, minlength=g.n)
+    mb = np.bincount(b.mem, minlength=g.n)
+    keep = (ma + mb) >= 40
+    assert keep.sum() > 500
+    assert chi2_contingency(np.vstack([ma[keep], mb[keep]]))[1] > 1e-3
+
+
+# ------------------------------------------- RandGreedi's offline global step
+@pytest.mark.parametrize("seed", range(10))
+def test_offline_aggregation_against_brute_force(seed):
+    """Alg. 4 global step on tiny set systems: S_g is drawn from the union of
+    the gathered local solutions, reaches (1 - 1/e) of the best k-subset of
+    that union (brute force), has non-increasing gains summing to its
+    coverage, and replays by hand as lowest-id argmax picks over the union."""
+    rng = np.random.default_rng(700 + seed)
+    n, universe = int(rng.integers(8, 15)), int(rng.integers(10, 40))
+    k, m = int(rng.integers(1, 5)), int(rng.integers(2, 5))
+    sets, io, im = _random_set_system(rng, n, universe, 0.3)
+    part = O.partition(n, m, 900 + seed)
+    ls, lg, lc, lv = O.local_greedy(n, universe, io, im, part, m, k, lazy=False)
+    alpha = float(rng.choice([1.0, 0.5]))
+    T = O.trunc_len(k, alpha)
+    union = sorted(int(ls[p, t]) for p in range(m) for t in range(min(T, int(lc[p]))))
+    gs, gg, gc = O.greedi_offline(n, universe, io, im, ls, lc, k, alpha=alpha)
+    assert set(gs.tolist()) <= set(union)
+    best = 0
+    for r_ in range(1, min(k, len(union)) + 1):
+        for S in itertools.combinations(union, r_):
+            best = max(best, len(set().union(*[sets[v] for v in S])))
+    assert gc >= (1 - 1 / math.e) * best - 1e-9
+    assert np.all(np.diff(gg) <= 0) and gg.sum() == gc == O.coverage(n, universe, io, im, gs)
+    covered = set()
+    for s, gval in zip(gs, gg):
+        marg = [len(sets[v] - covered) for v in union]
+        assert gval == max(marg) and s == union[marg.index(max(marg))]
+        covered |= sets[s]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_offline_aggregation_lazy_equals_plain(seed):
+    g, r, io, im = _small_collection(seed=140 + seed, n=300, count=3000, p_hi=0.25)
+    part = O.partition(g.n, 8, 11 + seed)
+    ls, lg, lc, lv = O.local_greedy(g.n, r.count, io, im, part, 8, 12)
+    a = O.greedi_offline(g.n, r.count, io, im, ls, lc, 12, lazy=False)
+    b = O.greedi_offline(g.n, r.count, io, im, ls, lc, 12, lazy=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_offline_aggregation_one_part_returns_its_greedy():
+    """m = 1: the gathered set is the standard greedy's own picks, and the
+    greedy over them picks them again in the same order."""
+    g, r, io, im = _small_collection(seed=150, n=200, count=2500, p_hi=0.2)
+    part = O.partition(g.n, 1, 3)
+    ls, lg, lc, lv = O.local_greedy(g.n, r.count, io, im, part, 1, 10)
+    gs, gg, gc = O.greedi_offline(g.n, r.count, io, im, ls, lc, 10)
+    s, ga, cov = O.greedy(g.n, r.count, io, im, 10)
+    assert list(gs) == list(s) and list(gg) == list(ga) and gc == cov
+
+
+def test_imm_randgreedi_final_choice():
+    """IMM with the RandGreedi selector: the result is the better of the
+    offline global solution and the best local one (Alg. 4, final step)."""
+    g = W.random_small_graph(400, 2400, seed=12, p_hi=0.3)
+    thr = O.ic_thresholds(g.weight)
+    res = O.imm(O.IC, g.in_off, g.in_src, thr, 6, 0.5, seed=5, selector=O.SEL_RANDGREEDI, m=4,
+                part_seed=6, theta=3000)
+    r = O.sample(O.IC, g.in_off, g.in_src, thr, 5, 1, 0, 3000)
+    io, im = O.incidence(g.n, r)
+    part = O.partition(g.n, 4, 6)
+    ls, lg, lc, lv = O.local_greedy(g.n, 3000, io, im, part, 4, 6)
+    gs, gg, gc = O.greedi_offline(g.n, 3000, io, im, ls, lc, 6)
+    assert res["coverage"] == max(gc, int(lv.max()))
+    assert res["global_won"] == int(gc >= lv.max())
+    assert res["stream_len"] == int(lc.sum())
