@@ -493,11 +493,11 @@ def bench_serve(args, im, W, torch):
     print(json.dumps(out), flush=True)
 
 
-def solve_steps(im, G, w, alpha, steps, warmup, torch):
+def solve_steps(im, G, w, alpha, steps, warmup, torch, selector=None):
     """Times `steps` whole solves after `warmup` untimed ones; every timed
     solve must give the same seeds.  Returns (seconds per solve, results)."""
-    kw = dict(selector=im.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha, seed=w.seed,
-              part_seed=w.part_seed)
+    kw = dict(selector=im.SEL_GREEDIRIS if selector is None else selector, m=w.m, delta=w.delta,
+              alpha=alpha, seed=w.seed, part_seed=w.part_seed)
     for i in range(warmup):
         res = im.solve(G, w.k, w.eps, **kw)
         log("alpha %g warmup %d: theta=%d rounds=%d coverage=%d sample launches %d passes %d"
@@ -554,7 +554,10 @@ def bench_imm(args, w, G, im, W, torch):
         "breakdown_ms": {"sample_main_kernel": round(mean("ms_sample_main"), 3),
                          "sample_large_kernel": round(mean("ms_sample_large"), 3),
                          "sample_gather": round(mean("ms_sample_gather"), 3),
-                         "select_all_rounds": round(mean("ms_select"), 3)},
+                         "select_all_rounds": round(mean("ms_select"), 3),
+                         "select_incidence": round(mean("ms_incidence"), 3),
+                         "select_local_greedy": round(mean("ms_local"), 3),
+                         "select_stream_cover": round(mean("ms_global"), 3)},
         "counts": {"sampled_sets": res["sampled_sets"], "sampled_sum_rrr": res["sampled_total"],
                    "probes": res["sampled_examined"], "edges_taken": res["sampled_live"],
                    "sample_launches": res["sample_launches"], "sample_passes": passes},
@@ -570,6 +573,22 @@ def bench_imm(args, w, G, im, W, torch):
                           "cover_ms": round(sum(o["ms_select"] for o in outs1) / len(outs1), 3),
                           "seeds_head": r1["seeds"][:8]}
         log("alpha 1: %.3f ms per solve" % (dt1 * 1e3))
+        dt2, outs2 = solve_steps(im, G, w, 1.0, args.steps, 1, torch,
+                                 selector=im.SEL_RANDGREEDI)
+        log("RandGreedi offline: %.3f ms per solve" % (dt2 * 1e3))
+
+        def split(os_, dt):
+            mk = lambda key: round(sum(o[key] for o in os_) / len(os_), 3)  # noqa: E731
+            return {"ms_per_solve": round(dt * 1e3, 3), "local_ms": mk("ms_local"),
+                    "global_ms": mk("ms_global"), "coverage": os_[0]["coverage"],
+                    "global_solution_chosen": os_[0]["global_won"]}
+        # the paper's Table 2 contrast: the local step (partition + local
+        # greedy over m parts) against the global step (streamed buckets, or
+        # the offline aggregation), summed over the solve's three selections
+        out["local_vs_global"] = {"greediris_alpha_0.125": split(outs, dt),
+                                  "greediris_alpha_1": split(outs1, dt1),
+                                  "randgreedi_offline": split(outs2, dt2)}
+        out["local_vs_global"]["randgreedi_offline"]["global_cover"] = outs2[0]["global_cover"]
         w2 = W.config(2)
         g2 = w2.graph
         G2 = im.prepare_graph(g2.in_off, g2.in_src, g2.weight, g2.model)

@@ -55,7 +55,7 @@ typedef enum {
 
 typedef enum { IM_IC = 0, IM_LT = 1 } im_model;
 
-typedef enum { IM_SEL_GREEDY = 0, IM_SEL_GREEDIRIS = 1 } im_selector;
+typedef enum { IM_SEL_GREEDY = 0, IM_SEL_GREEDIRIS = 1, IM_SEL_RANDGREEDI = 2 } im_selector;
 
 /* A graph prepared for sampling.  The in-edge CSR lists, for every vertex v,
  * the edges u -> v as in_src[in_off[v] .. in_off[v+1]); edge id e is the
@@ -118,6 +118,10 @@ int im_release(void);
  *   IM_TUNE_DENSE_RATIO    members per vertex above which the covering
  *                          subsets take the dense form, >= 0 (0: always
  *                          dense; default 256)
+ *   IM_TUNE_LT_BLOCKS      workgroups (4 wavefronts, one walk per lane) per CU
+ *                          of the LT sampling launch, 1..32 (default 2: measured
+ *                          fastest; walks are claimed 256 per wavefront, so more
+ *                          workgroups only add idle wavefronts and contention)
  * value -1 restores the default.  Returns IM_EINVAL for an unknown key or a
  * value outside its range (nothing changes then).  im_tune_get writes the
  * value in effect.
@@ -126,7 +130,8 @@ typedef enum {
   IM_TUNE_SAMPLE_BLOCKS = 0,
   IM_TUNE_BIG_SHAPE = 1,
   IM_TUNE_APPLY_BLOCKS = 2,
-  IM_TUNE_DENSE_RATIO = 3
+  IM_TUNE_DENSE_RATIO = 3,
+  IM_TUNE_LT_BLOCKS = 4
 } im_tune_key;
 int im_tune_set(int32_t key, int64_t value);
 int im_tune_get(int32_t key, int64_t* value);
@@ -269,6 +274,28 @@ int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off, const int3
                     const int64_t* lcover, double delta, double alpha, int32_t* seeds,
                     int32_t* nsel, int64_t* coverage, int32_t* info, void* stream);
 
+/*
+ * RandGreedi's global step without streaming, the offline GreeDI aggregation
+ * (Alg. 4: the local solutions are gathered, Alg. 2 lazy greedy selects among
+ * their union, then the final choice).  Gathered: the first T = ceil(alpha*k)
+ * picks of every part (clamped to [1,k]; all k at alpha = 1), i.e. row p of
+ * lseeds up to min(T, lcount[p]), from im_randgreedi.  The global solution
+ * S_g is the standard greedy (lowest id on ties, stop at zero gain -- the
+ * same picks as Alg. 2) with those vertices as candidates and all count
+ * samples as universe.  Final: S = S_g if C(S_g) >= max_p lcover[p], else
+ * the lowest p of largest lcover.
+ * seeds [device] k int32 (-1 past nsel); nsel [device] 1; coverage [device] 1
+ * int64; info [device] 4 int32 = {global solution chosen (1/0), vertices
+ * gathered, |S_g|, best local partition}; gcover [device] 1 int64 = C(S_g),
+ * or NULL.  0 < alpha <= 1, 1 <= m <= 256.  Reads lcount back to size the
+ * launches (synchronises `stream` once); otherwise asynchronous.
+ */
+int im_greedi_offline(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
+                      int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,
+                      int32_t m, const int32_t* lseeds, const int32_t* lcount,
+                      const int64_t* lcover, double alpha, int32_t* seeds, int32_t* nsel,
+                      int64_t* coverage, int32_t* info, int64_t* gcover, void* stream);
+
 /* IMM sample-size schedule (host values; see im_solve). */
 typedef struct {
   double ell, eps_prime, log_binom, lambda_prime, lambda_star;
@@ -283,10 +310,11 @@ int im_imm_plan(int32_t n, int32_t k, double eps, im_imm_plan_t* out);
 
 /* Options of im_solve. */
 typedef struct {
-  int32_t selector;      /* IM_SEL_GREEDY or IM_SEL_GREEDIRIS */
-  int32_t m;             /* partitions (GreediRIS), 1..256 */
+  int32_t selector;      /* IM_SEL_GREEDY, IM_SEL_GREEDIRIS or IM_SEL_RANDGREEDI */
+  int32_t m;             /* partitions (GreediRIS, RandGreedi), 1..256 */
   double delta;          /* bucket spacing (GreediRIS), 0 < delta < 1/2 */
-  double alpha;          /* truncation fraction (GreediRIS), 0 < alpha <= 1 */
+  double alpha;          /* truncation fraction (GreediRIS: streamed picks per part;
+                            RandGreedi: gathered picks per part), 0 < alpha <= 1 */
   uint64_t seed;         /* sampling seed */
   uint64_t part_seed;    /* partition seed (GreediRIS) */
   int64_t theta;         /* > 0: use this many samples and skip the IMM bound */
@@ -302,7 +330,8 @@ typedef struct {
   int64_t martingale_samples;  /* samples drawn in the martingale rounds */
   int32_t bucket;              /* b* of the last GreediRIS selection, else -1 */
   int32_t global_won;          /* 1 if the streamed solution won, 0 if local, -1 n/a */
-  int32_t stream_len;          /* seeds streamed in the last GreediRIS selection, else 0 */
+  int32_t stream_len;          /* seeds streamed (GreediRIS) or gathered (RandGreedi) in
+                                  the last selection, else 0 */
   int64_t final_total;         /* sum of set sizes of the final samples */
   /* Sampling and selection tally of the whole call (martingale rounds and
    * final samples).  Each pool extension samples its new sets once; the
@@ -316,6 +345,10 @@ typedef struct {
   double ms_sample_large;      /* large-set launches */
   double ms_sample_gather;     /* copies into the canonical pools */
   double ms_select;            /* covering subsets + selection, every round */
+  double ms_incidence;         /* ... of which covering subsets */
+  double ms_local;             /* ... standard greedy, or partition + local greedy */
+  double ms_global;            /* ... streaming cover or offline aggregation + final choice */
+  int64_t global_cover;        /* C(S_g) of the last RandGreedi selection, else -1 */
 } im_solve_result;
 
 /*
@@ -328,7 +361,8 @@ typedef struct {
  * ceil(lambda_star / LB), lambda_star = 2n((1-1/e) a + b)^2/eps^2, a = sqrt(ell ln n +
  * ln 2), b = sqrt((1-1/e)(ln C(n,k) + ell ln n + ln 2)), and the final seeds
  * are selected on theta fresh samples of stream 1.  The selector is the
- * standard greedy or GreediRIS (im_randgreedi + im_stream_cover).
+ * standard greedy, GreediRIS (im_randgreedi + im_stream_cover) or RandGreedi
+ * with the offline global step (im_randgreedi + im_greedi_offline).
  * seeds [host] k int32; res [host].  Synchronises `stream`.
  */
 int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* opts,

@@ -18,15 +18,16 @@ LIB_PATH = os.path.join(_HERE, "libim.so")
 
 IM_OK, IM_EINVAL, IM_ERANGE, IM_ENOMEM, IM_EDEVICE = 0, -1, -2, -3, -4
 IC, LT = 0, 1
-SEL_GREEDY, SEL_GREEDIRIS = 0, 1
-TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO = 0, 1, 2, 3
+SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
+TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS = \
+    0, 1, 2, 3, 4
 
 _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM",
            IM_EDEVICE: "IM_EDEVICE"}
 
 # every symbol the header declares
 EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
-           "im_build_incidence", "im_greedy_cover", "im_greedy_cover_static", "im_randgreedi", "im_stream_cover",
+           "im_build_incidence", "im_greedy_cover", "im_greedy_cover_static", "im_randgreedi", "im_stream_cover", "im_greedi_offline",
            "im_solve", "im_solve_batch", "im_imm_plan", "im_tune_set", "im_tune_get")
 
 
@@ -66,7 +67,9 @@ class _SolveResult(C.Structure):
                 ("sampled_sets", C.c_int64), ("sampled_total", C.c_int64),
                 ("sampled_examined", C.c_int64), ("sampled_live", C.c_int64),
                 ("ms_sample_main", C.c_double), ("ms_sample_large", C.c_double),
-                ("ms_sample_gather", C.c_double), ("ms_select", C.c_double)]
+                ("ms_sample_gather", C.c_double), ("ms_select", C.c_double),
+                ("ms_incidence", C.c_double), ("ms_local", C.c_double),
+                ("ms_global", C.c_double), ("global_cover", C.c_int64)]
 
 
 class _ImmPlan(C.Structure):
@@ -110,6 +113,8 @@ def lib():
         L.im_greedy_cover_static.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
         L.im_randgreedi.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, U64, P, P, P, P, P, P]
         L.im_stream_cover.argtypes = [I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P, P]
+        L.im_greedi_offline.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, P, P, P, D, P, P,
+                                        P, P, P, P]
         L.im_solve.argtypes = [C.POINTER(_Graph), I32, D, C.POINTER(_SolveOpts), P,
                                C.POINTER(_SolveResult), P]
         L.im_solve_batch.argtypes = [C.POINTER(_Task), I32, P, P, P, P, C.POINTER(_BatchStats),
@@ -291,6 +296,26 @@ def stream_cover(n: int, count: int, inc_off, inc_mem, lseeds, lcount, lcover, k
                                _ptr(nsel), _ptr(cov), _ptr(info), _stream(stream))
     _check(st, "im_stream_cover")
     return seeds, nsel, cov, info
+
+
+def greedi_offline(n: int, rrr: RRR, inc_off, inc_mem, lseeds, lcount, lcover, k: int,
+                   alpha: float = 1.0, stream=None):
+    """Offline GreeDI aggregation of the local solutions (Alg. 4).  Returns
+    device tensors (seeds int32[k], nsel int32[1], coverage int64[1], info
+    int32[4] = (global chosen, gathered, |S_g|, best local part), gcover int64[1])."""
+    dev = inc_off.device
+    m = lcount.numel()
+    seeds = torch.empty(k, dtype=torch.int32, device=dev)
+    nsel = torch.empty(1, dtype=torch.int32, device=dev)
+    cov = torch.empty(1, dtype=torch.int64, device=dev)
+    info = torch.empty(4, dtype=torch.int32, device=dev)
+    gcov = torch.empty(1, dtype=torch.int64, device=dev)
+    st = lib().im_greedi_offline(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
+                                 _ptr(inc_off), _ptr(inc_mem), k, m, _ptr(lseeds), _ptr(lcount),
+                                 _ptr(lcover), alpha, _ptr(seeds), _ptr(nsel), _ptr(cov),
+                                 _ptr(info), _ptr(gcov), _stream(stream))
+    _check(st, "im_greedi_offline")
+    return seeds, nsel, cov, info, gcov
 
 
 def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,

@@ -260,6 +260,7 @@ enum Slot {
   kSlotBatchMem,
   kSlotBatchInc,
   kSlotIncPairs,
+  kSlotOffline,
   kSlotCount
 };
 

@@ -18,9 +18,10 @@
 //    path: one workgroup per sample with a private visited bitmap and queue in
 //    HBM; members come out sorted from the bitmap.
 //  * LT: one lane per walk (walks are sequential chains), lanes refill from
-//    the work counter independently; the visited check is a per-lane hash in
-//    HBM; the kept edge is found by binary search over the inclusive integer
-//    prefix of the in-weights.
+//    the work counter independently; the visited check is a per-lane Bloom
+//    filter in registers backed by the walk's member list; the kept edge is
+//    found by binary search over the inclusive integer prefix of the
+//    in-weights.
 //  * Sets are first written to a staging arena (atomic cursor), then an
 //    exclusive scan of the sizes gives the canonical CSR offsets and a gather
 //    copies (and, for LT, sorts) each set into place.
@@ -72,7 +73,6 @@ struct BigCfg {
 using BigNarrow = BigCfg<64, IM_NARROW_BITS, 24>;
 using BigWide = BigCfg<256, 11, 8>;
 constexpr uint32_t kMaxHandoff = 1u << 16;  // large sets that resume from a snapshot
-constexpr int kLtH = 2048;                  // per-lane HBM hash slots (LT)
 constexpr int kLtCap = 1024;                // per-lane walk length before handing off
 constexpr int kLtBlock = 256;
 constexpr int kGatherSortCap = kLtCap;      // LT sets sorted by the gather kernel
@@ -1280,34 +1280,55 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
 }
 
 // ------------------------------------------------------------------ LT walks
-__device__ __forceinline__ bool lt_contains(const int32_t* H, int32_t u) {
-  uint32_t h = hash_slot(u, 11);
-  for (;;) {
-    const int32_t c = H[h];
-    if (c == u) return true;
-    if (c == kEmpty) return false;
-    h = (h + 1) & (kLtH - 1);
+// A walk's members are kept twice per lane: in order in the lane's list in
+// HBM (what is written out), and as a 256-bit Bloom filter in registers.  A
+// clear filter bit proves a vertex new, so the common step appends without
+// reading anything back; only on a set bit is the list scanned (16-byte
+// loads, eight members each round) for an exact answer.  Nothing has to be
+// cleared between walks.
+struct Bloom {
+  uint64_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ uint32_t bloom_bit(int32_t u) {
+  return ((uint32_t)u * 0x9E3779B1u) >> 24;
+}
+
+__device__ __forceinline__ bool bloom_has(const Bloom& b, uint32_t h) {
+  const uint64_t w = h < 128u ? (h < 64u ? b.w0 : b.w1) : (h < 192u ? b.w2 : b.w3);
+  return ((w >> (h & 63u)) & 1ull) != 0ull;
+}
+
+__device__ __forceinline__ void bloom_add(Bloom& b, uint32_t h) {
+  const uint64_t m = 1ull << (h & 63u);
+  if (h < 64u)
+    b.w0 |= m;
+  else if (h < 128u)
+    b.w1 |= m;
+  else if (h < 192u)
+    b.w2 |= m;
+  else
+    b.w3 |= m;
+}
+
+// Is u among the first len entries of the lane's list (16-byte aligned)?
+__device__ __forceinline__ bool list_has(const int32_t* Ls, int32_t len, int32_t u) {
+  for (int32_t j0 = 0; j0 < len; j0 += 8) {
+    const int4 x = *reinterpret_cast<const int4*>(Ls + j0);
+    const int4 y = *reinterpret_cast<const int4*>(Ls + j0 + 4);
+    const int32_t v[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+    bool hit = false;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) hit |= (j0 + q < len) & (v[q] == u);
+    if (hit) return true;
   }
-}
-__device__ __forceinline__ void lt_insert(int32_t* H, int32_t u) {
-  uint32_t h = hash_slot(u, 11);
-  while (H[h] != kEmpty) h = (h + 1) & (kLtH - 1);
-  H[h] = u;
-}
-// Removal in reverse insertion order restores the table exactly.
-__device__ __forceinline__ void lt_erase(int32_t* H, int32_t u) {
-  uint32_t h = hash_slot(u, 11);
-  while (H[h] != u) h = (h + 1) & (kLtH - 1);
-  H[h] = kEmpty;
+  return false;
 }
 
 // One lane per walk.  Lanes take new samples as their walks end (aggregated
-// per wave), so a long walk does not hold up the other 63 lanes.  The per-lane
-// hash (kLtH slots) is empty between walks.
-__global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* lane_hash,
-                                                        int32_t* lane_list) {
+// per wave), so a long walk does not hold up the other 63 lanes.
+__global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* lane_list) {
   const size_t gl = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t* H = lane_hash + gl * kLtH;
   int32_t* Ls = lane_list + gl * kLtCap;
   const int lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
@@ -1317,6 +1338,7 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
   GView G{};
   uint64_t seed = 0;
   int32_t v = 0, len = 0;
+  Bloom bl{0ull, 0ull, 0ull, 0ull};
   unsigned long long ex = 0, lv = 0, s_ex = 0, s_lv = 0, w_tot = 0;
   unsigned long long pnext = 0, pend = 0;  // this wave's pool of sample ids
   bool dry = false;                        // no ids left anywhere
@@ -1344,7 +1366,8 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
           G = view_of(A.tasks[tk]);
           seed = ((uint64_t)G.seed_hi << 32) | G.seed_lo;
           v = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
-          lt_insert(H, v);
+          bl = Bloom{0ull, 0ull, 0ull, 0ull};
+          bloom_add(bl, bloom_bit(v));
           Ls[0] = v;
           len = 1;
           s_ex = s_lv = 0;
@@ -1378,13 +1401,14 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
         } else {
           ++s_lv;
           const int32_t u = G.in_src[lo];
-          if (lt_contains(H, u)) {
+          const uint32_t h = bloom_bit(u);
+          if (bloom_has(bl, h) && list_has(Ls, len, u)) {
             fin = true;
           } else if (len == kLtCap) {
             fin = true;
             over = true;
           } else {
-            lt_insert(H, u);
+            bloom_add(bl, h);
             Ls[len++] = u;
             v = u;
           }
@@ -1414,14 +1438,21 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
         A.big_list[slot] = il;
         A.len[il] = -1;
       } else {
-        if (pos + (unsigned long long)len <= A.arena_cap)
-          for (int32_t j = 0; j < len; ++j) A.arena[pos + j] = Ls[j];
+        if (pos + (unsigned long long)len <= A.arena_cap) {
+          for (int32_t j0 = 0; j0 < len; j0 += 8) {  // eight members per round
+            const int4 x = *reinterpret_cast<const int4*>(Ls + j0);
+            const int4 y = *reinterpret_cast<const int4*>(Ls + j0 + 4);
+            const int32_t m8[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+              if (j0 + q < len) A.arena[pos + j0 + q] = m8[q];
+          }
+        }
         A.start[il] = (int64_t)pos;
         A.len[il] = len;
         ex += s_ex;
         lv += s_lv;
       }
-      for (int32_t j = len - 1; j >= 0; --j) lt_erase(H, Ls[j]);
       have = false;
     }
   }
@@ -1636,16 +1667,11 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
       Al.seg_task = d_task_lt;
       Al.nseg = (int32_t)task_lt.size();
       Al.count = (uint64_t)seg_lt.back();
-      const int blocks = di.num_cus * 2;
+      const int blocks = di.num_cus * (int)tune(IM_TUNE_LT_BLOCKS);
       const size_t lanes = (size_t)blocks * kLtBlock;
-      bool fresh = false;
       void* hp = nullptr;
-      IM_TRY(scratch_fresh(s, kSlotSampleLtLane, lanes * (kLtH + kLtCap) * sizeof(int32_t), &hp,
-                           &fresh));
-      if (fresh) IM_HIP(hipMemsetAsync(hp, 0xFF, lanes * kLtH * sizeof(int32_t), s));
-      int32_t* lane_hash = (int32_t*)hp;
-      int32_t* lane_list = lane_hash + lanes * kLtH;
-      k_sample_lt<<<dim3(blocks), dim3(kLtBlock), 0, s>>>(Al, lane_hash, lane_list);
+      IM_TRY(scratch(s, kSlotSampleLtLane, lanes * kLtCap * sizeof(int32_t), &hp));
+      k_sample_lt<<<dim3(blocks), dim3(kLtBlock), 0, s>>>(Al, (int32_t*)hp);
       IM_HIP(hipGetLastError());
     }
     if (timed) IM_HIP(hipEventRecord(ev[1], s));

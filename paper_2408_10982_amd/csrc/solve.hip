@@ -55,6 +55,7 @@ struct SolveTally {
   int32_t launches = 0, passes = 0;
   int64_t sets = 0, total = 0, examined = 0, live = 0;
   double ms_main = 0.0, ms_large = 0.0, ms_gather = 0.0, ms_select = 0.0;
+  double ms_inc = 0.0, ms_local = 0.0, ms_global = 0.0;
 };
 
 // Extends the pool to sets [0, want).  The new sets are sampled once into
@@ -109,17 +110,18 @@ struct Selection {
   int32_t bucket = -1;
   int32_t global_won = -1;
   int32_t stream_len = 0;
+  int64_t global_cover = -1;
 };
 
 static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o,
                      Selection* out, SolveTally* tally, hipStream_t s) {
   void *pio = nullptr, *pim = nullptr, *pout = nullptr;
-  hipEvent_t ev[2];
+  hipEvent_t ev[4];
   for (auto& e : ev) IM_HIP(hipEventCreate(&e));
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int j = 0; j < 2; ++j) (void)hipEventDestroy(e[j]);
+      for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[j]);
     }
   } ev_guard{ev};
   IM_HIP(hipEventRecord(ev[0], s));
@@ -128,18 +130,21 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
   int64_t* inc_off = (int64_t*)pio;
   int32_t* inc_mem = (int32_t*)pim;
   IM_TRY(im_build_incidence(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, s));
-  // outputs: seeds k, gains k, nsel, coverage, info 4
-  IM_TRY(scratch(s, kSlotSolveOut, (size_t)k * 12 + 64, &pout));
+  IM_HIP(hipEventRecord(ev[1], s));
+  // outputs: seeds k, coverage, nsel, info 4, global cover
+  IM_TRY(scratch(s, kSlotSolveOut, (size_t)k * 12 + 128, &pout));
   int32_t* d_seeds = (int32_t*)pout;
   int64_t* d_cov = (int64_t*)((char*)pout + ((size_t)k * 4 + 7) / 8 * 8);
   int32_t* d_nsel = (int32_t*)(d_cov + 1);
   int32_t* d_info = d_nsel + 2;
+  int64_t* d_gcov = (int64_t*)(d_info + 4);
   out->seeds.assign(k, -1);
   if (o->selector == IM_SEL_GREEDY) {
     void* pg = nullptr;
     IM_TRY(scratch(s, kSlotSolveLocal, (size_t)k * 8, &pg));
     IM_TRY(im_greedy_cover(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, d_seeds,
                            (int64_t*)pg, d_nsel, d_cov, s));
+    IM_HIP(hipEventRecord(ev[2], s));
   } else {
     const int32_t m = o->m;
     void* pl = nullptr;
@@ -152,27 +157,49 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
     uint8_t* part = (uint8_t*)(lcount + m);
     IM_TRY(im_randgreedi(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, m, o->part_seed,
                          part, lseeds, lgains, lcount, lcover, s));
-    IM_TRY(im_stream_cover(n, P.count, inc_off, inc_mem, k, m, lseeds, lcount, lcover, o->delta,
-                           o->alpha, d_seeds, d_nsel, d_cov, d_info, s));
+    IM_HIP(hipEventRecord(ev[2], s));
+    if (o->selector == IM_SEL_GREEDIRIS)
+      IM_TRY(im_stream_cover(n, P.count, inc_off, inc_mem, k, m, lseeds, lcount, lcover, o->delta,
+                             o->alpha, d_seeds, d_nsel, d_cov, d_info, s));
+    else
+      IM_TRY(im_greedi_offline(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, m, lseeds,
+                               lcount, lcover, o->alpha, d_seeds, d_nsel, d_cov, d_info, d_gcov,
+                               s));
   }
-  IM_HIP(hipEventRecord(ev[1], s));
+  IM_HIP(hipEventRecord(ev[3], s));
   int32_t h_nsel = 0, h_info[4] = {-1, 0, -1, 0};
-  int64_t h_cov = 0;
+  int64_t h_cov = 0, h_gcov = -1;
   IM_HIP(hipMemcpyAsync(out->seeds.data(), d_seeds, (size_t)k * 4, hipMemcpyDeviceToHost, s));
   IM_HIP(hipMemcpyAsync(&h_nsel, d_nsel, 4, hipMemcpyDeviceToHost, s));
   IM_HIP(hipMemcpyAsync(&h_cov, d_cov, 8, hipMemcpyDeviceToHost, s));
   if (o->selector != IM_SEL_GREEDY)
     IM_HIP(hipMemcpyAsync(h_info, d_info, 16, hipMemcpyDeviceToHost, s));
+  if (o->selector == IM_SEL_RANDGREEDI)
+    IM_HIP(hipMemcpyAsync(&h_gcov, d_gcov, 8, hipMemcpyDeviceToHost, s));
   IM_HIP(hipStreamSynchronize(s));
-  float ms = 0.f;
-  IM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-  if (tally) tally->ms_select += ms;
+  float t_inc = 0.f, t_loc = 0.f, t_glob = 0.f;
+  IM_HIP(hipEventElapsedTime(&t_inc, ev[0], ev[1]));
+  IM_HIP(hipEventElapsedTime(&t_loc, ev[1], ev[2]));
+  IM_HIP(hipEventElapsedTime(&t_glob, ev[2], ev[3]));
+  if (tally) {
+    tally->ms_select += (double)t_inc + t_loc + t_glob;
+    tally->ms_inc += t_inc;
+    tally->ms_local += t_loc;
+    tally->ms_global += t_glob;
+  }
   out->nsel = h_nsel;
   out->coverage = h_cov;
-  if (o->selector != IM_SEL_GREEDY) {
+  out->bucket = -1;
+  out->global_won = -1;
+  out->stream_len = 0;
+  out->global_cover = h_gcov;
+  if (o->selector == IM_SEL_GREEDIRIS) {
     out->bucket = h_info[0];
     out->global_won = h_info[2];
     out->stream_len = h_info[3];
+  } else if (o->selector == IM_SEL_RANDGREEDI) {
+    out->global_won = h_info[0];
+    out->stream_len = h_info[1];
   }
   return IM_OK;
 }
@@ -211,11 +238,13 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
                         int32_t* seeds, im_solve_result* res, void* stream) {
   using namespace im;
   if (!g || !o || !seeds || !res || k <= 0 || g->n <= 1 || k > g->n || !(eps > 0.0 && eps < 1.0) ||
-      (o->selector != IM_SEL_GREEDY && o->selector != IM_SEL_GREEDIRIS) || o->theta < 0)
+      (o->selector != IM_SEL_GREEDY && o->selector != IM_SEL_GREEDIRIS &&
+       o->selector != IM_SEL_RANDGREEDI) ||
+      o->theta < 0)
     return IM_EINVAL;
-  if (o->selector == IM_SEL_GREEDIRIS &&
-      (o->m < 1 || o->m > 256 || !(o->delta > 0.0 && o->delta < 0.5) ||
-       !(o->alpha > 0.0 && o->alpha <= 1.0)))
+  if (o->selector != IM_SEL_GREEDY &&
+      (o->m < 1 || o->m > 256 || !(o->alpha > 0.0 && o->alpha <= 1.0) ||
+       (o->selector == IM_SEL_GREEDIRIS && !(o->delta > 0.0 && o->delta < 0.5))))
     return IM_EINVAL;
   if (g->model != IM_IC && g->model != IM_LT) return IM_EINVAL;
   hipStream_t s = (hipStream_t)stream;
@@ -279,5 +308,9 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   res->ms_sample_large = tally.ms_large;
   res->ms_sample_gather = tally.ms_gather;
   res->ms_select = tally.ms_select;
+  res->ms_incidence = tally.ms_inc;
+  res->ms_local = tally.ms_local;
+  res->ms_global = tally.ms_global;
+  res->global_cover = sel.global_cover;
   return IM_OK;
 }

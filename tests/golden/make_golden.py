@@ -3,7 +3,8 @@
 Calls only the CPU oracle (oracle/) on the seeded synthetic workloads
 (workloads/); nothing here reads an output of the HIP path.  Run from the
 repository root:  python tests/golden/make_golden.py [2] [3]
-Config 2 takes about five minutes of single-core CPU time, config 3 a few.
+Config 2 takes about a minute of single-core CPU time, config 3 about five
+(four whole IMM solves), config 4 about three (the listed subset of tasks).
 """
 import hashlib
 import json
@@ -46,22 +47,33 @@ def config2():
     }
 
 
+CONFIG3_RUNS = (("1.0", "greediris", 1.0), ("0.125", "greediris", 0.125),
+                ("0.01", "greediris", 0.01), ("randgreedi", "randgreedi", 1.0))
+
+
 def config3():
+    """IMM + GreediRIS at alpha 1, 0.125 and 0.01 (T = 1: a 64-entry stream,
+    the first alpha at which truncation changes this workload's seeds), and
+    IMM + RandGreedi with the offline global step (Alg. 4)."""
     w = W.config(3)
     g = w.graph
     thr = O.thresholds(g.model, g.in_off, g.weight)
     out = {"workload": w.name, "k": w.k, "eps": w.eps, "m": w.m, "delta": w.delta,
            "seed": w.seed, "part_seed": w.part_seed, "runs": {}}
-    for alpha in w.alphas:
+    for key, sel, alpha in CONFIG3_RUNS:
         t0 = time.time()
         res = O.imm(g.model, g.in_off, g.in_src, thr, w.k, w.eps, seed=w.seed,
-                    selector=O.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha,
-                    part_seed=w.part_seed, lazy=True)
+                    selector=O.SEL_GREEDIRIS if sel == "greediris" else O.SEL_RANDGREEDI,
+                    m=w.m, delta=w.delta, alpha=alpha, part_seed=w.part_seed, lazy=True)
         res["seeds"] = res["seeds"].tolist()
+        res["selector"] = sel
+        res["alpha"] = alpha
         res["oracle_seconds"] = round(time.time() - t0, 1)
-        out["runs"][repr(alpha)] = res
+        out["runs"][key] = res
+        print("config 3 %s: %s" % (key, {k: v for k, v in res.items() if k != "seeds"}),
+              flush=True)
     # the final-stream sets themselves, for a sampled parity check
-    theta = out["runs"][repr(w.alphas[0])]["theta"]
+    theta = out["runs"]["1.0"]["theta"]
     r = O.sample(g.model, g.in_off, g.in_src, thr, w.seed, 1, 0, theta)
     out["final_theta"] = theta
     out["final_total"] = r.total
@@ -69,10 +81,38 @@ def config3():
     return out
 
 
+# Tasks of the 256-task batch the oracle checks: every 16th task whose oracle
+# run takes under a minute (task 176, IC with theta = 2^18 on 55,855 vertices,
+# takes over five), plus the IC task of most vertices (22: 62,968 vertices)
+# and the LT task of most vertices at theta = 2^17 (178: 65,131 vertices).
+CONFIG4_TASKS = (0, 16, 22, 32, 48, 64, 80, 96, 112, 128, 144, 160, 178, 192, 208, 224, 240)
+
+
+def config4():
+    spec = W.batch_tasks(256)
+    out = {"workload": "chunglu_batch_256", "tasks": {}}
+    for i in CONFIG4_TASKS:
+        t = spec[i]
+        g = W.batch_graph(t)
+        thr = O.thresholds(g.model, g.in_off, g.weight)
+        t0 = time.time()
+        r = O.sample(g.model, g.in_off, g.in_src, thr, t["seed"], 0, 0, t["theta"])
+        io, im_ = O.incidence(g.n, r)
+        seeds, gains, cov = O.greedy(g.n, t["theta"], io, im_, t["k"], lazy=True)
+        out["tasks"][str(i)] = {
+            "n": g.n, "model": t["model"], "k": t["k"], "theta": t["theta"],
+            "total": r.total, "examined": r.examined, "live": r.live,
+            "rrr_sha256": digest(r.off, r.mem), "seeds": seeds.tolist(),
+            "gains": gains.tolist(), "coverage": cov,
+            "oracle_seconds": round(time.time() - t0, 1)}
+        print("config 4 task %d: %.1f s" % (i, time.time() - t0), flush=True)
+    return out
+
+
 def main():
-    which = sys.argv[1:] or ["2", "3"]
+    which = sys.argv[1:] or ["2", "3", "4"]
     for c in which:
-        fn = {"2": config2, "3": config3}[c]
+        fn = {"2": config2, "3": config3, "4": config4}[c]
         t0 = time.time()
         res = fn()
         path = os.path.join(HERE, "config%s_expected.json" % c)

@@ -5,9 +5,13 @@ Config 2: R-MAT scale 20, 2^24 edges, IC weighted cascade, 2^20 RRR sets,
 greedy k = 100 -- the whole RRR collection (SHA-256 of the canonical CSR),
 its counters, sampled sets, and the seeds, gains and coverage.
 Config 3: R-MAT scale 22, 2^26 edges, LT, IMM with eps = 0.13, k = 100,
-GreediRIS (m = 64, delta = 0.077) with and without truncation (alpha 0.125)
--- the IMM sample counts, lower bound, seeds, coverage, winning bucket, and
-the final-stream RRR collection.
+GreediRIS (m = 64, delta = 0.077) at alpha 1, 0.125 and 0.01 (the last
+changes the seeds: one pick per partition streamed), and RandGreedi with the
+offline global step -- the IMM sample counts, lower bound, seeds, coverage,
+winning bucket, stream length, and the final-stream RRR collection.
+Config 4: the whole 256-task batch in one im_solve_batch call; a listed
+subset of its tasks (IC and LT, the largest graphs the oracle finishes)
+against the oracle: seeds, gains, coverage, and each task's RRR collection.
 """
 import hashlib
 import json
@@ -76,23 +80,48 @@ def c3(im):
     return w, im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
 
 
-@pytest.mark.parametrize("alpha", [1.0, 0.125])
-def test_config3_imm_greediris(im, c3, alpha):
-    print("[case] config 3 full size alpha=%s" % alpha, flush=True)
+@pytest.mark.parametrize("run", ["1.0", "0.125", "0.01", "randgreedi"])
+def test_config3_imm(im, c3, run):
+    print("[case] config 3 full size %s" % run, flush=True)
     exp = _golden(3)
-    run = exp["runs"][repr(alpha)]
+    e = exp["runs"][run]
     w, G = c3
-    got = im.solve(G, w.k, w.eps, selector=im.SEL_GREEDIRIS, m=w.m, delta=w.delta, alpha=alpha,
+    sel = im.SEL_GREEDIRIS if e["selector"] == "greediris" else im.SEL_RANDGREEDI
+    got = im.solve(G, w.k, w.eps, selector=sel, m=w.m, delta=w.delta, alpha=e["alpha"],
                    seed=w.seed, part_seed=w.part_seed)
-    assert got["theta"] == run["theta"]
-    assert got["rounds"] == run["rounds_run"]
-    assert got["martingale_samples"] == run["martingale_samples"]
-    assert got["lower_bound"] == run["lb"]
-    assert got["seeds"] == run["seeds"]
-    assert got["coverage"] == run["coverage"]
-    assert got["bucket"] == run["bucket"]
-    assert got["global_won"] == run["global_won"]
-    if alpha == 1.0:
+    assert got["theta"] == e["theta"]
+    assert got["rounds"] == e["rounds_run"]
+    assert got["martingale_samples"] == e["martingale_samples"]
+    assert got["lower_bound"] == e["lb"]
+    assert got["seeds"] == e["seeds"]
+    assert got["coverage"] == e["coverage"]
+    assert got["bucket"] == e["bucket"]
+    assert got["global_won"] == e["global_won"]
+    assert got["stream_len"] == e["stream_len"]
+    assert got["sample_passes"] == got["sample_launches"] == got["rounds"] + 1
+    if run == "1.0":
         r = im.sample_rrr(G, w.seed, 1, 0, exp["final_theta"], capacity=exp["final_total"])
         assert r.total == exp["final_total"] == got["final_total"]
         assert _digest(r.off, r.mem) == exp["final_rrr_sha256"]
+
+
+def test_config4_batch_subset(im):
+    print("[case] config 4 full batch", flush=True)
+    exp = _golden(4)["tasks"]
+    spec = W.batch_tasks(256)
+    graphs = [W.batch_graph(t) for t in spec]
+    prepared = [im.prepare_graph(g.in_off, g.in_src, g.weight, g.model) for g in graphs]
+    tasks = [(G, t["seed"], 0, t["k"], t["theta"]) for G, t in zip(prepared, spec)]
+    out, st = im.solve_batch(tasks)
+    assert st["sets"] == sum(t["theta"] for t in spec)
+    for key, e in exp.items():
+        i = int(key)
+        print("[case] config 4 task %d" % i, flush=True)
+        assert out[i]["seeds"] == e["seeds"]
+        assert out[i]["gains"] == e["gains"]
+        assert out[i]["coverage"] == e["coverage"]
+        G, seed, tag, k, theta = tasks[i]
+        r = im.sample_rrr(G, seed, tag, 0, theta, capacity=e["total"])
+        assert (r.total, r.examined, r.live) == (e["total"], e["examined"], e["live"])
+        assert _digest(r.off, r.mem) == e["rrr_sha256"]
+        del r

@@ -353,9 +353,37 @@ def test_stream_cover_all_streamed_sets_empty(im):
     assert (inf[0], inf[1], inf[2], inf[3]) == (gb, gnb, int(won), 5)
 
 
+@pytest.mark.parametrize("name,count,k,m,alpha", [
+    ("ic_dense", 2000, 10, 4, 1.0), ("lt_small", 6000, 20, 8, 1.0), ("rmat12", 16384, 16, 64, 1.0),
+    ("rmat12", 16384, 16, 64, 0.25), ("ic_sparse", 300, 16, 80, 1.0), ("ic_sparse", 3000, 1, 3, 1.0)])
+def test_greedi_offline(im, name, count, k, m, alpha):
+    """Alg. 4's offline global step: the GPU's S_g, its coverage, the final
+    choice and the gathered count against the oracle's lazy greedy over the
+    union of the local solutions."""
+    _say("offline", name, count, k, m, alpha)
+    g = GRAPHS[name]()
+    G, r, io, imem, o, oio, oim = _pipeline(im, g, count, 47)
+    part, ls, lg, lc, lv = im.randgreedi(g.n, r, io, imem, k, m, part_seed=55)
+    seeds, nsel, cov, info, gcov = im.greedi_offline(g.n, r, io, imem, ls, lc, lv, k, alpha)
+    opart = O.partition(g.n, m, 55)
+    ols, olg, olc, olv = O.local_greedy(g.n, count, oio, oim, opart, m, k)
+    assert np.array_equal(_np(lc), olc) and np.array_equal(_np(ls), ols)
+    gs, gg, gc = O.greedi_offline(g.n, count, oio, oim, ols, olc, k, alpha=alpha)
+    fs, fc, won = O.final_select(ols, olc, olv, gs, gc)
+    ns = int(_np(nsel)[0])
+    inf = _np(info)
+    T = O.trunc_len(k, alpha)
+    assert int(_np(gcov)[0]) == gc
+    assert (inf[0], inf[1], inf[2]) == (int(won), int(np.minimum(olc, T).sum()), len(gs))
+    assert ns == len(fs) and np.array_equal(_np(seeds)[:ns], fs)
+    assert np.all(_np(seeds)[ns:] == -1)
+    assert int(_np(cov)[0]) == fc
+
+
 @pytest.mark.parametrize("name,k,eps,selector", [
     ("ic_sparse", 5, 0.5, O.SEL_GREEDY), ("lt_small", 8, 0.4, O.SEL_GREEDIRIS),
-    ("rmat12", 16, 0.5, O.SEL_GREEDY), ("rmat12", 16, 0.5, O.SEL_GREEDIRIS)])
+    ("rmat12", 16, 0.5, O.SEL_GREEDY), ("rmat12", 16, 0.5, O.SEL_GREEDIRIS),
+    ("lt_small", 8, 0.4, O.SEL_RANDGREEDI), ("rmat12", 16, 0.5, O.SEL_RANDGREEDI)])
 def test_solve_imm(im, name, k, eps, selector):
     _say("imm", name, k, eps, selector)
     g = GRAPHS[name]()
@@ -369,6 +397,8 @@ def test_solve_imm(im, name, k, eps, selector):
     assert got["lower_bound"] == exp["lb"]
     assert got["seeds"] == exp["seeds"].tolist()
     assert got["coverage"] == exp["coverage"]
+    assert got["global_won"] == exp["global_won"] and got["bucket"] == exp["bucket"]
+    assert got["stream_len"] == exp["stream_len"]
 
 
 @pytest.mark.parametrize("form", ["auto", "dense", "tiled_slices"])
