@@ -119,9 +119,11 @@ int im_release(void);
  *                          subsets take the dense form, >= 0 (0: always
  *                          dense; default 256)
  *   IM_TUNE_LT_BLOCKS      workgroups (4 wavefronts, one walk per lane) per CU
- *                          of the LT sampling launch, 1..32 (default 2: measured
- *                          fastest; walks are claimed 256 per wavefront, so more
- *                          workgroups only add idle wavefronts and contention)
+ *                          of the LT sampling launch, 1..32 (default 7: at 70
+ *                          VGPRs, seven wavefronts per SIMD are resident at once)
+ *   IM_TUNE_LT_GRAB        sample ids an LT wavefront claims at once, 1..4096
+ *                          (default 16: with 256 only ~1,250 wavefronts of a
+ *                          320 K-walk launch get work; 16 spreads it over all)
  * value -1 restores the default.  Returns IM_EINVAL for an unknown key or a
  * value outside its range (nothing changes then).  im_tune_get writes the
  * value in effect.
@@ -131,7 +133,8 @@ typedef enum {
   IM_TUNE_BIG_SHAPE = 1,
   IM_TUNE_APPLY_BLOCKS = 2,
   IM_TUNE_DENSE_RATIO = 3,
-  IM_TUNE_LT_BLOCKS = 4
+  IM_TUNE_LT_BLOCKS = 4,
+  IM_TUNE_LT_GRAB = 5
 } im_tune_key;
 int im_tune_set(int32_t key, int64_t value);
 int im_tune_get(int32_t key, int64_t* value);

@@ -9,10 +9,10 @@ from .binding import (IC, LT, SEL_GREEDIRIS, SEL_GREEDY, SEL_RANDGREEDI, greedi_
                       build_incidence, greedy_cover, greedy_cover_static, lib, prepare_graph, randgreedi, release,
                       sample_rrr, solve, solve_batch, stream_cover, version,
                       imm_plan, sample_into, tune_set, tune_get, TUNE_SAMPLE_BLOCKS,
-                      TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS)
+                      TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS, TUNE_LT_GRAB)
 
 __all__ = ["IC", "LT", "SEL_GREEDY", "SEL_GREEDIRIS", "SEL_RANDGREEDI", "greedi_offline", "EXPORTS", "Graph", "ImError", "RRR",
            "build_incidence", "greedy_cover", "greedy_cover_static", "lib", "prepare_graph", "randgreedi", "release",
            "sample_rrr", "solve", "solve_batch", "stream_cover", "version", "imm_plan",
            "sample_into", "tune_set", "tune_get", "TUNE_SAMPLE_BLOCKS", "TUNE_BIG_SHAPE",
-           "TUNE_APPLY_BLOCKS", "TUNE_DENSE_RATIO", "TUNE_LT_BLOCKS"]
+           "TUNE_APPLY_BLOCKS", "TUNE_DENSE_RATIO", "TUNE_LT_BLOCKS", "TUNE_LT_GRAB"]

@@ -19,8 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libim.so")
 IM_OK, IM_EINVAL, IM_ERANGE, IM_ENOMEM, IM_EDEVICE = 0, -1, -2, -3, -4
 IC, LT = 0, 1
 SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
-TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS = \
-    0, 1, 2, 3, 4
+(TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS,
+ TUNE_LT_GRAB) = 0, 1, 2, 3, 4, 5
 
 _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM",
            IM_EDEVICE: "IM_EDEVICE"}

@@ -24,6 +24,7 @@ struct CoverArgs {
   const int32_t* __restrict__ inc_mem;   // sample ids (partition-local when sbase is set)
   const int32_t* __restrict__ order;     // n: vertex at each position (nullptr: identity)
   const int32_t* __restrict__ pos_of;    // n: position of each vertex (nullptr: identity)
+  const uint8_t* __restrict__ part;      // n: partition of each vertex (RandGreedi), or nullptr
   const int64_t* __restrict__ pbase;     // m+1: positions of partition p (nullptr: [0, n))
   const int32_t* __restrict__ kpart;     // m: picks per partition (nullptr: k)
   const int64_t* __restrict__ koff;      // m: first output slot (nullptr: p * k)

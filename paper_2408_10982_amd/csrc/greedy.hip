@@ -243,6 +243,9 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
       const int64_t a = __shfl(ma, src, kWave), b = __shfl(mb, src, kWave);
       for (int64_t t = a + lane; t < b; t += kWave) {
         const int32_t u = A.mem[t];
+        // RandGreedi: only members of the covering partition lose a count; the
+        // one-byte partition id is checked before the position lookup
+        if (A.part && A.part[u] != (uint8_t)s_p) continue;
         const int64_t pos = A.local_ids ? lo_p + u : (A.pos_of ? A.pos_of[u] : u);
         if (pos >= lo_p && pos < hi_p) atomicSub(&A.cnt[pos], 1u);
       }
@@ -690,6 +693,7 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   A.inc_mem = inc_mem;
   A.order = order;
   A.pos_of = pos_of;
+  A.part = part;
   A.pbase = pbase;
   A.cnt = cnt;
   A.covered = covered;

@@ -87,6 +87,7 @@ struct SampleArgs {
   const int32_t* __restrict__ seg_task;
   int32_t nseg;
   uint64_t count;                // work items of this launch
+  uint32_t lt_grab;              // LT: sample ids a wavefront claims at once
   int32_t* __restrict__ arena;
   uint64_t arena_cap;
   int64_t* __restrict__ start;   // per output position: arena position
@@ -200,9 +201,9 @@ __device__ __forceinline__ int owner_of(const int32_t* pre, int32_t gi) {
 constexpr int kUnroll = IM_UNROLL;  // 4-edge groups per lane per iteration
 
 // Same-address atomics serialise at one coherence point, so work and arena
-// space are claimed in batches: 64 sample ids per IC wavefront (kLtGrab for
-// LT) and kChunk arena entries per atomic.
-constexpr uint32_t kLtGrab = 256;
+// space are claimed in batches: 64 sample ids per IC wavefront (a launch
+// knob for LT) and kChunk arena entries per atomic.
+
 constexpr unsigned long long kChunk = 1024;
 
 __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long x, int src) {
@@ -1348,13 +1349,13 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
     if (need) {
       if (pnext == pend && !dry) {
         unsigned long long b = 0;
-        if (lane == 0) b = atomicAdd(&A.ctr[11], (unsigned long long)kLtGrab);
+        if (lane == 0) b = atomicAdd(&A.ctr[11], (unsigned long long)A.lt_grab);
         b = shfl_u64(b, 0);
         if (b >= A.count) {
           dry = true;
         } else {
           pnext = b;
-          pend = min(b + kLtGrab, (unsigned long long)A.count);
+          pend = min(b + A.lt_grab, (unsigned long long)A.count);
         }
       }
       const unsigned long long avail = pend - pnext;
@@ -1667,6 +1668,7 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
       Al.seg_task = d_task_lt;
       Al.nseg = (int32_t)task_lt.size();
       Al.count = (uint64_t)seg_lt.back();
+      Al.lt_grab = (uint32_t)tune(IM_TUNE_LT_GRAB);
       const int blocks = di.num_cus * (int)tune(IM_TUNE_LT_BLOCKS);
       const size_t lanes = (size_t)blocks * kLtBlock;
       void* hp = nullptr;

@@ -146,9 +146,18 @@ __global__ __launch_bounds__(kSBlock) void k_stream_bucket(StreamArgs A) {
       const int64_t a = A.sa[j], e = A.sb[j];
       if (e - a >= thr) {
         int32_t c = 0;
-        for (int64_t q = a + lane; q < e; q += kWave) {
-          const uint32_t i = (uint32_t)A.inc_mem[q];
-          c += (int32_t)(((bitmap_word<kLds>(bits, i) >> (i & 31u)) & 1u) ^ 1u);
+        constexpr int kU = 8;  // ids loaded together, then their bits tested
+        for (int64_t q0 = a + lane; q0 < e; q0 += kU * kWave) {
+          uint32_t ids[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) {
+            const int64_t q = q0 + (int64_t)u * kWave;
+            ids[u] = q < e ? (uint32_t)A.inc_mem[q] : 0xFFFFFFFFu;
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+            if (ids[u] != 0xFFFFFFFFu)
+              c += (int32_t)(((bitmap_word<kLds>(bits, ids[u]) >> (ids[u] & 31u)) & 1u) ^ 1u);
         }
         c = wave_sum(c);
         g = (int64_t)c >= thr ? c : -1;
