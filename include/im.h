@@ -30,7 +30,8 @@
  * Random numbers.  Every random quantity is one 32-bit word of Philox4x32-10
  * (Salmon et al., SC'11) with key (seed lo, seed hi) and counter
  * (id >> 2, sample id, domain tag, stream tag), word id & 3.  Domain tags:
- * root 0, IC edge 1, LT vertex 2, partition 3.  A draw depends only on its
+ * root 0, IC edge 1, LT vertex 2, partition 3, simulation edge 4, simulation
+ * vertex 5.  A draw depends only on its
  * ids, so results do not depend on launch shape or on how samples are split
  * (the property the paper's Leap-Frog generator provides, Sec. 3.2).
  */
@@ -97,8 +98,12 @@ const char* im_version(void);
 /* Text of the calling thread's last error: a failed HIP call, scratch
  * allocation or arena ("" if none). */
 const char* im_last_error(void);
+/* Device bytes of private scratch the library holds for `stream` on the
+ * current device (host query; grows with the largest call made on it). */
+int im_scratch_bytes(void* stream, size_t* bytes);
 /* Releases the library's device scratch for every stream of the current
- * device.  The caller must ensure no call is in flight. */
+ * device, and the calling thread's captured cover graphs.  The caller must
+ * ensure no call is in flight. */
 int im_release(void);
 
 /*
@@ -121,6 +126,12 @@ int im_release(void);
  *   IM_TUNE_LT_BLOCKS      workgroups (4 wavefronts, one walk per lane) per CU
  *                          of the LT sampling launch, 1..32 (default 7: at 70
  *                          VGPRs, seven wavefronts per SIMD are resident at once)
+ *   IM_TUNE_GRAPH          1: a cover's 2k + 2 launches (greedy, RandGreedi local
+ *                          step, offline aggregation, batch) are captured into a
+ *                          hipGraph once per launch shape and replayed (updated
+ *                          with each call's arguments) as one submission; 0:
+ *                          launched one by one (default 0: measured no faster,
+ *                          the launches already run back to back)
  *   IM_TUNE_LT_GRAB        sample ids an LT wavefront claims at once, 1..4096
  *                          (default 16: with 256 only ~1,250 wavefronts of a
  *                          320 K-walk launch get work; 16 spreads it over all)
@@ -134,7 +145,8 @@ typedef enum {
   IM_TUNE_APPLY_BLOCKS = 2,
   IM_TUNE_DENSE_RATIO = 3,
   IM_TUNE_LT_BLOCKS = 4,
-  IM_TUNE_LT_GRAB = 5
+  IM_TUNE_LT_GRAB = 5,
+  IM_TUNE_GRAPH = 6
 } im_tune_key;
 int im_tune_set(int32_t key, int64_t value);
 int im_tune_get(int32_t key, int64_t* value);
@@ -299,6 +311,37 @@ int im_greedi_offline(int32_t n, int64_t count, const int64_t* off, const int32_
                       const int64_t* lcover, double alpha, int32_t* seeds, int32_t* nsel,
                       int64_t* coverage, int32_t* info, int64_t* gcover, void* stream);
 
+/*
+ * Forward view of a graph for influence simulation: the in-edge ids grouped
+ * by source.  out_off [device] n+1 int64 (out_off[u] .. out_off[u+1] index
+ * out_eid); out_eid [device] E int32, the in-edge ids e with in_src[e] = u
+ * (order inside a source unspecified); edge_dst [device] E int32, the
+ * vertex whose in-edge list holds e.  Synchronises `stream`.
+ */
+int im_prepare_forward(int32_t n, int64_t num_edges, const int32_t* in_off, const int32_t* in_src,
+                       int64_t* out_off, int32_t* out_eid, int32_t* edge_dst, void* stream);
+
+/*
+ * Forward Monte-Carlo influence of a seed set -- the paper's quality measure
+ * (Sec. 4.1: mean number of vertices the diffusion model activates from the
+ * seeds over simulations).  Simulation r draws one live-edge world of the
+ * model (the live-edge reading of Sec. 2's IC and LT models) from its own
+ * domains, independent of the RRR samples:
+ *  IC: in-edge e is live iff thr[e] == 0xFFFFFFFF or draw(sim edge 4, r, e) < thr[e];
+ *  LT: vertex v keeps its first in-edge j with thr[j] > draw(sim vertex 5, r, v)
+ *      or thr[j] saturated (none if no such j).
+ * Activated = every vertex reachable from a seed over live edges, seeds
+ * included (duplicates once).  counts [device] nsims int64: the activated
+ * count of simulations r = first .. first+nsims-1 of (seed, stream_tag).
+ * seeds [host] nseeds ids in [0, n) (else IM_EINVAL).  out_off / out_eid /
+ * edge_dst from im_prepare_forward on the same graph.  first + nsims <= 2^32.
+ * Synchronises `stream` (once per batch of 16 levels of the search).
+ */
+int im_influence(const im_graph* g, const int64_t* out_off, const int32_t* out_eid,
+                 const int32_t* edge_dst, uint64_t seed, uint32_t stream_tag, int64_t first,
+                 int64_t nsims, const int32_t* seeds, int32_t nseeds, int64_t* counts,
+                 void* stream);
+
 /* IMM sample-size schedule (host values; see im_solve). */
 typedef struct {
   double ell, eps_prime, log_binom, lambda_prime, lambda_star;
@@ -310,6 +353,15 @@ typedef struct {
  * caller driving the rounds itself (e.g. over resident sample pools) takes
  * exactly the same decisions.  Host only; 2 <= n, 1 <= k <= n, 0 < eps < 1. */
 int im_imm_plan(int32_t n, int32_t k, double eps, im_imm_plan_t* out);
+
+/* One martingale round's test of Alg. 1 (the bounds of im_solve): after
+ * round x (1-based) selected seeds covering `coverage` of its theta_x
+ * samples, stop = 1 and lb = n C / (theta_x (1 + eps')) when
+ * n C / theta_x >= (1 + eps') n / 2^x; else stop = 0, lb = 1.  Host only. */
+int im_imm_round(const im_imm_plan_t* plan, int32_t n, int32_t round, int64_t theta_x,
+                 int64_t coverage, int32_t* stop, double* lb);
+/* The final sample count of Alg. 1: theta = ceil(lambda_star / lb).  Host only. */
+int im_imm_theta(const im_imm_plan_t* plan, double lb, int64_t* theta);
 
 /* Options of im_solve. */
 typedef struct {
@@ -370,6 +422,46 @@ typedef struct {
  */
 int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* opts,
              int32_t* seeds, im_solve_result* res, void* stream);
+
+/* Result of im_opim (host). */
+typedef struct {
+  int32_t nsel;
+  int32_t rounds;
+  int64_t theta;        /* samples per half (R1 and R2 each) in the last round */
+  int64_t cover1;       /* C(S*) on R1 */
+  int64_t cover2;       /* C(S*) on R2 */
+  int64_t upper1;       /* upper bound on the optimum's coverage of R1 */
+  double lower;         /* lower bound on sigma(S*) */
+  double upper;         /* upper bound on sigma(OPT) */
+  double guarantee;     /* lower / upper: the instance-wise approximation guarantee */
+  double theta_max;
+  int32_t i_max;
+  int32_t bucket;       /* b* of the last GreediRIS selection, else -1 */
+  int32_t global_won;   /* as in im_solve_result */
+} im_opim_result;
+
+/*
+ * OPIM, the online RIS method the paper extends GreediRIS to (Sec. 3.3,
+ * closing paragraph; Sec. 4.4), with the OPIM-C bounds of Tang, Tang, Xiao
+ * and Yuan (2018).  Each round holds two independent halves of theta sets,
+ * R1 (stream 0) and R2 (stream 1), doubled from round to round (earlier
+ * samples kept); S* is selected on R1 by opts->selector (as in im_solve) and
+ * validated on R2.  With a = ln(3 i_max / fail), in fp64:
+ *   theta_max = 2n((1-1/e) sqrt(ln(6/fail)) + sqrt((1-1/e)(ln C(n,k) + ln(6/fail))))^2
+ *               / (eps^2 k);   theta_1 = ceil(theta_max eps^2 k / n);
+ *   i_max = max(1, ceil(log2(theta_max / theta_1)));
+ *   U = min(sum of the k largest |S_R1(v)|, C_R1(S*) + sum of the k largest
+ *       marginals |S_R1(v) minus covered|) -- an upper bound on the optimum's
+ *       coverage of R1 for any selector, by submodularity;
+ *   lower = ((sqrt(C_R2(S*) + 2a/9) - sqrt(a/2))^2 - a/18) n / theta;
+ *   upper = (sqrt(U + a/2) + sqrt(a/2))^2 n / theta;  guarantee = lower / upper.
+ * Stops when guarantee >= 1 - 1/e - eps, at round i_max, or once the two
+ * halves together hold theta_cap samples or more (the paper's runs stop at
+ * 2^20).  0 < eps < 1, 0 < fail < 1.  seeds [host] k int32 (-1 past nsel);
+ * res [host].  opts->theta is ignored.  Synchronises `stream`.
+ */
+int im_opim(const im_graph* g, int32_t k, double eps, double fail, int64_t theta_cap,
+            const im_solve_opts* opts, int32_t* seeds, im_opim_result* res, void* stream);
 
 /* One task of a batch: theta samples [0, theta) of (seed, stream_tag) on a
  * prepared graph, then the standard greedy with k picks. */

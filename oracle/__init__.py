@@ -22,7 +22,7 @@ _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 IC, LT = 0, 1
 SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
-TAG_ROOT, TAG_EDGE, TAG_VERT, TAG_PART = 0, 1, 2, 3
+TAG_ROOT, TAG_EDGE, TAG_VERT, TAG_PART, TAG_SIM_EDGE, TAG_SIM_VERT = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +59,13 @@ class _ImmOpts(C.Structure):
                 ("eps", C.c_double), ("delta", C.c_double), ("alpha", C.c_double),
                 ("seed", C.c_uint64), ("part_seed", C.c_uint64),
                 ("theta_override", C.c_int64)]
+
+
+class _OpimResult(C.Structure):
+    _fields_ = [("nsel", C.c_int32), ("rounds", C.c_int32), ("theta", C.c_int64),
+                ("cover1", C.c_int64), ("cover2", C.c_int64), ("upper1", C.c_int64),
+                ("lower", C.c_double), ("upper", C.c_double), ("guarantee", C.c_double),
+                ("theta_max", C.c_double), ("i_max", C.c_int32)]
 
 
 class _ImmResult(C.Structure):
@@ -114,6 +121,10 @@ def lib():
                                         C.c_double, C.c_int, P, P, P, P]
         L.or_final_select.argtypes = [C.c_int32, C.c_int32, P, P, P, P, C.c_int32,
                                       C.c_int64, P, P, P]
+        L.or_influence.argtypes = [C.c_int, C.c_int32, P, P, P, C.c_uint64, C.c_uint32,
+                                   C.c_uint32, C.c_int64, C.c_int32, P, P]
+        L.or_opim.argtypes = [C.c_int32, P, P, P, P, C.POINTER(_ImmOpts), C.c_double,
+                              C.c_int64, P, C.POINTER(_OpimResult)]
         L.or_imm_parameters.argtypes = [C.c_int32, C.c_int32, C.c_double,
                                         C.POINTER(_ImmParams)]
         L.or_imm.argtypes = [C.c_int32, P, P, P, P, C.POINTER(_ImmOpts), P,
@@ -368,6 +379,20 @@ def final_select(lseeds, lcount, lcover, gseeds, gcover: int):
     return seeds[:nsel.value].copy(), int(cov.value), bool(won)
 
 
+def influence(model: int, in_off, in_src, thr, seed: int, stream: int, first: int, nsims: int,
+              seeds) -> np.ndarray:
+    """Activated-vertex count of each forward simulation r in [first, first+nsims)."""
+    in_off = _c(in_off, np.int32)
+    in_src = _c(in_src, np.int32)
+    thr = _c(thr, np.uint32)
+    sd = _c(np.asarray(seeds).reshape(-1), np.int32)
+    out = np.zeros(nsims, np.int64)
+    if lib().or_influence(model, in_off.shape[0] - 1, _p(in_off), _p(in_src), _p(thr), seed,
+                          stream, first, nsims, sd.shape[0], _p(sd), _p(out)):
+        raise MemoryError("oracle influence failed")
+    return out
+
+
 def imm_parameters(n: int, k: int, eps: float) -> dict:
     p = _ImmParams()
     lib().or_imm_parameters(n, k, eps, C.byref(p))
@@ -390,5 +415,26 @@ def imm(model: int, in_off, in_src, thr, k: int, eps: float, seed: int,
                     _p(sk) if sk is not None else None, C.byref(o), _p(seeds), C.byref(res)):
         raise MemoryError("oracle IMM failed")
     out = {f: getattr(res, f) for f, _ in _ImmResult._fields_}
+    out["seeds"] = seeds[:res.nsel].copy()
+    return out
+
+
+def opim(model: int, in_off, in_src, thr, k: int, eps: float, seed: int, fail: float,
+         theta_cap: int, selector: int = SEL_GREEDY, m: int = 1, delta: float = 0.077,
+         alpha: float = 1.0, part_seed: int = 0, lazy: bool = True, skip="auto"):
+    """OPIM rounds (R1 on stream 0, R2 on stream 1).  Returns a dict."""
+    in_off = _c(in_off, np.int32)
+    in_src = _c(in_src, np.int32)
+    thr = _c(thr, np.uint32)
+    sk = _skip_arg(model, in_off, thr, skip)
+    o = _ImmOpts(model=model, selector=selector, lazy=int(lazy), k=k, m=m, eps=eps,
+                 delta=delta, alpha=alpha, seed=seed, part_seed=part_seed, theta_override=0)
+    res = _OpimResult()
+    seeds = np.zeros(k, np.int32)
+    if lib().or_opim(in_off.shape[0] - 1, _p(in_off), _p(in_src), _p(thr),
+                     _p(sk) if sk is not None else None, C.byref(o), fail, theta_cap,
+                     _p(seeds), C.byref(res)):
+        raise MemoryError("oracle OPIM failed")
+    out = {f: getattr(res, f) for f, _ in _OpimResult._fields_}
     out["seeds"] = seeds[:res.nsel].copy()
     return out

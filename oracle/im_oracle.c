@@ -671,6 +671,82 @@ int or_final_select(int32_t m, int32_t k, const int32_t* lseeds, const int32_t* 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Forward influence simulation (the quality measure of Sec. 4.1).           */
+/* ------------------------------------------------------------------------ */
+/* LT: the in-edge v keeps in world r (-1 if none), by a linear scan of its
+ * prefix sums */
+static int32_t sim_kept_edge(const int32_t* in_off, const uint32_t* thr, uint64_t seed,
+                             uint32_t stream, uint32_t r, int32_t v) {
+  uint32_t x = or_draw(seed, OR_TAG_SIM_VERT, stream, r, (uint32_t)v);
+  for (int32_t j = in_off[v]; j < in_off[v + 1]; ++j)
+    if (thr[j] > x || thr[j] == 0xFFFFFFFFu) return j;
+  return -1;
+}
+
+int or_influence(int model, int32_t n, const int32_t* in_off, const int32_t* in_src,
+                 const uint32_t* thr, uint64_t seed, uint32_t stream, uint32_t first,
+                 int64_t nsims, int32_t nseeds, const int32_t* seeds, int64_t* counts) {
+  int64_t E = in_off[n];
+  /* out-edges of every vertex: the in-edge ids grouped by their source */
+  int32_t* out_off = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  int32_t* out_e = (int32_t*)malloc(((size_t)E + 1) * sizeof(int32_t));
+  int32_t* dst = (int32_t*)malloc(((size_t)E + 1) * sizeof(int32_t));
+  int32_t* fill = (int32_t*)malloc(((size_t)n + 1) * sizeof(int32_t));
+  uint32_t* mark = (uint32_t*)calloc((size_t)n + 1, sizeof(uint32_t));
+  int32_t* queue = (int32_t*)malloc(((size_t)n + 1) * sizeof(int32_t));
+  /* LT: each vertex's kept edge, found once per simulation */
+  uint32_t* kstamp = (uint32_t*)calloc((size_t)n + 1, sizeof(uint32_t));
+  int32_t* kept = (int32_t*)malloc(((size_t)n + 1) * sizeof(int32_t));
+  if (!out_off || !out_e || !dst || !fill || !mark || !queue || !kstamp || !kept) {
+    free(out_off); free(out_e); free(dst); free(fill); free(mark); free(queue);
+    free(kstamp); free(kept);
+    return -1;
+  }
+  for (int32_t v = 0; v < n; ++v)
+    for (int32_t e = in_off[v]; e < in_off[v + 1]; ++e) {
+      dst[e] = v;
+      out_off[in_src[e] + 1]++;
+    }
+  for (int32_t u = 0; u < n; ++u) out_off[u + 1] += out_off[u];
+  for (int32_t u = 0; u < n; ++u) fill[u] = out_off[u];
+  for (int64_t e = 0; e < E; ++e) out_e[fill[in_src[e]]++] = (int32_t)e;
+  for (int64_t s = 0; s < nsims; ++s) {
+    uint32_t r = first + (uint32_t)s, stamp = (uint32_t)(s + 1);
+    int32_t head = 0, tail = 0;
+    for (int32_t j = 0; j < nseeds; ++j)
+      if (mark[seeds[j]] != stamp) {
+        mark[seeds[j]] = stamp;
+        queue[tail++] = seeds[j];
+      }
+    while (head < tail) {
+      int32_t u = queue[head++];
+      for (int32_t j = out_off[u]; j < out_off[u + 1]; ++j) {
+        int32_t e = out_e[j], v = dst[e];
+        if (mark[v] == stamp) continue;
+        int live;
+        if (model == OR_IC) {
+          uint32_t q = thr[e];
+          live = q == 0xFFFFFFFFu || or_draw(seed, OR_TAG_SIM_EDGE, stream, r, (uint32_t)e) < q;
+        } else {
+          if (kstamp[v] != stamp) {
+            kstamp[v] = stamp;
+            kept[v] = sim_kept_edge(in_off, thr, seed, stream, r, v);
+          }
+          live = kept[v] == e;
+        }
+        if (!live) continue;
+        mark[v] = stamp;
+        queue[tail++] = v;
+      }
+    }
+    counts[s] = tail;
+  }
+  free(out_off); free(out_e); free(dst); free(fill); free(mark); free(queue);
+  free(kstamp); free(kept);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* IMM (Alg. 1; sample-size bounds of Tang, Shi and Xiao 2015, with the      */
 /* fresh final sample of Chen 2018 that Alg. 1 writes as Sample(G, theta)).  */
 /* ------------------------------------------------------------------------ */
@@ -816,4 +892,99 @@ int or_imm(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32
   res->global_won = gwon;
   res->stream_len = slen;
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* OPIM (bounds of Tang, Tang, Xiao and Yuan 2018).                          */
+/* ------------------------------------------------------------------------ */
+static int cmp_i64_desc(const void* a, const void* b) {
+  int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+  return (x < y) - (x > y);
+}
+
+/* sum of the k largest of v[0..n) (v is reordered) */
+static int64_t top_k_sum(int64_t* v, int32_t n, int32_t k) {
+  qsort(v, (size_t)n, sizeof(int64_t), cmp_i64_desc);
+  int64_t s = 0;
+  for (int32_t j = 0; j < k && j < n; ++j) s += v[j];
+  return s;
+}
+
+int or_opim(int32_t n, const int32_t* in_off, const int32_t* in_src, const uint32_t* thr,
+            const double* skip, const or_imm_opts* opt, double fail, int64_t theta_cap,
+            int32_t* seeds, or_opim_result* res) {
+  memset(res, 0, sizeof(*res));
+  int32_t k = opt->k;
+  double nd = (double)n, eps = opt->eps;
+  double e1 = 1.0 - exp(-1.0);
+  double lb = 0.0; /* ln C(n, k) */
+  for (int32_t i = 0; i < k; ++i) lb += log(nd - (double)i);
+  for (int32_t i = 1; i <= k; ++i) lb -= log((double)i);
+  double l6 = log(6.0 / fail);
+  double t = e1 * sqrt(l6) + sqrt(e1 * (lb + l6));
+  double theta_max = 2.0 * nd * t * t / (eps * eps * (double)k);
+  int64_t theta = (int64_t)ceil(theta_max * eps * eps * (double)k / nd);
+  int32_t i_max = (int32_t)ceil(log2(theta_max / (double)theta));
+  if (i_max < 1) i_max = 1;
+  double a = log(3.0 * (double)i_max / fail);
+  res->theta_max = theta_max;
+  res->i_max = i_max;
+  pool_t R1 = {0, 0, NULL, NULL}, R2 = {0, 0, NULL, NULL};
+  int64_t* marg = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+  int rc = 0;
+  for (int32_t i = 1;; ++i) {
+    if (pool_extend(&R1, opt->model, n, in_off, in_src, thr, skip, opt->seed, 0u, theta) ||
+        pool_extend(&R2, opt->model, n, in_off, in_src, thr, skip, opt->seed, 1u, theta)) {
+      rc = -1;
+      break;
+    }
+    int32_t nsel = 0, bucket = -1, slen = 0;
+    int64_t cov1 = 0;
+    int gwon = -1;
+    select_on(&R1, n, opt, seeds, &nsel, &cov1, &bucket, &gwon, &slen);
+    /* upper bound on the optimum's coverage of R1 */
+    int64_t* io1 = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t* im1 = (int32_t*)malloc(((size_t)R1.total + 1) * sizeof(int32_t));
+    or_incidence(n, R1.count, R1.off, R1.mem, io1, im1);
+    for (int32_t v = 0; v < n; ++v) marg[v] = io1[v + 1] - io1[v];
+    int64_t u0 = top_k_sum(marg, n, k);
+    uint8_t* cov = (uint8_t*)calloc((size_t)R1.count + 1, 1);
+    for (int32_t j = 0; j < nsel; ++j) cover_with(io1, im1, cov, seeds[j]);
+    for (int32_t v = 0; v < n; ++v) marg[v] = marginal(io1, im1, cov, v);
+    int64_t u1 = cov1 + top_k_sum(marg, n, k);
+    int64_t up1 = u0 < u1 ? u0 : u1;
+    free(cov);
+    free(io1);
+    free(im1);
+    /* validation on R2 */
+    int64_t* io2 = (int64_t*)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t* im2 = (int32_t*)malloc(((size_t)R2.total + 1) * sizeof(int32_t));
+    or_incidence(n, R2.count, R2.off, R2.mem, io2, im2);
+    int64_t cov2 = or_coverage(n, R2.count, io2, im2, nsel, seeds);
+    free(io2);
+    free(im2);
+    double th = (double)theta;
+    double x = sqrt((double)cov2 + 2.0 * a / 9.0) - sqrt(a / 2.0);
+    double lower = (x * x - a / 18.0) * nd / th;
+    double y = sqrt((double)up1 + a / 2.0) + sqrt(a / 2.0);
+    double upper = y * y * nd / th;
+    double g = lower / upper;
+    res->nsel = nsel;
+    res->rounds = i;
+    res->theta = theta;
+    res->cover1 = cov1;
+    res->cover2 = cov2;
+    res->upper1 = up1;
+    res->lower = lower;
+    res->upper = upper;
+    res->guarantee = g;
+    if (g >= e1 - eps || i >= i_max || 2 * theta >= theta_cap) break;
+    theta *= 2;
+  }
+  free(marg);
+  free(R1.off);
+  free(R1.mem);
+  free(R2.off);
+  free(R2.mem);
+  return rc;
 }

@@ -20,7 +20,7 @@ IM_OK, IM_EINVAL, IM_ERANGE, IM_ENOMEM, IM_EDEVICE = 0, -1, -2, -3, -4
 IC, LT = 0, 1
 SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
 (TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS,
- TUNE_LT_GRAB) = 0, 1, 2, 3, 4, 5
+ TUNE_LT_GRAB, TUNE_GRAPH) = 0, 1, 2, 3, 4, 5, 6
 
 _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM",
            IM_EDEVICE: "IM_EDEVICE"}
@@ -28,7 +28,9 @@ _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM
 # every symbol the header declares
 EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_sample_rrr",
            "im_build_incidence", "im_greedy_cover", "im_greedy_cover_static", "im_randgreedi", "im_stream_cover", "im_greedi_offline",
-           "im_solve", "im_solve_batch", "im_imm_plan", "im_tune_set", "im_tune_get")
+           "im_prepare_forward", "im_influence", "im_opim",
+           "im_solve", "im_solve_batch", "im_imm_plan", "im_imm_round", "im_imm_theta",
+           "im_scratch_bytes", "im_tune_set", "im_tune_get")
 
 
 class ImError(RuntimeError):
@@ -78,6 +80,14 @@ class _ImmPlan(C.Structure):
                 ("theta1", C.c_int64), ("rounds", C.c_int32)]
 
 
+class _OpimResult(C.Structure):
+    _fields_ = [("nsel", C.c_int32), ("rounds", C.c_int32), ("theta", C.c_int64),
+                ("cover1", C.c_int64), ("cover2", C.c_int64), ("upper1", C.c_int64),
+                ("lower", C.c_double), ("upper", C.c_double), ("guarantee", C.c_double),
+                ("theta_max", C.c_double), ("i_max", C.c_int32), ("bucket", C.c_int32),
+                ("global_won", C.c_int32)]
+
+
 class _Task(C.Structure):
     _fields_ = [("graph", _Graph), ("seed", C.c_uint64), ("stream_tag", C.c_uint32),
                 ("k", C.c_int32), ("theta", C.c_int64)]
@@ -113,6 +123,10 @@ def lib():
         L.im_greedy_cover_static.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
         L.im_randgreedi.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, U64, P, P, P, P, P, P]
         L.im_stream_cover.argtypes = [I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P, P]
+        L.im_opim.argtypes = [C.POINTER(_Graph), I32, D, D, I64, C.POINTER(_SolveOpts), P,
+                              C.POINTER(_OpimResult), P]
+        L.im_prepare_forward.argtypes = [I32, I64, P, P, P, P, P, P]
+        L.im_influence.argtypes = [C.POINTER(_Graph), P, P, P, U64, U32, I64, I64, P, I32, P, P]
         L.im_greedi_offline.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, P, P, P, D, P, P,
                                         P, P, P, P]
         L.im_solve.argtypes = [C.POINTER(_Graph), I32, D, C.POINTER(_SolveOpts), P,
@@ -120,6 +134,10 @@ def lib():
         L.im_solve_batch.argtypes = [C.POINTER(_Task), I32, P, P, P, P, C.POINTER(_BatchStats),
                                      P]
         L.im_imm_plan.argtypes = [I32, I32, D, C.POINTER(_ImmPlan)]
+        L.im_imm_round.argtypes = [C.POINTER(_ImmPlan), I32, I32, I64, I64,
+                                   C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+        L.im_imm_theta.argtypes = [C.POINTER(_ImmPlan), D, C.POINTER(C.c_int64)]
+        L.im_scratch_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
         L.im_tune_set.argtypes = [I32, I64]
         L.im_tune_get.argtypes = [I32, C.POINTER(C.c_int64)]
         for f in EXPORTS[2:]:
@@ -318,6 +336,41 @@ def greedi_offline(n: int, rrr: RRR, inc_off, inc_mem, lseeds, lcount, lcover, k
     return seeds, nsel, cov, info, gcov
 
 
+@dataclass
+class Forward:
+    """Out-edge view of a prepared graph (im_prepare_forward)."""
+    out_off: torch.Tensor    # int64 [n+1]
+    out_eid: torch.Tensor    # int32 [E]
+    edge_dst: torch.Tensor   # int32 [E]
+
+
+def prepare_forward(g: Graph, stream=None) -> Forward:
+    dev = g.in_off.device
+    out_off = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
+    out_eid = torch.empty(max(g.num_edges, 1), dtype=torch.int32, device=dev)
+    edge_dst = torch.empty(max(g.num_edges, 1), dtype=torch.int32, device=dev)
+    st = lib().im_prepare_forward(g.n, g.num_edges, _ptr(g.in_off),
+                                  _ptr(g.in_src) if g.num_edges else None, _ptr(out_off),
+                                  _ptr(out_eid), _ptr(edge_dst), _stream(stream))
+    _check(st, "im_prepare_forward")
+    return Forward(out_off, out_eid, edge_dst)
+
+
+def influence(g: Graph, fwd: Forward, seed: int, stream_tag: int, first: int, nsims: int,
+              seeds, stream=None) -> torch.Tensor:
+    """Activated-vertex counts of forward simulations [first, first+nsims)
+    (int64 device tensor)."""
+    sd = [int(x) for x in seeds]
+    arr = (C.c_int32 * max(len(sd), 1))(*sd)
+    counts = torch.empty(max(nsims, 1), dtype=torch.int64, device=g.in_off.device)
+    gs = g.struct()
+    st = lib().im_influence(C.byref(gs), _ptr(fwd.out_off), _ptr(fwd.out_eid),
+                            _ptr(fwd.edge_dst), seed, stream_tag, first, nsims, arr, len(sd),
+                            _ptr(counts), _stream(stream))
+    _check(st, "im_influence")
+    return counts[:nsims]
+
+
 def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,
           delta: float = 0.077, alpha: float = 1.0, seed: int = 0, part_seed: int = 0,
           theta: int = 0, stream=None) -> dict:
@@ -328,6 +381,22 @@ def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,
     st = lib().im_solve(C.byref(gs), k, eps, C.byref(o), seeds, C.byref(res), _stream(stream))
     _check(st, "im_solve")
     out = {f: getattr(res, f) for f, _ in _SolveResult._fields_}
+    out["seeds"] = list(seeds)[:res.nsel]
+    return out
+
+
+def opim(g: Graph, k: int, eps: float, fail: float, theta_cap: int,
+         selector: int = SEL_GREEDY, m: int = 1, delta: float = 0.077, alpha: float = 1.0,
+         seed: int = 0, part_seed: int = 0, stream=None) -> dict:
+    """OPIM rounds with the given selector (im_opim)."""
+    o = _SolveOpts(selector, m, delta, alpha, seed, part_seed, 0)
+    res = _OpimResult()
+    seeds = (C.c_int32 * k)()
+    gs = g.struct()
+    st = lib().im_opim(C.byref(gs), k, eps, fail, theta_cap, C.byref(o), seeds, C.byref(res),
+                       _stream(stream))
+    _check(st, "im_opim")
+    out = {f: getattr(res, f) for f, _ in _OpimResult._fields_}
     out["seeds"] = list(seeds)[:res.nsel]
     return out
 
@@ -361,10 +430,39 @@ def solve_batch(tasks, stream=None):
     return out, {f: getattr(st, f) for f, _ in _BatchStats._fields_}
 
 
-def imm_plan(n: int, k: int, eps: float) -> dict:
-    p = _ImmPlan()
-    _check(lib().im_imm_plan(n, k, eps, C.byref(p)), "im_imm_plan")
-    return {f: getattr(p, f) for f, _ in _ImmPlan._fields_}
+class ImmPlan:
+    """The library's IMM schedule for (n, k, eps) and its round decisions."""
+
+    def __init__(self, n: int, k: int, eps: float):
+        self.n = n
+        self.p = _ImmPlan()
+        _check(lib().im_imm_plan(n, k, eps, C.byref(self.p)), "im_imm_plan")
+
+    def __getitem__(self, key):
+        return getattr(self.p, key)
+
+    def round(self, x: int, theta_x: int, coverage: int):
+        """(stop, lb) after martingale round x (im_imm_round)."""
+        stop, lb = C.c_int32(), C.c_double()
+        _check(lib().im_imm_round(C.byref(self.p), self.n, x, theta_x, coverage, C.byref(stop),
+                                  C.byref(lb)), "im_imm_round")
+        return bool(stop.value), lb.value
+
+    def theta(self, lb: float) -> int:
+        t = C.c_int64()
+        _check(lib().im_imm_theta(C.byref(self.p), lb, C.byref(t)), "im_imm_theta")
+        return int(t.value)
+
+
+def imm_plan(n: int, k: int, eps: float) -> ImmPlan:
+    return ImmPlan(n, k, eps)
+
+
+def scratch_bytes(stream=None) -> int:
+    """Device bytes of library scratch held for the stream."""
+    b = C.c_size_t()
+    _check(lib().im_scratch_bytes(_stream(stream), C.byref(b)), "im_scratch_bytes")
+    return int(b.value)
 
 
 def sample_into(g: Graph, seed: int, stream_tag: int, first: int, count: int,

@@ -18,7 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libim.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["runtime.hip", "ingest.hip", "sample.hip", "incidence.hip", "greedy.hip",
-           "stream.hip", "offline.hip", "solve.hip", "batch.hip"]
+           "stream.hip", "offline.hip", "influence.hip",
+           "solve.hip", "batch.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -261,6 +261,10 @@ enum Slot {
   kSlotBatchInc,
   kSlotIncPairs,
   kSlotOffline,
+  kSlotForward,
+  kSlotOpim,
+  kSlotOpimIncOff,
+  kSlotOpimInc,
   kSlotCount
 };
 

@@ -44,6 +44,9 @@ struct CoverArgs {
   int64_t recount_min;
 };
 
+// Destroys the calling thread's captured cover graphs (im_release).
+void release_cover_graphs();
+
 // Enqueues the whole greedy (2k + 2 launches, plus one per early pick of a
 // one-partition cover).  gains must be zeroed first.
 int launch_cover(CoverArgs& A, hipStream_t s);

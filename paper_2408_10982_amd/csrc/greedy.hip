@@ -17,8 +17,10 @@
 // over the full universe of samples, and a covered sample only decrements the
 // members of the partition that covered it (Alg. 4, local greedy step; Sec. 3.4 S3).
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -549,39 +551,137 @@ __global__ void k_pos_of(int32_t n, const int32_t* __restrict__ order,
   if (pos < n) pos_of[order[pos]] = (int32_t)pos;
 }
 
-// k picks = 2k small launches; kernel boundaries make each pass's writes
-// visible device-wide (one cache flush per launch rather than per wave).
+// The launch sequence of one cover: init, then per pick argmax + apply (+ a
+// recount for a heavy early pick), then finish.  Kernel boundaries make each
+// pass's writes visible device-wide (one cache flush per launch rather than
+// per wave).
+struct CoverPlan {
+  unsigned init_blocks, arg_blocks, apply_blocks, agg_blocks, recount_blocks, finish_blocks;
+  bool can_recount;
+};
+
+static void enqueue_cover(const CoverArgs& A, const CoverPlan& P, hipStream_t s) {
+  k_cover_init<<<dim3(P.init_blocks), dim3(kGBlock), 0, s>>>(A);
+  for (int it = 0; it < A.k; ++it) {
+    k_cover_argmax<<<dim3(P.arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
+    if (P.can_recount)
+      k_cover_apply_one<<<dim3(P.agg_blocks), dim3(kAggBlock), 0, s>>>(A, it);
+    else
+      k_cover_apply<<<dim3(P.apply_blocks), dim3(kApplyBlock), 0, s>>>(A, it);
+    if (P.can_recount && it < kRecountPicks)
+      k_cover_recount<<<dim3(P.recount_blocks), dim3(kRecountBlock), 0, s>>>(A, it);
+  }
+  k_cover_finish<<<dim3(P.finish_blocks), dim3(256), 0, s>>>(A);
+}
+
+// Captured form: the sequence is recorded on a private stream of the calling
+// thread into a hipGraph, instantiated once per launch shape (k, grids, form)
+// and afterwards updated in place with the new arguments, then launched on
+// the caller's stream as one submission.  Handles are plain values (no
+// destructor runs HIP at thread or process exit); im_release destroys the
+// calling thread's executables.
+namespace {
+struct PlanKey {
+  int dev, k, m;
+  unsigned init_blocks, arg_blocks, apply_blocks, agg_blocks, recount_blocks, finish_blocks;
+  bool can_recount;
+  bool operator<(const PlanKey& o) const {
+    return std::tie(dev, k, m, init_blocks, arg_blocks, apply_blocks, agg_blocks, recount_blocks,
+                    finish_blocks, can_recount) <
+           std::tie(o.dev, o.k, o.m, o.init_blocks, o.arg_blocks, o.apply_blocks, o.agg_blocks,
+                    o.recount_blocks, o.finish_blocks, o.can_recount);
+  }
+};
+thread_local std::map<PlanKey, hipGraphExec_t>* t_execs = nullptr;
+thread_local hipStream_t t_capture[64] = {};
+}  // namespace
+
+void release_cover_graphs() {
+  if (!t_execs) return;
+  for (auto& kv : *t_execs) (void)hipGraphExecDestroy(kv.second);
+  t_execs->clear();
+}
+
+static int launch_captured(const CoverArgs& A, const CoverPlan& P, int dev, hipStream_t s) {
+  if (dev < 0 || dev >= 64) return IM_EDEVICE;
+  if (!t_capture[dev]) IM_HIP(hipStreamCreateWithFlags(&t_capture[dev], hipStreamNonBlocking));
+  const hipStream_t cap = t_capture[dev];
+  IM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  enqueue_cover(A, P, cap);
+  const hipError_t le = hipGetLastError();
+  hipGraph_t graph = nullptr;
+  const hipError_t ee = hipStreamEndCapture(cap, &graph);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_error(le != hipSuccess ? le : ee, "capture of the cover launches");
+    return IM_EDEVICE;
+  }
+  if (!t_execs) t_execs = new std::map<PlanKey, hipGraphExec_t>();
+  const PlanKey key{dev, A.k, A.m, P.init_blocks, P.arg_blocks, P.apply_blocks, P.agg_blocks,
+                    P.recount_blocks, P.finish_blocks, P.can_recount};
+  auto it = t_execs->find(key);
+  if (it != t_execs->end()) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult ur;
+    if (hipGraphExecUpdate(it->second, graph, &err_node, &ur) != hipSuccess ||
+        ur != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(it->second);
+      t_execs->erase(it);
+      it = t_execs->end();
+    }
+  }
+  if (it == t_execs->end()) {
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      set_error(ie, "hipGraphInstantiate(cover)");
+      return IM_EDEVICE;
+    }
+    it = t_execs->emplace(key, ex).first;
+  }
+  (void)hipGraphDestroy(graph);
+  IM_HIP(hipGraphLaunch(it->second, s));
+  return IM_OK;
+}
+
+// k picks: 2k + 2 launches (plus a recount per heavy early pick), enqueued
+// directly or as one captured graph (IM_TUNE_GRAPH).
 int launch_cover(CoverArgs& A, hipStream_t s) {
   DeviceInfo di;
   IM_TRY(device_info(&di));
-  const int64_t init_blocks = std::min<int64_t>(
+  CoverPlan P;
+  P.init_blocks = (unsigned)std::min<int64_t>(
       std::max<int64_t>(((int64_t)A.n + kGBlock - 1) / kGBlock, 1), (int64_t)di.num_cus * 4);
-  k_cover_init<<<dim3((unsigned)init_blocks), dim3(kGBlock), 0, s>>>(A);
-  IM_HIP(hipGetLastError());
-  const unsigned arg_blocks = (unsigned)std::max<int64_t>(((int64_t)A.n + kArgTile - 1) / kArgTile, 1);
-  const unsigned apply_blocks = (unsigned)di.num_cus * 4;
-  const unsigned agg_blocks = (unsigned)(di.num_cus * tune(IM_TUNE_APPLY_BLOCKS));
+  P.arg_blocks = (unsigned)std::max<int64_t>(((int64_t)A.n + kArgTile - 1) / kArgTile, 1);
+  P.apply_blocks = (unsigned)di.num_cus * 4;
+  P.agg_blocks = (unsigned)(di.num_cus * tune(IM_TUNE_APPLY_BLOCKS));
+  P.recount_blocks = (unsigned)di.num_cus * 8;
+  P.finish_blocks = (unsigned)((A.m + 255) / 256);
   // A plain one-partition cover rebuilds all counts after one of its first
   // kRecountPicks picks if that pick covers at least count / 64 samples (at
   // 2^20 weighted-cascade sets the first pick newly covers 41 K samples
   // holding 12 M members, the second 7 K holding 0.9 M; a recount is one pass
   // over the covering subsets, 0.1 ms); the decision is taken on the device
   // from the pick's gain.  Its other picks use the aggregated apply.
-  const bool can_recount = A.m == 1 && !A.order && !A.pos_of && !A.sbase && !A.local_ids;
-  A.recount_min = can_recount ? std::max<int64_t>(1, A.count / 64) : 0;
-  for (int it = 0; it < A.k; ++it) {
-    k_cover_argmax<<<dim3(arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
-    if (can_recount)
-      k_cover_apply_one<<<dim3(agg_blocks), dim3(kAggBlock), 0, s>>>(A, it);
-    else
-      k_cover_apply<<<dim3(apply_blocks), dim3(kApplyBlock), 0, s>>>(A, it);
-    if (can_recount && it < kRecountPicks)
-      k_cover_recount<<<dim3((unsigned)di.num_cus * 8), dim3(kRecountBlock), 0, s>>>(A, it);
+  P.can_recount = A.m == 1 && !A.order && !A.pos_of && !A.sbase && !A.local_ids;
+  A.recount_min = P.can_recount ? std::max<int64_t>(1, A.count / 64) : 0;
+  bool graph = tune(IM_TUNE_GRAPH) != 0;
+  if (graph) {  // a stream the caller is capturing gets the launches themselves
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    IM_HIP(hipStreamIsCapturing(s, &cs));
+    graph = cs == hipStreamCaptureStatusNone;
+  }
+  int rc = IM_OK;
+  if (graph) {
+    rc = launch_captured(A, P, di.device, s);
+  } else {
+    enqueue_cover(A, P, s);
+    if (hipGetLastError() != hipSuccess) rc = IM_EDEVICE;
   }
   A.recount_min = 0;
-  k_cover_finish<<<dim3((unsigned)((A.m + 255) / 256)), dim3(256), 0, s>>>(A);
-  IM_HIP(hipGetLastError());
-  return IM_OK;
+  return rc;
 }
 
 }  // namespace im

@@ -6,6 +6,7 @@
 #include <tuple>
 
 #include "common.h"
+#include "cover.h"
 
 namespace im {
 
@@ -192,11 +193,11 @@ int exclusive_scan_u32_to_i64(const uint32_t* in, int64_t n, int64_t* out, hipSt
 }
 
 namespace {
-constexpr int kTuneKeys = 6;
-constexpr int64_t kTuneDefault[kTuneKeys] = {5, 0, 1, 256, 7, 16};
-constexpr int64_t kTuneMin[kTuneKeys] = {1, 0, 1, 0, 1, 1};
-constexpr int64_t kTuneMax[kTuneKeys] = {64, 2, 16, (int64_t)1 << 40, 32, 4096};
-std::atomic<int64_t> g_tune[kTuneKeys] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+constexpr int kTuneKeys = 7;
+constexpr int64_t kTuneDefault[kTuneKeys] = {5, 0, 1, 256, 7, 16, 0};
+constexpr int64_t kTuneMin[kTuneKeys] = {1, 0, 1, 0, 1, 1, 0};
+constexpr int64_t kTuneMax[kTuneKeys] = {64, 2, 16, (int64_t)1 << 40, 32, 4096, 1};
+std::atomic<int64_t> g_tune[kTuneKeys] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 }  // namespace
 
 int64_t tune(im_tune_key key) {
@@ -225,10 +226,24 @@ const char* im_version(void) { return "im-mi355x 0.1 (gfx950)"; }
 
 const char* im_last_error(void) { return im::g_last_error.c_str(); }
 
+int im_scratch_bytes(void* stream, size_t* bytes) {
+  if (!bytes) return IM_EINVAL;
+  int dev = 0;
+  IM_HIP(hipGetDevice(&dev));
+  size_t b = 0;
+  std::lock_guard<std::mutex> lk(im::g_mu);
+  for (const auto& kv : im::g_scratch)
+    if (std::get<0>(kv.first) == dev && std::get<1>(kv.first) == (uintptr_t)stream)
+      b += kv.second.bytes;
+  *bytes = b;
+  return IM_OK;
+}
+
 int im_release(void) {
   int dev = 0;
   IM_HIP(hipGetDevice(&dev));
   IM_HIP(hipDeviceSynchronize());
+  im::release_cover_graphs();
   std::lock_guard<std::mutex> lk(im::g_mu);
   for (auto it = im::g_scratch.begin(); it != im::g_scratch.end();) {
     if (std::get<0>(it->first) == dev) {

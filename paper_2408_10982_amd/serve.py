@@ -7,14 +7,15 @@ device-resident RRR pools and continuous batching.
   function of its ids, the prefix [0, theta) of a pool is exactly what fresh
   sampling of theta sets returns, so a query answered from pools has the same
   seeds as the same query answered alone (im_solve), bit for bit.
-* solve_pooled() runs IMM (Alg. 1, greedy selector) over pool prefixes with
-  the library's own fp64 schedule (im_imm_plan) and the same decision
-  expressions as im_solve.
+* solve_pooled() runs IMM (Alg. 1, greedy selector) over pool prefixes; the
+  schedule and every round decision come from the library (im_imm_plan,
+  im_imm_round, im_imm_theta), the same calls im_solve makes.
 * Server runs queries in S slots.  Each slot is a thread with its own HIP
   stream (the library keeps scratch per stream and releases the GIL inside
   its calls), so the work of queries admitted together overlaps on the GPU.
   A query is admitted when a slot is free and its HBM footprint estimate fits
-  the budget; others wait in arrival order.
+  what the budget leaves after the resident bytes (pools and the library's
+  per-stream scratch, both measured); others wait in arrival order.
 Every step on the device is a library kernel; this module schedules them.
 """
 from __future__ import annotations
@@ -120,11 +121,9 @@ def _select(n: int, pref: _Prefix, k: int, stream):
 
 def solve_pooled(graph: B.Graph, pools: tuple, k: int, eps: float, stream) -> dict:
     """IMM with the standard greedy over resident pools (martingale pool on
-    stream 0, final pool on stream 1); same decisions as im_solve."""
+    stream 0, final pool on stream 1); the library takes every decision."""
     n = graph.n
     plan = B.imm_plan(n, k, eps)
-    nd = float(n)
-    eps_p = plan["eps_prime"]
     lb = 1.0
     th = plan["theta1"]
     rounds_run = 0
@@ -136,11 +135,11 @@ def solve_pooled(graph: B.Graph, pools: tuple, k: int, eps: float, stream) -> di
         _, cov = _select(n, _Prefix(off, mem, members), k, stream)
         rounds_run = i
         mart = th
-        x = nd / math.ldexp(1.0, i)
-        if nd * cov / th >= (1.0 + eps_p) * x:
-            lb = nd * cov / (th * (1.0 + eps_p))
+        stop, lbx = plan.round(i, th, cov)
+        if stop:
+            lb = lbx
             break
-    theta = math.ceil(plan["lambda_star"] / lb)
+    theta = plan.theta(lb)
     off, mem, members = pools[1].prefix(theta, stream)
     seeds, cov = _select(n, _Prefix(off, mem, members), k, stream)
     return {"seeds": seeds, "coverage": cov, "theta": theta, "rounds": rounds_run,
@@ -151,9 +150,9 @@ class Admission:
     """Arrival-order admission by slots and HBM footprint (host logic only).
 
     A query is admitted when fewer than `slots` queries are in flight and its
-    footprint fits what the in-flight queries leave of `budget`; the head of
-    the line is never overtaken.  A query larger than the whole budget is
-    admitted alone."""
+    footprint fits what the resident bytes (`held`: pools and library
+    scratch) and the in-flight queries leave of `budget`; the head of the
+    line is never overtaken.  A query larger than all that is admitted alone."""
 
     def __init__(self, slots: int, budget: int):
         self.slots = slots
@@ -166,11 +165,11 @@ class Admission:
     def push(self, item, footprint: int):
         self.waiting.append((item, footprint))
 
-    def pop(self):
+    def pop(self, held: int = 0):
         if not self.waiting or self.in_flight >= self.slots:
             return None
         item, fp = self.waiting[0]
-        if self.in_flight > 0 and self.reserved + fp > self.budget:
+        if self.in_flight > 0 and held + self.reserved + fp > self.budget:
             return None
         self.waiting.pop(0)
         self.in_flight += 1
@@ -240,14 +239,24 @@ class Server:
             return self.pools[name]
 
     def footprint(self, q: Query) -> int:
-        """HBM bytes a query needs beyond the pools: covering subsets and
-        greedy state for its largest prefix (estimated from earlier queries
-        on the same graph, else from the first martingale round)."""
+        """HBM bytes a query needs on top of the resident ones: covering
+        subsets and greedy state for its largest prefix, and the pool growth
+        and sampling staging an extension to that prefix can take (estimated
+        from earlier queries on the same graph, else from the first
+        martingale round)."""
         g = self.graphs[q.graph]
         plan = B.imm_plan(g.n, q.k, q.eps)
         theta = max(self.theta_seen.get(q.graph, 0), 8 * plan["theta1"])
         members = int(theta * self.avg_set.get(q.graph, 32.0))
-        return 8 * (g.n + 1) + 4 * members + 4 * g.n + theta + 16 * q.k
+        cover = 8 * (g.n + 1) + 4 * members + 4 * g.n + theta + 16 * q.k
+        extension = 2 * (8 * theta + 4 * members)  # staging arena + metadata, pool growth
+        return cover + extension
+
+    def resident_bytes(self) -> int:
+        """Pools plus the library's scratch on the slots' streams (measured)."""
+        with self.pools_lock:
+            pools = sum(p0.nbytes() + p1.nbytes() for p0, p1 in self.pools.values())
+        return pools + sum(B.scratch_bytes(s) for s in self.streams)
 
     @property
     def max_in_flight(self) -> int:
@@ -263,12 +272,12 @@ class Server:
         stream = self.streams[threading.current_thread().slot]
         while True:
             with self.cv:
-                got = self.adm.pop()
+                got = self.adm.pop(self.resident_bytes())
                 while got is None:
                     if self.stopping and not self.adm.waiting:
                         return
                     self.cv.wait()
-                    got = self.adm.pop()
+                    got = self.adm.pop(self.resident_bytes())
             q = got[0]
             q.admitted = time.perf_counter()
             g = self.graphs[q.graph]

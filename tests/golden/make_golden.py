@@ -48,23 +48,34 @@ def config2():
 
 
 CONFIG3_RUNS = (("1.0", "greediris", 1.0), ("0.125", "greediris", 0.125),
-                ("0.01", "greediris", 0.01), ("randgreedi", "randgreedi", 1.0))
+                ("0.01", "greediris", 0.01), ("randgreedi", "randgreedi", 1.0),
+                ("greedy", "greedy", 1.0))
+SELECTORS = {"greedy": O.SEL_GREEDY, "greediris": O.SEL_GREEDIRIS, "randgreedi": O.SEL_RANDGREEDI}
+# forward simulations per seed set (the paper's quality measure averages five)
+INFLUENCE_SIMS, INFLUENCE_SEED, INFLUENCE_STREAM = 5, 9003, 0
 
 
 def config3():
     """IMM + GreediRIS at alpha 1, 0.125 and 0.01 (T = 1: a 64-entry stream,
-    the first alpha at which truncation changes this workload's seeds), and
-    IMM + RandGreedi with the offline global step (Alg. 4)."""
+    the first alpha at which truncation changes this workload's seeds),
+    IMM + RandGreedi with the offline global step (Alg. 4), and IMM + the
+    standard greedy; each seed set's activated counts over five forward
+    simulations."""
     w = W.config(3)
     g = w.graph
     thr = O.thresholds(g.model, g.in_off, g.weight)
     out = {"workload": w.name, "k": w.k, "eps": w.eps, "m": w.m, "delta": w.delta,
-           "seed": w.seed, "part_seed": w.part_seed, "runs": {}}
+           "seed": w.seed, "part_seed": w.part_seed, "runs": {},
+           "influence_sims": INFLUENCE_SIMS, "influence_seed": INFLUENCE_SEED,
+           "influence_stream": INFLUENCE_STREAM}
     for key, sel, alpha in CONFIG3_RUNS:
         t0 = time.time()
         res = O.imm(g.model, g.in_off, g.in_src, thr, w.k, w.eps, seed=w.seed,
-                    selector=O.SEL_GREEDIRIS if sel == "greediris" else O.SEL_RANDGREEDI,
-                    m=w.m, delta=w.delta, alpha=alpha, part_seed=w.part_seed, lazy=True)
+                    selector=SELECTORS[sel], m=w.m, delta=w.delta, alpha=alpha,
+                    part_seed=w.part_seed, lazy=True)
+        res["influence"] = O.influence(g.model, g.in_off, g.in_src, thr, INFLUENCE_SEED,
+                                       INFLUENCE_STREAM, 0, INFLUENCE_SIMS,
+                                       res["seeds"]).tolist()
         res["seeds"] = res["seeds"].tolist()
         res["selector"] = sel
         res["alpha"] = alpha

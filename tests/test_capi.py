@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every symbol its header declares
 (no compute calls: these run without a GPU)."""
 import ctypes
+import math
 import os
 import re
 
@@ -72,16 +73,42 @@ def test_tune_knobs_validate_and_round_trip():
         assert L.im_tune_get(key, ctypes.byref(v)) == 0
         return v.value
 
-    defaults = {0: 5, 1: 0, 2: 1, 3: 256, 4: 7, 5: 16}
+    defaults = {0: 5, 1: 0, 2: 1, 3: 256, 4: 7, 5: 16, 6: 0}
     assert {k: get(k) for k in defaults} == defaults
     for key, bad in ((0, 0), (0, 65), (1, 3), (2, 0), (2, 17), (3, -2), (4, 0), (4, 33), (5, 0),
-                     (5, 4097), (6, 1), (-1, 1)):
+                     (5, 4097), (6, 2), (6, -2), (7, 1), (-1, 1)):
         assert L.im_tune_set(key, bad) == -1, (key, bad)
     assert {k: get(k) for k in defaults} == defaults
     assert L.im_tune_get(9, ctypes.byref(v)) == -1
     assert L.im_tune_get(0, None) == -1
-    for key, good in ((0, 12), (1, 2), (2, 4), (3, 0), (4, 2), (5, 64)):
+    for key, good in ((0, 12), (1, 2), (2, 4), (3, 0), (4, 2), (5, 64), (6, 1)):
         assert L.im_tune_set(key, good) == 0
         assert get(key) == good
         assert L.im_tune_set(key, -1) == 0
         assert get(key) == defaults[key]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_imm_host_schedule_and_decisions_match_oracle():
+    """The library's IMM schedule (im_imm_plan) equals the oracle's bit for
+    bit, and its round test / final theta (im_imm_round, im_imm_theta) take
+    the oracle's decisions: stop once n C / theta_x >= (1 + eps') n / 2^x.
+    Host only."""
+    import oracle as O
+    import paper_2408_10982_amd as im
+    for n, k, eps in ((4096, 16, 0.5), (1 << 20, 100, 0.13), (1 << 22, 100, 0.13), (500, 8, 0.4)):
+        p = im.imm_plan(n, k, eps)
+        o = O.imm_parameters(n, k, eps)
+        for key in ("ell", "eps_prime", "log_binom", "lambda_prime", "lambda_star", "theta1",
+                    "rounds"):
+            assert p[key] == o[key], (n, k, eps, key)
+        th = p["theta1"]
+        for x in range(1, 4):
+            for cov in (0, 1, th // 8, th // 3, th // 2, th):
+                stop, lb = p.round(x, th, cov)
+                need = (1.0 + o["eps_prime"]) * (n / 2.0 ** x)
+                assert stop == (n * cov / th >= need)
+                if stop:
+                    assert lb == n * cov / (th * (1.0 + o["eps_prime"]))
+                    assert p.theta(lb) == math.ceil(o["lambda_star"] / lb)
+            th *= 2

@@ -80,13 +80,14 @@ def c3(im):
     return w, im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
 
 
-@pytest.mark.parametrize("run", ["1.0", "0.125", "0.01", "randgreedi"])
+@pytest.mark.parametrize("run", ["1.0", "0.125", "0.01", "randgreedi", "greedy"])
 def test_config3_imm(im, c3, run):
     print("[case] config 3 full size %s" % run, flush=True)
     exp = _golden(3)
     e = exp["runs"][run]
     w, G = c3
-    sel = im.SEL_GREEDIRIS if e["selector"] == "greediris" else im.SEL_RANDGREEDI
+    sel = {"greediris": im.SEL_GREEDIRIS, "randgreedi": im.SEL_RANDGREEDI,
+           "greedy": im.SEL_GREEDY}[e["selector"]]
     got = im.solve(G, w.k, w.eps, selector=sel, m=w.m, delta=w.delta, alpha=e["alpha"],
                    seed=w.seed, part_seed=w.part_seed)
     assert got["theta"] == e["theta"]
@@ -99,6 +100,11 @@ def test_config3_imm(im, c3, run):
     assert got["global_won"] == e["global_won"]
     assert got["stream_len"] == e["stream_len"]
     assert got["sample_passes"] == got["sample_launches"] == got["rounds"] + 1
+    # the quality measure: activated counts of five forward simulations
+    F = im.prepare_forward(G)
+    cnt = im.influence(G, F, exp["influence_seed"], exp["influence_stream"], 0,
+                       exp["influence_sims"], got["seeds"])
+    assert cnt.cpu().tolist() == e["influence"]
     if run == "1.0":
         r = im.sample_rrr(G, w.seed, 1, 0, exp["final_theta"], capacity=exp["final_total"])
         assert r.total == exp["final_total"] == got["final_total"]

@@ -266,6 +266,40 @@ def test_greedy(im, name, count, k):
     assert int(_np(cov)[0]) == oc
 
 
+def test_cover_graph_replays_match_eager(im):
+    """The captured cover (IM_TUNE_GRAPH = 1) replayed several times, with
+    eager work and synchronisations between the replays and two collections
+    alternating (the cached executable is updated with new arguments), gives
+    the seeds, gains and coverage of the launches issued one by one -- for
+    the standard greedy, the RandGreedi local step and the offline step."""
+    _say("graph replays")
+    ga, gb = GRAPHS["rmat14_wc"](), GRAPHS["lt_small"]()
+    Ga, ra, ioa, ima, *_ = _pipeline(im, ga, 20000, 51)
+    Gb, rb, iob, imb, *_ = _pipeline(im, gb, 6000, 52)
+
+    def run_all():
+        out = [tuple(_np(x).tolist() for x in im.greedy_cover(ga.n, ra, ioa, ima, 30)),
+               tuple(_np(x).tolist() for x in im.greedy_cover(gb.n, rb, iob, imb, 20))]
+        part, ls, lg, lc, lv = im.randgreedi(gb.n, rb, iob, imb, 12, 8, part_seed=5)
+        out.append(tuple(_np(x).tolist() for x in (ls, lg, lc, lv)))
+        fo = im.greedi_offline(gb.n, rb, iob, imb, ls, lc, lv, 12, 1.0)
+        out.append(tuple(_np(x).tolist() for x in fo))
+        return out
+
+    try:
+        im.tune_set(im.TUNE_GRAPH, 0)
+        ref = run_all()
+        im.tune_set(im.TUNE_GRAPH, 1)
+        for rep in range(4):
+            got = run_all()
+            assert got == ref, rep
+            torch.cuda.synchronize()
+            im.sample_rrr(Ga, 77 + rep, 0, 0, 500)  # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        im.tune_set(im.TUNE_GRAPH, -1)
+
+
 @pytest.mark.parametrize("name,count,k,m", [("ic_dense", 2000, 10, 4), ("lt_small", 6000, 20, 8),
                                             ("rmat12", 16384, 16, 64), ("ic_sparse", 3000, 5, 1)])
 def test_randgreedi(im, name, count, k, m):
@@ -380,6 +414,27 @@ def test_greedi_offline(im, name, count, k, m, alpha):
     assert int(_np(cov)[0]) == fc
 
 
+@pytest.mark.parametrize("name,seeds,nsims", [
+    ("ic_sparse", [1, 2, 3], 64), ("ic_dense", [0, 50, 100, 150], 64), ("ic_p1", [7], 8),
+    ("lt_small", [4, 9, 400], 64), ("lt_chain", [0], 4), ("rmat12", list(range(0, 4096, 256)), 40),
+    ("rmat14_wc", [5, 99, 1000, 8000], 24), ("ic_sparse", [], 3), ("lt_small", [3, 3, 3], 17)])
+def test_influence(im, name, seeds, nsims):
+    """Forward simulations: every simulation's activated count equals the
+    oracle's (same live-edge world, keyed by simulation id), across more than
+    one batch of simulations and with duplicate or no seeds."""
+    _say("influence", name, len(seeds), nsims)
+    g = GRAPHS[name]()
+    G = _prep(im, g)
+    F = im.prepare_forward(G)
+    got = _np(im.influence(G, F, 61, 2, 5, nsims, seeds))
+    exp = O.influence(g.model, g.in_off, g.in_src, _oracle_thr(g), 61, 2, 5, nsims, seeds)
+    assert np.array_equal(got, exp), (got[:8], exp[:8])
+    # the out-edge view is a regrouping of the in-edges
+    oe = np.sort(_np(F.out_eid)[:g.num_edges])
+    assert np.array_equal(oe, np.arange(g.num_edges))
+    assert np.array_equal(_np(F.edge_dst)[:g.num_edges], np.repeat(np.arange(g.n), np.diff(g.in_off)))
+
+
 @pytest.mark.parametrize("name,k,eps,selector", [
     ("ic_sparse", 5, 0.5, O.SEL_GREEDY), ("lt_small", 8, 0.4, O.SEL_GREEDIRIS),
     ("rmat12", 16, 0.5, O.SEL_GREEDY), ("rmat12", 16, 0.5, O.SEL_GREEDIRIS),
@@ -399,6 +454,28 @@ def test_solve_imm(im, name, k, eps, selector):
     assert got["coverage"] == exp["coverage"]
     assert got["global_won"] == exp["global_won"] and got["bucket"] == exp["bucket"]
     assert got["stream_len"] == exp["stream_len"]
+
+
+@pytest.mark.parametrize("name,k,eps,selector,cap", [
+    ("ic_sparse", 5, 0.3, O.SEL_GREEDY, 1 << 20), ("lt_small", 8, 0.2, O.SEL_GREEDIRIS, 1 << 20),
+    ("rmat12", 16, 0.1, O.SEL_GREEDY, 1 << 16), ("rmat12", 16, 0.1, O.SEL_GREEDIRIS, 1 << 16),
+    ("rmat14_wc", 20, 0.2, O.SEL_RANDGREEDI, 1 << 18)])
+def test_opim(im, name, k, eps, selector, cap):
+    """OPIM rounds: the same halves, seeds, coverages on R1 and R2, upper
+    bound, rounds and (bit for bit, the same fp64 operations) guarantee."""
+    _say("opim", name, k, eps, selector, cap)
+    g = GRAPHS[name]()
+    G = _prep(im, g)
+    kw = dict(selector=selector, m=8, delta=0.077, alpha=0.5, seed=3005, part_seed=4005)
+    fail = 1.0 / g.n
+    got = im.opim(G, k, eps, fail, cap, **kw)
+    exp = O.opim(g.model, g.in_off, g.in_src, _oracle_thr(g), k, eps, fail=fail, theta_cap=cap,
+                 **kw)
+    for key in ("rounds", "theta", "cover1", "cover2", "upper1", "i_max", "nsel"):
+        assert got[key] == exp[key], key
+    for key in ("lower", "upper", "guarantee", "theta_max"):
+        assert got[key] == exp[key], key
+    assert got["seeds"] == exp["seeds"].tolist()
 
 
 @pytest.mark.parametrize("form", ["auto", "dense", "tiled_slices"])

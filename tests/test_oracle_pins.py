@@ -811,3 +811,168 @@ def test_imm_randgreedi_final_choice():
     assert res["coverage"] == max(gc, int(lv.max()))
     assert res["global_won"] == int(gc >= lv.max())
     assert res["stream_len"] == int(lc.sum())
+
+
+# ------------------------------------------- forward influence (quality measure)
+def test_influence_p1_is_forward_reachability():
+    """p = 1: every world is the whole graph, so each count is the number of
+    vertices reachable from the seeds (breadth-first search, textbook)."""
+    g = W.random_small_graph(300, 700, seed=11)
+    thr = O.ic_thresholds(np.ones(g.num_edges, np.float32))
+    fwd = sp.csr_matrix((np.ones(g.num_edges), (g.in_src, np.repeat(np.arange(g.n),
+                                                                     np.diff(g.in_off)))),
+                        shape=(g.n, g.n))
+    for seeds in ([0], [5, 17, 200], [3, 3, 3]):
+        reach = set()
+        for s in seeds:
+            reach |= set(breadth_first_order(fwd, s, directed=True,
+                                             return_predecessors=False).tolist())
+        c = O.influence(O.IC, g.in_off, g.in_src, thr, 9, 0, 0, 20, seeds)
+        assert np.all(c == len(reach))
+
+
+def test_influence_p0_and_zero_weights_are_the_seeds():
+    g = W.random_small_graph(80, 400, seed=12)
+    thr0 = O.ic_thresholds(np.zeros(g.num_edges, np.float32))
+    assert np.all(O.influence(O.IC, g.in_off, g.in_src, thr0, 1, 0, 0, 50, [4, 9, 9]) == 2)
+    c0 = O.lt_thresholds(g.in_off, np.zeros(g.num_edges, np.float32))
+    assert np.all(O.influence(O.LT, g.in_off, g.in_src, c0, 1, 0, 0, 50, [4, 9, 11]) == 3)
+
+
+def _exact_sigma_ic(n, edges, q, S):
+    total = 0.0
+    m = len(edges)
+    for mask in range(1 << m):
+        pr = 1.0
+        live = []
+        for j in range(m):
+            if mask >> j & 1:
+                pr *= q[j]
+                live.append(edges[j])
+            else:
+                pr *= 1 - q[j]
+        reach = set()
+        for s in S:
+            reach |= _forward_reach(n, live, s)
+        total += pr * len(reach)
+    return total
+
+
+def _exact_sigma_lt(n, edges, w, S):
+    ins = [[] for _ in range(n)]
+    for j, (u, v) in enumerate(edges):
+        ins[v].append(j)
+    choices = [[(j, w[j]) for j in ins[v]] + [(None, max(0.0, 1.0 - sum(w[j] for j in ins[v])))]
+               for v in range(n)]
+    total = 0.0
+    for combo in itertools.product(*choices):
+        pr = 1.0
+        live = []
+        for (j, pj) in combo:
+            pr *= pj
+            if j is not None:
+                live.append(edges[j])
+        if pr == 0:
+            continue
+        reach = set()
+        for s in S:
+            reach |= _forward_reach(n, live, s)
+        total += pr * len(reach)
+    return total
+
+
+@pytest.mark.parametrize("S", [[0], [2, 4], [1, 3, 5]])
+def test_influence_mean_matches_exact_sigma(S):
+    """The mean count over many simulations equals sigma(S) computed exactly
+    over all live-edge worlds (IC: 2^10 worlds; LT: every vertex's choice)."""
+    n = 6
+    g = W.tiny_graph(n, TINY_EDGES, TINY_P)
+    thr = O.ic_thresholds(g.weight)
+    q = O.ic_thresholds(np.array(TINY_P, np.float32)).astype(np.float64) / 2.0 ** 32
+    N = 60000
+    c = O.influence(O.IC, g.in_off, g.in_src, thr, 31, 0, 0, N, S)
+    mu = _exact_sigma_ic(n, TINY_EDGES, list(q), S)
+    assert abs(c.mean() - mu) < 5 * c.std() / math.sqrt(N) + 1e-9, (c.mean(), mu)
+    w = [x * 0.45 for x in TINY_P]  # in-weights of every vertex sum below 1
+    gl = W.tiny_graph(n, TINY_EDGES, w, model=W.LT)
+    cl = O.lt_thresholds(gl.in_off, gl.weight)
+    wq = [math.floor(np.float32(x) * 2.0 ** 32) / 2.0 ** 32 for x in w]
+    c = O.influence(O.LT, gl.in_off, gl.in_src, cl, 32, 0, 0, N, S)
+    mu = _exact_sigma_lt(n, TINY_EDGES, wq, S)
+    assert abs(c.mean() - mu) < 5 * c.std() / math.sqrt(N) + 1e-9, (c.mean(), mu)
+
+
+@pytest.mark.parametrize("model", [O.IC, O.LT])
+def test_influence_agrees_with_reverse_sampling(model):
+    """sigma(S) two ways on one graph: forward simulation, and n times the
+    fraction of RRR sets that S hits (the RIS estimator of Sec. 2.1)."""
+    g = W.random_small_graph(2000, 12000, seed=40 + model, model=model, p_hi=0.25)
+    thr = O.thresholds(model, g.in_off, g.weight)
+    S = [1, 77, 400, 1234, 1999]
+    N = 20000
+    c = O.influence(model, g.in_off, g.in_src, thr, 51, 0, 0, N, S)
+    theta = 200000
+    r = O.sample(model, g.in_off, g.in_src, thr, 52, 0, 0, theta)
+    io, im = O.incidence(g.n, r)
+    ris = g.n * O.coverage(g.n, theta, io, im, S) / theta
+    p = O.coverage(g.n, theta, io, im, S) / theta
+    sd = math.sqrt(c.var() / N + (g.n ** 2) * p * (1 - p) / theta)
+    assert abs(c.mean() - ris) < 5 * sd, (c.mean(), ris, sd)
+
+
+# ------------------------------------------- OPIM (instance-wise guarantee)
+def test_opim_round_quantities_against_brute_force():
+    """On a tiny graph: the upper bound U on R1 is at least the best k-subset's
+    coverage of R1 (brute force over all k-subsets) and at least C_R1(S*);
+    C_R2(S*) is the coverage of the returned seeds on the stream-1 half."""
+    g = W.random_small_graph(14, 40, seed=71, p_hi=0.4)
+    thr = O.ic_thresholds(g.weight)
+    for k in (1, 2, 3):
+        res = O.opim(O.IC, g.in_off, g.in_src, thr, k, 0.4, seed=8, fail=0.1, theta_cap=4096)
+        th = res["theta"]
+        r1 = O.sample(O.IC, g.in_off, g.in_src, thr, 8, 0, 0, th)
+        r2 = O.sample(O.IC, g.in_off, g.in_src, thr, 8, 1, 0, th)
+        io1, im1 = O.incidence(g.n, r1)
+        io2, im2 = O.incidence(g.n, r2)
+        best = max(O.coverage(g.n, th, io1, im1, list(S))
+                   for S in itertools.combinations(range(g.n), k))
+        assert res["cover1"] <= best <= res["upper1"]
+        assert res["cover1"] == O.coverage(g.n, th, io1, im1, res["seeds"])
+        assert res["cover2"] == O.coverage(g.n, th, io2, im2, res["seeds"])
+        assert 2 * th >= 4096 or res["rounds"] == res["i_max"] or \
+            res["guarantee"] >= 1 - 1 / math.e - 0.4
+
+
+def test_opim_bounds_hold_against_exact_influence():
+    """The lower bound on sigma(S*) and the upper bound on sigma(OPT) bracket
+    the exact values (every live-edge world enumerated) in nearly every run;
+    the bounds hold with probability 1 - fail per run (fail = 0.05 here)."""
+    n = 6
+    g = W.tiny_graph(n, TINY_EDGES, TINY_P)
+    thr = O.ic_thresholds(g.weight)
+    q = list(O.ic_thresholds(np.array(TINY_P, np.float32)).astype(np.float64) / 2.0 ** 32)
+    k = 2
+    sig = {S: _exact_sigma_ic(n, TINY_EDGES, q, list(S))
+           for S in itertools.combinations(range(n), k)}
+    opt = max(sig.values())
+    bad_lo = bad_up = 0
+    runs = 40
+    for seed in range(runs):
+        res = O.opim(O.IC, g.in_off, g.in_src, thr, k, 0.05, seed=100 + seed, fail=0.05,
+                     theta_cap=1 << 16)
+        S = tuple(sorted(int(x) for x in res["seeds"]))
+        bad_lo += res["lower"] > sig[S] + 1e-9
+        bad_up += res["upper"] < opt - 1e-9
+        assert 0.5 < res["guarantee"] <= 1.0 + 1e-12  # the bounds are near (within 1/2)
+    assert bad_lo <= 2 and bad_up <= 2, (bad_lo, bad_up)
+
+
+def test_opim_schedule():
+    """theta_0 = ceil(theta_max eps^2 k / n) and the rounds double it."""
+    g = W.random_small_graph(500, 3000, seed=72, p_hi=0.2)
+    thr = O.ic_thresholds(g.weight)
+    res = O.opim(O.IC, g.in_off, g.in_src, thr, 5, 0.2, seed=9, fail=1 / 500,
+                 theta_cap=1 << 30)
+    t0 = math.ceil(res["theta_max"] * 0.2 * 0.2 * 5 / 500)
+    assert res["theta"] == t0 * 2 ** (res["rounds"] - 1)
+    assert res["i_max"] == max(1, math.ceil(math.log2(res["theta_max"] / t0)))

@@ -38,3 +38,15 @@ def test_admission_refuses_over_budget_and_keeps_order():
     a.release(5)
     assert a.pop() == ("huge", 500)    # alone it is admitted
     assert a.in_flight == 1 and a.reserved == 500
+
+
+def test_admission_counts_resident_bytes():
+    """Resident bytes (pools, library scratch) come off the budget before the
+    in-flight queries' footprints; the first query is admitted regardless."""
+    A = _admission()(slots=4, budget=100)
+    for j in range(3):
+        A.push(j, 30)
+    assert A.pop(held=60)[0] == 0          # alone: admitted whatever it needs
+    assert A.pop(held=60) is None          # 60 + 30 + 30 > 100
+    assert A.pop(held=30)[0] == 1          # 30 + 30 + 30 <= 100
+    assert A.pop(held=30) is None
