@@ -135,8 +135,8 @@ __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
 
 // Pick `it`, step 2: record the picks, cover their covering subsets, and
 // decrement the counts of the members of every newly covered sample.  Each
-// wavefront takes 64 consecutive entries of the picks' subsets; a newly
-// covered sample is then walked by the whole wavefront.
+// wavefront takes kApplyEntries consecutive entries of the picks' subsets; a
+// newly covered sample is then walked by the whole wavefront.
 // One of the first kRecountPicks picks whose gain reaches recount_min
 // (one-partition covers only): mark its samples covered and zero every count;
 // k_cover_recount, launched for exactly those picks, then rebuilds them.
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   __shared__ unsigned long long pbest[kMaxParts];
   __shared__ int64_t pre[kMaxParts + 1];
   __shared__ int64_t part_scan[kApplyBlock / kWave + 1];
+  __shared__ int64_t ppos[kMaxParts];  // count position of each partition's pick
   const int tid = threadIdx.x, lane = lane_id();
   const int m = A.m;
   const unsigned long long* gm = A.gmax + (int64_t)it * m;
@@ -159,9 +160,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   if (tid < m) {
     const unsigned long long b = it < part_k(A, tid) ? gm[tid] : 0ull;
     pbest[tid] = b;
+    ppos[tid] = -1;
     if (key_count(b) > 0) {
       const uint32_t v = key_vertex(b);
       sz = A.inc_off[v + 1] - A.inc_off[v];
+      ppos[tid] = A.pos_of ? (int64_t)A.pos_of[v] : (int64_t)v;
     }
   }
   {  // pre = exclusive prefix of the sizes, pre[m] = total
@@ -188,6 +191,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
     if (blockIdx.x == 0 && tid == 0) *A.done = 1;
     return;
   }
+  const bool decrement = !recount_pick(A, it);
   if (blockIdx.x == 0) {
     for (int p = tid; p < m; p += kApplyBlock) {
       const unsigned long long b = pbest[p];
@@ -195,11 +199,14 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
         const int64_t v = key_vertex(b);
         A.seeds[part_out(A, p) + it] = (int32_t)(A.local_ids ? v - part_lo(A, p) : v);
         A.gains[part_out(A, p) + it] = (int64_t)key_count(b);
+        // every sample of S(v*) ends up covered, so the pick's own count
+        // becomes 0; it is stored once here and skipped in the member walks
+        // (one atomic per covered sample on that one address otherwise)
+        if (decrement) A.cnt[ppos[p]] = 0u;
       }
     }
   }
   const int64_t gtid = (int64_t)blockIdx.x * kApplyBlock + tid;
-  const bool decrement = !recount_pick(A, it);
   if (!decrement)
     for (int64_t pos = gtid; pos < A.n; pos += (int64_t)gridDim.x * kApplyBlock) A.cnt[pos] = 0u;
   const int64_t nchunks = (tot + kApplyEntries - 1) / kApplyEntries;
@@ -236,12 +243,14 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
         fresh = true;
       }
     }
+    // each newly covered sample is walked by the whole wavefront
     unsigned long long todo = decrement ? __ballot(fresh) : 0ull;
     while (todo) {
       const int src = __ffsll(todo) - 1;
       todo &= todo - 1;
       const int s_p = __shfl(p, src, kWave);
       const int64_t lo_p = part_lo(A, s_p), hi_p = part_hi(A, s_p);
+      const int64_t skip = ppos[s_p];
       const int64_t a = __shfl(ma, src, kWave), b = __shfl(mb, src, kWave);
       for (int64_t t = a + lane; t < b; t += kWave) {
         const int32_t u = A.mem[t];
@@ -249,7 +258,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
         // one-byte partition id is checked before the position lookup
         if (A.part && A.part[u] != (uint8_t)s_p) continue;
         const int64_t pos = A.local_ids ? lo_p + u : (A.pos_of ? A.pos_of[u] : u);
-        if (pos >= lo_p && pos < hi_p) atomicSub(&A.cnt[pos], 1u);
+        if (pos >= lo_p && pos < hi_p && pos != skip) atomicSub(&A.cnt[pos], 1u);
       }
     }
   }
