@@ -148,8 +148,8 @@ def main():
     try:
         run(args, im, W, torch)
     finally:
-        # hand the library's scratch back while the runtime is whole, so that
-        # exit-time teardown frees no HIP memory of ours
+        # drop the workspaces and captured graphs while the runtime is whole,
+        # so that exit-time teardown frees no HIP memory of ours
         torch.cuda.synchronize()
         im.release()
 
@@ -197,7 +197,7 @@ def run_plain(args, w, G, im, torch, steps=None, warmup=None):
 
     # Step i runs on stream i mod S: its covering subsets and greedy (a chain
     # of small launches) overlap the next step's sampling.  Every step does
-    # all of its work; each stream has its own library scratch.
+    # all of its work; each stream has its own workspace.
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream()
                                                for _ in range(max(args.streams, 1) - 1)]
 
@@ -480,8 +480,8 @@ def bench_serve(args, im, W, torch):
             done = S.run_arrivals(server, qs)
         finally:
             server.close()
-        # each rate starts with empty pools; the slots' streams (and the
-        # library scratch they hold) carry over, as in a long-running server
+        # each rate starts with empty pools; the slots' streams (and their
+        # workspaces) carry over, as in a long-running server
         pool_stats, max_in_flight = server.pool_stats(), server.max_in_flight
         resident = server.resident_bytes()
         del server
@@ -592,6 +592,9 @@ def bench_imm(args, w, G, im, W, torch):
         "counts": {"sampled_sets": res["sampled_sets"], "sampled_sum_rrr": res["sampled_total"],
                    "probes": res["sampled_examined"], "edges_taken": res["sampled_live"],
                    "sample_launches": res["sample_launches"], "sample_passes": passes},
+        # the caller-owned device workspace the solves ran in (pools, staging,
+        # covering subsets, cover state), as the binding grew it
+        "workspace_bytes": im.workspace_bytes(),
         "roofline": roofline,
     }
     if not args.no_extra:

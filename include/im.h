@@ -13,16 +13,30 @@
  * Conventions shared by every entry point
  *  - Pointers marked [device] are HIP device memory owned by the caller;
  *    pointers marked [host] are host memory owned by the caller.  The library
- *    never frees caller memory.  It keeps private device scratch per
- *    (device, stream) that grows on demand and is released by im_release().
+ *    never frees caller memory and allocates no device memory of its own
+ *    (the one fixed array of im_greedy_cover_static aside).
+ *  - Workspace: every entry point that needs device memory beyond its inputs
+ *    and outputs takes (ws, ws_bytes), a [device] region owned by the caller
+ *    and used on `stream` only for the duration of the call (its contents
+ *    are undefined before and after).  im_workspace_size() gives the bytes to
+ *    pass for a problem shape.  A workspace shorter than the call's minimum
+ *    returns IM_ENOMEM before any device work or output write; one that runs
+ *    out part way (the data-dependent sizes of the IMM and OPIM pools and of
+ *    the sampling arena) returns IM_ENOMEM with outputs undefined.  In both
+ *    cases im_workspace_need() then gives the bytes that call needed at
+ *    least; repeating it with that many bytes gets further or succeeds.
+ *    After any call it also gives the bytes that call could have used.
+ *    Larger workspaces let sampling stage more sets per pass and run more
+ *    large-set workers, and let the covering subsets be built in one round;
+ *    results never depend on the size.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *    on it; entry points that return a host-side value (sizes, counts)
  *    synchronise that stream before returning, and say so.
  *  - Errors are status codes; nothing is thrown across the ABI.  IM_EINVAL is
  *    returned before any device work is enqueued or any output is written.
  *  - Calls that share one stream run in order.  Calls on different streams
- *    use different scratch and may overlap; they must not write the same
- *    caller buffers.
+ *    may overlap when they are given different workspaces; they must not
+ *    write the same caller buffers.
  *  - All arithmetic on the device is integer.  The only floating-point steps
  *    (IMM sample-size bounds, streaming bucket thresholds) run on the host in
  *    fp64 with a fixed operation order.
@@ -49,8 +63,9 @@ typedef enum {
   IM_OK = 0,
   IM_EINVAL = -1,  /* invalid argument; nothing was enqueued or written */
   IM_ERANGE = -2,  /* output capacity too small; the needed size is returned */
-  IM_ENOMEM = -3,  /* device scratch allocation failed, or a sampling arena stayed
-                      short after its retries (the detail is in im_last_error()) */
+  IM_ENOMEM = -3,  /* the workspace is too small (im_workspace_need() gives the bytes
+                      needed), or a sampling arena stayed short after its retries
+                      (the detail is in im_last_error()) */
   IM_EDEVICE = -4  /* a HIP call failed (the HIP error is in im_last_error()) */
 } im_status;
 
@@ -95,16 +110,62 @@ typedef struct {
 
 /* Library version string. */
 const char* im_version(void);
-/* Text of the calling thread's last error: a failed HIP call, scratch
- * allocation or arena ("" if none). */
+/* Text of the calling thread's last error: a failed HIP call, a short
+ * workspace or arena ("" if none). */
 const char* im_last_error(void);
-/* Device bytes of private scratch the library holds for `stream` on the
- * current device (host query; grows with the largest call made on it). */
-int im_scratch_bytes(void* stream, size_t* bytes);
-/* Releases the library's device scratch for every stream of the current
- * device, and the calling thread's captured cover graphs.  The caller must
- * ensure no call is in flight. */
+/* Waits for the current device and releases the calling thread's captured
+ * cover graphs (IM_TUNE_GRAPH).  The caller must ensure no call is in flight. */
 int im_release(void);
+
+/* Entry points whose workspace im_workspace_size() reports. */
+typedef enum {
+  IM_WS_PREPARE_GRAPH = 0,  /* im_prepare_graph */
+  IM_WS_SAMPLE = 1,         /* im_sample_rrr: n, model, count, total = capacity */
+  IM_WS_INCIDENCE = 2,      /* im_build_incidence: n, total */
+  IM_WS_GREEDY = 3,         /* im_greedy_cover: n, count, k */
+  IM_WS_RANDGREEDI = 4,     /* im_randgreedi: n, count, k, m */
+  IM_WS_STREAM = 5,         /* im_stream_cover: count, k, m, delta (alpha = 1 bound) */
+  IM_WS_OFFLINE = 6,        /* im_greedi_offline: n, count, k, m */
+  IM_WS_FORWARD = 7,        /* im_prepare_forward: n */
+  IM_WS_INFLUENCE = 8,      /* im_influence: n, count = nsims, k = nseeds */
+  IM_WS_SOLVE = 9,          /* im_solve: n, model, count = theta, total, k, selector, m, delta */
+  IM_WS_OPIM = 10,          /* im_opim: as im_solve, count = samples per half */
+  IM_WS_BATCH = 11          /* im_solve_batch: ntasks, n = sum of vertices, count = sum of
+                               theta, total, k = largest k, model (LT if any) */
+} im_ws_op;
+
+/* A problem shape for im_workspace_size.  Fields an op does not list are
+ * ignored.  total is the sum of set sizes; where it is not known yet (IMM,
+ * OPIM, batches) an estimate, e.g. count times the mean set size of a small
+ * sample.  full = 1 asks for room for the fastest launch shapes (every
+ * large-set worker up to 16 GiB, one round of covering subsets); 0 for the
+ * least the op runs in.  num_cus: compute units of the device the call will
+ * run on, or 0 for the current device. */
+typedef struct {
+  int32_t n;
+  int32_t model;
+  int64_t count;
+  int64_t total;
+  int32_t k;
+  int32_t m;
+  double delta;
+  int32_t selector;
+  int32_t ntasks;
+  int32_t full;
+  int32_t num_cus;
+} im_ws_shape;
+
+/* Bytes of workspace to pass for `op` on `shape` (host only, except that
+ * num_cus = 0 queries the current device).  For im_solve, im_opim and
+ * im_solve_batch it is an estimate from shape->total; the calls report
+ * IM_ENOMEM and im_workspace_need() when it falls short. */
+int im_workspace_size(int32_t op, const im_ws_shape* shape, size_t* bytes);
+/* For the calling thread's last call with a workspace: *need = the bytes it
+ * needed at least if it returned IM_ENOMEM for its workspace (else 0);
+ * *want = the bytes that would have let it take its fastest launch shapes
+ * (at least what it used: more large-set workers, one round of covering
+ * subsets).  Either pointer may be NULL, not both. */
+int im_workspace_need(size_t* need, size_t* want);
 
 /*
  * Launch-shape knobs (the batched and served paths' tile choices; the
@@ -173,14 +234,15 @@ int im_tune_get(int32_t key, int64_t* value);
  *      sqrt(2)), odd atanh series to s^19), so results are reproducible
  *      bit for bit.
  * in_off [device] n+1; in_src [device] E; weight [device] E fp32;
- * thr [device] round_up(E,4); skip [device] n fp64 or NULL (ignored for LT).  Synchronises `stream`; returns IM_EINVAL if
+ * thr [device] round_up(E,4); skip [device] n fp64 or NULL (ignored for LT);
+ * ws [device] 256 bytes.  Synchronises `stream`; returns IM_EINVAL if
  * in_off is not a valid CSR offset array (nothing else is then read), or if a
  * source id is outside [0,n), or a weight is NaN, negative, infinite, or (IC)
  * above 1 (thr is then partly written and must not be used).
  */
 int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off, const int32_t* in_src,
                      const float* weight, int32_t model, uint32_t* thr, double* skip,
-                     void* stream);
+                     void* ws, size_t ws_bytes, void* stream);
 
 /*
  * RRR sampling (Def. 2.3 and Sec. 2.1; Alg. 1 Sample, Alg. 3 sampling step).
@@ -197,11 +259,14 @@ int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off, const 
  * *total [host] receives the sum of set sizes.  If it exceeds capacity the
  * call returns IM_ERANGE, off is written, mem is left undefined, and a repeat
  * with capacity >= *total returns bit-identical output.  stats [host] may be
- * NULL.  first + count <= 2^32.  Synchronises `stream`.
+ * NULL.  first + count <= 2^32.  The workspace stages the sets before they
+ * are placed (about 4.5 bytes per member of capacity plus 16 per set) and
+ * holds the large-set workers (4.125 n bytes each, at least one).
+ * Synchronises `stream`.
  */
 int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t first,
                   int64_t count, int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
-                  im_sample_stats* stats, void* stream);
+                  im_sample_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Covering subsets (Sec. 3.2; Alg. 3 per-vertex step): S(v) = {j : v in R(j)}
@@ -211,16 +276,18 @@ int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t
  * [0, n) (the caller's contract; sets from im_sample_rrr do).  Collections of
  * at most 256 members per vertex (the environment variable
  * IM_INCIDENCE_DENSE_RATIO changes that bound) are transposed through LDS
- * histograms: scratch holds 8 bytes per member, up to 40% of the free device
- * memory, and a larger collection is transposed in rounds of vertex-id ranges
- * (IM_INCIDENCE_PAIR_BUDGET, a member count, lowers that cap; the round split
- * synchronises `stream` once).  Denser collections over at most 4 x 32768
- * vertex ids count and place members in LDS tiles of 32768 ids (scratch 8
- * bytes per vertex; IM_INCIDENCE_DENSE_TILES=0 turns that form off); wider
- * ones take one global atomic per member and pass.  Otherwise asynchronous.
+ * histograms: the workspace holds 8 bytes per member of one round (at least
+ * 2^24 members), and a collection larger than the workspace allows is
+ * transposed in rounds of vertex-id ranges (IM_INCIDENCE_PAIR_BUDGET, a member
+ * count, lowers that cap; the round split synchronises `stream` once).
+ * Denser collections over at most 4 x 32768 vertex ids count and place
+ * members in LDS tiles of 32768 ids (8 bytes of workspace per vertex;
+ * IM_INCIDENCE_DENSE_TILES=0 turns that form off); wider ones take one global
+ * atomic per member and pass.  Otherwise asynchronous.
  */
 int im_build_incidence(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
-                       int64_t total, int64_t* inc_off, int32_t* inc_mem, void* stream);
+                       int64_t total, int64_t* inc_off, int32_t* inc_mem, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /*
  * Standard greedy max-k-cover (Sec. 3.2): k times take the vertex v of largest
@@ -229,18 +296,18 @@ int im_build_incidence(int32_t n, int64_t count, const int64_t* off, const int32
  * Inputs from im_sample_rrr / im_build_incidence (total = off[count]).
  * seeds [device] k int32 (entries past nsel set to -1); gains [device] k int64
  * (0 past nsel); nsel [device] 1 int32; coverage [device] 1 int64 = C(S).
- * Asynchronous.
+ * Workspace: 4n + count + 8k bytes and change.  Asynchronous.
  */
 int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                     int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,
                     int32_t* seeds, int64_t* gains, int32_t* nsel, int64_t* coverage,
-                    void* stream);
+                    void* ws, size_t ws_bytes, void* stream);
 
 /*
- * im_greedy_cover without any device allocation, for callers that cannot
- * allocate device memory: code under HIP stream capture, tight serving loops,
- * harnesses that forbid hipMalloc.  Same arguments, operation and outputs as
- * im_greedy_cover (bit-identical results).  Its scratch -- 64 + 8*round_up(k,8)
+ * im_greedy_cover without a workspace, for callers that cannot allocate
+ * device memory: code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments (no ws), operation and
+ * outputs as im_greedy_cover (bit-identical results).  Its scratch -- 64 + 8*round_up(k,8)
  * + 4n + count bytes: argmax keys, per-vertex counts, covered flags -- lives
  * in a fixed 64 MiB device array that each GPU the library runs on holds
  * until the process ends; a call needing more returns IM_ENOMEM (the sizes
@@ -263,12 +330,13 @@ int im_greedy_cover_static(int32_t n, int64_t count, const int64_t* off, const i
  * launch, recording all k picks.  part [device] n uint8 (written);
  * lseeds [device] m*k int32, row p = part p's picks in order, -1 past
  * lcount[p]; lgains [device] m*k int64; lcount [device] m int32;
- * lcover [device] m int64 = C(S_p).  1 <= m <= 256.  Asynchronous.
+ * lcover [device] m int64 = C(S_p).  1 <= m <= 256.  Workspace: 12n + m count
+ * + 8mk bytes and change.  Asynchronous.
  */
 int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                   int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,
                   int32_t m, uint64_t part_seed, uint8_t* part, int32_t* lseeds, int64_t* lgains,
-                  int32_t* lcount, int64_t* lcover, void* stream);
+                  int32_t* lcount, int64_t* lcover, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Streaming max-k-cover at the receiver (Alg. 5), truncation (Sec. 3.3.2) and
@@ -282,12 +350,15 @@ int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const int32_t* m
  *   lcover.
  * seeds [device] k int32 (-1 past nsel); nsel [device] 1; coverage [device] 1
  * int64; info [device] 4 int32 = {b*, B, global solution chosen (1/0), stream
- * length}.  0 < delta < 1/2, 0 < alpha <= 1.  Asynchronous.
+ * length}.  0 < delta < 1/2, 0 < alpha <= 1.  Workspace: the stream (20 bytes
+ * per item) and the buckets' seeds, plus B count / 8 bytes of bucket bitmaps
+ * when count exceeds what LDS holds (1,179,648 samples).  Asynchronous.
  */
 int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off, const int32_t* inc_mem,
                     int32_t k, int32_t m, const int32_t* lseeds, const int32_t* lcount,
                     const int64_t* lcover, double delta, double alpha, int32_t* seeds,
-                    int32_t* nsel, int64_t* coverage, int32_t* info, void* stream);
+                    int32_t* nsel, int64_t* coverage, int32_t* info, void* ws, size_t ws_bytes,
+                    void* stream);
 
 /*
  * RandGreedi's global step without streaming, the offline GreeDI aggregation
@@ -302,24 +373,28 @@ int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off, const int3
  * seeds [device] k int32 (-1 past nsel); nsel [device] 1; coverage [device] 1
  * int64; info [device] 4 int32 = {global solution chosen (1/0), vertices
  * gathered, |S_g|, best local partition}; gcover [device] 1 int64 = C(S_g),
- * or NULL.  0 < alpha <= 1, 1 <= m <= 256.  Reads lcount back to size the
- * launches (synchronises `stream` once); otherwise asynchronous.
+ * or NULL.  0 < alpha <= 1, 1 <= m <= 256.  Workspace: 4n + count + 8mk
+ * bytes and change.  Reads lcount back to size the launches (synchronises
+ * `stream` once); otherwise asynchronous.
  */
 int im_greedi_offline(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                       int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,
                       int32_t m, const int32_t* lseeds, const int32_t* lcount,
                       const int64_t* lcover, double alpha, int32_t* seeds, int32_t* nsel,
-                      int64_t* coverage, int32_t* info, int64_t* gcover, void* stream);
+                      int64_t* coverage, int32_t* info, int64_t* gcover, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /*
  * Forward view of a graph for influence simulation: the in-edge ids grouped
  * by source.  out_off [device] n+1 int64 (out_off[u] .. out_off[u+1] index
  * out_eid); out_eid [device] E int32, the in-edge ids e with in_src[e] = u
  * (order inside a source unspecified); edge_dst [device] E int32, the
- * vertex whose in-edge list holds e.  Synchronises `stream`.
+ * vertex whose in-edge list holds e.  Workspace: 8n bytes and change.
+ * Synchronises `stream`.
  */
 int im_prepare_forward(int32_t n, int64_t num_edges, const int32_t* in_off, const int32_t* in_src,
-                       int64_t* out_off, int32_t* out_eid, int32_t* edge_dst, void* stream);
+                       int64_t* out_off, int32_t* out_eid, int32_t* edge_dst, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /*
  * Forward Monte-Carlo influence of a seed set -- the paper's quality measure
@@ -335,12 +410,13 @@ int im_prepare_forward(int32_t n, int64_t num_edges, const int32_t* in_off, cons
  * count of simulations r = first .. first+nsims-1 of (seed, stream_tag).
  * seeds [host] nseeds ids in [0, n) (else IM_EINVAL).  out_off / out_eid /
  * edge_dst from im_prepare_forward on the same graph.  first + nsims <= 2^32.
- * Synchronises `stream` (once per batch of 16 levels of the search).
+ * Workspace: 16 simulations at a time, 16.125 n bytes each.  Synchronises
+ * `stream` (once per batch of 16 levels of the search).
  */
 int im_influence(const im_graph* g, const int64_t* out_off, const int32_t* out_eid,
                  const int32_t* edge_dst, uint64_t seed, uint32_t stream_tag, int64_t first,
-                 int64_t nsims, const int32_t* seeds, int32_t nseeds, int64_t* counts,
-                 void* stream);
+                 int64_t nsims, const int32_t* seeds, int32_t nseeds, int64_t* counts, void* ws,
+                 size_t ws_bytes, void* stream);
 
 /* IMM sample-size schedule (host values; see im_solve). */
 typedef struct {
@@ -418,10 +494,12 @@ typedef struct {
  * are selected on theta fresh samples of stream 1.  The selector is the
  * standard greedy, GreediRIS (im_randgreedi + im_stream_cover) or RandGreedi
  * with the offline global step (im_randgreedi + im_greedi_offline).
- * seeds [host] k int32; res [host].  Synchronises `stream`.
+ * seeds [host] k int32; res [host].  The sample pools live in the workspace
+ * (a pool, its covering subsets and the staging of its newest sets: about
+ * 20 bytes per member at the final theta; IM_WS_SOLVE).  Synchronises `stream`.
  */
 int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* opts,
-             int32_t* seeds, im_solve_result* res, void* stream);
+             int32_t* seeds, im_solve_result* res, void* ws, size_t ws_bytes, void* stream);
 
 /* Result of im_opim (host). */
 typedef struct {
@@ -458,10 +536,12 @@ typedef struct {
  * Stops when guarantee >= 1 - 1/e - eps, at round i_max, or once the two
  * halves together hold theta_cap samples or more (the paper's runs stop at
  * 2^20).  0 < eps < 1, 0 < fail < 1.  seeds [host] k int32 (-1 past nsel);
- * res [host].  opts->theta is ignored.  Synchronises `stream`.
+ * res [host].  opts->theta is ignored.  Both halves and their covering
+ * subsets live in the workspace (IM_WS_OPIM).  Synchronises `stream`.
  */
 int im_opim(const im_graph* g, int32_t k, double eps, double fail, int64_t theta_cap,
-            const im_solve_opts* opts, int32_t* seeds, im_opim_result* res, void* stream);
+            const im_solve_opts* opts, int32_t* seeds, im_opim_result* res, void* ws,
+            size_t ws_bytes, void* stream);
 
 /* One task of a batch: theta samples [0, theta) of (seed, stream_tag) on a
  * prepared graph, then the standard greedy with k picks. */
@@ -489,10 +569,13 @@ typedef struct {
  * tasks [host] ntasks; seeds [device] and gains [device] hold sum_t k_t
  * entries, task t's at offset sum_{u<t} k_u (-1 / 0 past its nsel);
  * nsel [device] ntasks int32; coverage [device] ntasks int64; stats [host]
- * may be NULL.  Tasks are processed 256 at a time.  Synchronises `stream`.
+ * may be NULL.  Tasks are processed 256 at a time, each group's sets,
+ * covering subsets and counts in the workspace (IM_WS_BATCH).  Synchronises
+ * `stream`.
  */
 int im_solve_batch(const im_task* tasks, int32_t ntasks, int32_t* seeds, int64_t* gains,
-                   int32_t* nsel, int64_t* coverage, im_batch_stats* stats, void* stream);
+                   int32_t* nsel, int64_t* coverage, im_batch_stats* stats, void* ws,
+                   size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -2,13 +2,18 @@
 
 Every step of the hot path runs in the library's HIP kernels; this module
 only turns torch tensors (device memory) and torch's current HIP stream into
-the plain pointers the C ABI takes, checks status codes, and sizes outputs.
+the plain pointers the C ABI takes, checks status codes, and sizes outputs
+and workspaces.  The library allocates no device memory: each call gets a
+workspace, a torch uint8 tensor kept per (device, stream) that grows when a
+call reports IM_ENOMEM with the bytes it needs (the call is then repeated;
+results never depend on the workspace size).
 If libim.so is missing the import fails: there is no CPU fallback.
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 from dataclasses import dataclass
 
 import torch
@@ -21,6 +26,8 @@ IC, LT = 0, 1
 SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
 (TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS,
  TUNE_LT_GRAB, TUNE_GRAPH) = 0, 1, 2, 3, 4, 5, 6
+(WS_PREPARE_GRAPH, WS_SAMPLE, WS_INCIDENCE, WS_GREEDY, WS_RANDGREEDI, WS_STREAM, WS_OFFLINE,
+ WS_FORWARD, WS_INFLUENCE, WS_SOLVE, WS_OPIM, WS_BATCH) = range(12)
 
 _STATUS = {IM_EINVAL: "IM_EINVAL", IM_ERANGE: "IM_ERANGE", IM_ENOMEM: "IM_ENOMEM",
            IM_EDEVICE: "IM_EDEVICE"}
@@ -30,7 +37,7 @@ EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_
            "im_build_incidence", "im_greedy_cover", "im_greedy_cover_static", "im_randgreedi", "im_stream_cover", "im_greedi_offline",
            "im_prepare_forward", "im_influence", "im_opim",
            "im_solve", "im_solve_batch", "im_imm_plan", "im_imm_round", "im_imm_theta",
-           "im_scratch_bytes", "im_tune_set", "im_tune_get")
+           "im_workspace_size", "im_workspace_need", "im_tune_set", "im_tune_get")
 
 
 class ImError(RuntimeError):
@@ -88,6 +95,13 @@ class _OpimResult(C.Structure):
                 ("global_won", C.c_int32)]
 
 
+class _WsShape(C.Structure):
+    _fields_ = [("n", C.c_int32), ("model", C.c_int32), ("count", C.c_int64),
+                ("total", C.c_int64), ("k", C.c_int32), ("m", C.c_int32), ("delta", C.c_double),
+                ("selector", C.c_int32), ("ntasks", C.c_int32), ("full", C.c_int32),
+                ("num_cus", C.c_int32)]
+
+
 class _Task(C.Structure):
     _fields_ = [("graph", _Graph), ("seed", C.c_uint64), ("stream_tag", C.c_uint32),
                 ("k", C.c_int32), ("theta", C.c_int64)]
@@ -115,29 +129,34 @@ def lib():
         L.im_version.restype = C.c_char_p
         L.im_last_error.restype = C.c_char_p
         L.im_release.argtypes = []
-        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P, P]
+        W = [P, C.c_size_t]  # (ws, ws_bytes)
+        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P] + W + [P]
         L.im_sample_rrr.argtypes = [C.POINTER(_Graph), U64, U32, I64, I64, P, P, I64,
-                                    C.POINTER(C.c_int64), C.POINTER(_Stats), P]
-        L.im_build_incidence.argtypes = [I32, I64, P, P, I64, P, P, P]
-        L.im_greedy_cover.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
+                                    C.POINTER(C.c_int64), C.POINTER(_Stats)] + W + [P]
+        L.im_build_incidence.argtypes = [I32, I64, P, P, I64, P, P] + W + [P]
+        L.im_greedy_cover.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P] + W + [P]
         L.im_greedy_cover_static.argtypes = [I32, I64, P, P, I64, P, P, I32, P, P, P, P, P]
-        L.im_randgreedi.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, U64, P, P, P, P, P, P]
-        L.im_stream_cover.argtypes = [I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P, P]
+        L.im_randgreedi.argtypes = ([I32, I64, P, P, I64, P, P, I32, I32, U64, P, P, P, P, P] +
+                                    W + [P])
+        L.im_stream_cover.argtypes = ([I32, I64, P, P, I32, I32, P, P, P, D, D, P, P, P, P] +
+                                      W + [P])
         L.im_opim.argtypes = [C.POINTER(_Graph), I32, D, D, I64, C.POINTER(_SolveOpts), P,
-                              C.POINTER(_OpimResult), P]
-        L.im_prepare_forward.argtypes = [I32, I64, P, P, P, P, P, P]
-        L.im_influence.argtypes = [C.POINTER(_Graph), P, P, P, U64, U32, I64, I64, P, I32, P, P]
-        L.im_greedi_offline.argtypes = [I32, I64, P, P, I64, P, P, I32, I32, P, P, P, D, P, P,
-                                        P, P, P, P]
+                              C.POINTER(_OpimResult)] + W + [P]
+        L.im_prepare_forward.argtypes = [I32, I64, P, P, P, P, P] + W + [P]
+        L.im_influence.argtypes = ([C.POINTER(_Graph), P, P, P, U64, U32, I64, I64, P, I32, P] +
+                                   W + [P])
+        L.im_greedi_offline.argtypes = ([I32, I64, P, P, I64, P, P, I32, I32, P, P, P, D, P, P,
+                                         P, P, P] + W + [P])
         L.im_solve.argtypes = [C.POINTER(_Graph), I32, D, C.POINTER(_SolveOpts), P,
-                               C.POINTER(_SolveResult), P]
-        L.im_solve_batch.argtypes = [C.POINTER(_Task), I32, P, P, P, P, C.POINTER(_BatchStats),
-                                     P]
+                               C.POINTER(_SolveResult)] + W + [P]
+        L.im_solve_batch.argtypes = ([C.POINTER(_Task), I32, P, P, P, P,
+                                      C.POINTER(_BatchStats)] + W + [P])
+        L.im_workspace_size.argtypes = [I32, C.POINTER(_WsShape), C.POINTER(C.c_size_t)]
+        L.im_workspace_need.argtypes = [C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         L.im_imm_plan.argtypes = [I32, I32, D, C.POINTER(_ImmPlan)]
         L.im_imm_round.argtypes = [C.POINTER(_ImmPlan), I32, I32, I64, I64,
                                    C.POINTER(C.c_int32), C.POINTER(C.c_double)]
         L.im_imm_theta.argtypes = [C.POINTER(_ImmPlan), D, C.POINTER(C.c_int64)]
-        L.im_scratch_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
         L.im_tune_set.argtypes = [I32, I64]
         L.im_tune_get.argtypes = [I32, C.POINTER(C.c_int64)]
         for f in EXPORTS[2:]:
@@ -159,6 +178,90 @@ def _ptr(t: torch.Tensor | None):
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ workspaces
+_WS: dict = {}            # (device index, stream handle) -> uint8 device tensor
+_WS_LOCK = threading.Lock()
+_WS_GRAIN = 2 << 20       # workspaces grow in whole 2 MiB steps
+_WS_TRIES = 8             # a call that keeps running short gives up after this many
+
+
+def workspace_size(op: int, n: int = 0, model: int = IC, count: int = 0, total: int = 0,
+                   k: int = 0, m: int = 0, delta: float = 0.0, selector: int = SEL_GREEDY,
+                   ntasks: int = 0, full: bool = False, num_cus: int = 0) -> int:
+    """Bytes of workspace the library asks for `op` (WS_*) on a shape (im_workspace_size)."""
+    sh = _WsShape(n, model, count, total, k, m, delta, selector, ntasks, int(full), num_cus)
+    b = C.c_size_t()
+    _check(lib().im_workspace_size(op, C.byref(sh), C.byref(b)), "im_workspace_size")
+    return int(b.value)
+
+
+def workspace_need():
+    """(need, want) of the calling thread's last call (im_workspace_need):
+    the bytes it needed at least if it ran short (else 0), and the bytes its
+    fastest launch shapes would have used."""
+    need, want = C.c_size_t(), C.c_size_t()
+    _check(lib().im_workspace_need(C.byref(need), C.byref(want)), "im_workspace_need")
+    return int(need.value), int(want.value)
+
+
+def _ws_tensor(s, want: int) -> torch.Tensor:
+    key = (s.device.index, s.cuda_stream)
+    with _WS_LOCK:
+        t = _WS.get(key)
+        if t is not None and t.numel() >= want:
+            return t
+    size = max(_WS_GRAIN, -(-want // _WS_GRAIN) * _WS_GRAIN)
+    # allocated on the stream that uses it, so that the caching allocator
+    # reuses the old block only after that stream's queued work
+    with torch.cuda.stream(s):
+        if t is not None:
+            with _WS_LOCK:
+                _WS.pop(key, None)
+            del t
+        t = torch.empty(size, dtype=torch.uint8, device=s.device)
+    with _WS_LOCK:
+        _WS[key] = t
+    return t
+
+
+def _call_ws(fn, where: str, args: tuple, stream=None, hint: int = 0, ok=(IM_OK,)) -> int:
+    """Calls an entry point with the stream's workspace, growing it and
+    calling again while the call reports a workspace shortfall.  A call that
+    could have used more (faster launch shapes) gets it from the next call
+    on the stream on."""
+    s = torch.cuda.current_stream() if stream is None else stream
+    size = hint
+    rc = IM_ENOMEM
+    for _ in range(_WS_TRIES):
+        ws = _ws_tensor(s, size)
+        rc = fn(*args, C.c_void_p(ws.data_ptr()), ws.numel(), C.c_void_p(s.cuda_stream))
+        need, want = workspace_need()
+        if rc != IM_ENOMEM:
+            if want > ws.numel():
+                _ws_tensor(s, want)
+            break
+        if need <= ws.numel():  # not a workspace shortfall
+            break
+        size = max(need + need // 4, want)
+    if rc not in ok:
+        _check(rc, where)
+    return rc
+
+
+def workspace_bytes(stream=None) -> int:
+    """Device bytes of the workspace held for the stream (0 if none yet)."""
+    s = torch.cuda.current_stream() if stream is None else stream
+    with _WS_LOCK:
+        t = _WS.get((s.device.index, s.cuda_stream))
+    return 0 if t is None else t.numel()
+
+
+def drop_workspaces():
+    """Forgets every cached workspace (their memory returns to torch's allocator)."""
+    with _WS_LOCK:
+        _WS.clear()
 
 
 def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
@@ -201,10 +304,9 @@ def prepare_graph(in_off, in_src, weight, model: int, device="cuda", stream=None
     thr = torch.empty(max((E + 3) // 4 * 4, 4), dtype=torch.int32, device=device)
     skip = (torch.empty(n, dtype=torch.float64, device=device)
             if model == IC and run_length else None)
-    st = lib().im_prepare_graph(n, E, _ptr(in_off), _ptr(in_src) if E else None,
-                                _ptr(weight) if E else None, model, _ptr(thr), _ptr(skip),
-                                _stream(stream))
-    _check(st, "im_prepare_graph")
+    _call_ws(lib().im_prepare_graph, "im_prepare_graph",
+             (n, E, _ptr(in_off), _ptr(in_src) if E else None, _ptr(weight) if E else None,
+              model, _ptr(thr), _ptr(skip)), stream)
     return Graph(n, E, model, in_off, in_src, thr, skip)
 
 
@@ -232,12 +334,13 @@ def sample_rrr(g: Graph, seed: int, stream_tag: int, first: int, count: int,
         mem = torch.empty(max(cap, 1), dtype=torch.int32, device=g.in_off.device)
         total = C.c_int64()
         stats = _Stats()
-        st = lib().im_sample_rrr(C.byref(gs), seed, stream_tag, first, count, _ptr(off),
-                                 _ptr(mem), cap, C.byref(total), C.byref(stats), _stream(stream))
+        hint = workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=count, total=cap)
+        st = _call_ws(lib().im_sample_rrr, "im_sample_rrr",
+                      (C.byref(gs), seed, stream_tag, first, count, _ptr(off), _ptr(mem), cap,
+                       C.byref(total), C.byref(stats)), stream, hint, ok=(IM_OK, IM_ERANGE))
         if st == IM_ERANGE:
             cap = int(total.value)
             continue
-        _check(st, "im_sample_rrr")
         sd = {f: getattr(stats, f) for f, _ in _Stats._fields_}
         return RRR(off, mem[:total.value], int(total.value), int(stats.examined),
                    int(stats.live), int(stats.large_sets), sd)
@@ -247,9 +350,9 @@ def sample_rrr(g: Graph, seed: int, stream_tag: int, first: int, count: int,
 def build_incidence(n: int, rrr: RRR, stream=None):
     inc_off = torch.empty(n + 1, dtype=torch.int64, device=rrr.off.device)
     inc_mem = torch.empty(max(rrr.total, 1), dtype=torch.int32, device=rrr.off.device)
-    st = lib().im_build_incidence(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
-                                  _ptr(inc_off), _ptr(inc_mem), _stream(stream))
-    _check(st, "im_build_incidence")
+    _call_ws(lib().im_build_incidence, "im_build_incidence",
+             (n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total, _ptr(inc_off),
+              _ptr(inc_mem)), stream, workspace_size(WS_INCIDENCE, n=n, total=rrr.total))
     return inc_off, inc_mem[:rrr.total]
 
 
@@ -260,16 +363,16 @@ def greedy_cover(n: int, rrr: RRR, inc_off, inc_mem, k: int, stream=None):
     gains = torch.empty(k, dtype=torch.int64, device=dev)
     nsel = torch.empty(1, dtype=torch.int32, device=dev)
     cov = torch.empty(1, dtype=torch.int64, device=dev)
-    st = lib().im_greedy_cover(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
-                               _ptr(inc_off), _ptr(inc_mem), k, _ptr(seeds), _ptr(gains),
-                               _ptr(nsel), _ptr(cov), _stream(stream))
-    _check(st, "im_greedy_cover")
+    _call_ws(lib().im_greedy_cover, "im_greedy_cover",
+             (n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total, _ptr(inc_off),
+              _ptr(inc_mem), k, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov)), stream,
+             workspace_size(WS_GREEDY, n=n, count=rrr.count, k=k))
     return seeds, gains, nsel, cov
 
 
 def greedy_cover_static(n: int, rrr: RRR, inc_off, inc_mem, k: int, stream=None):
     """im_greedy_cover_static: the same greedy with the library's fixed scratch
-    (no device allocation).  Returns (seeds, gains, nsel, coverage) device tensors."""
+    array (no workspace).  Returns (seeds, gains, nsel, coverage) device tensors."""
     dev = rrr.off.device
     seeds = torch.empty(k, dtype=torch.int32, device=dev)
     gains = torch.empty(k, dtype=torch.int64, device=dev)
@@ -292,10 +395,10 @@ def randgreedi(n: int, rrr: RRR, inc_off, inc_mem, k: int, m: int, part_seed: in
     lg = torch.empty((m, k), dtype=torch.int64, device=dev)
     lc = torch.empty(m, dtype=torch.int32, device=dev)
     lv = torch.empty(m, dtype=torch.int64, device=dev)
-    st = lib().im_randgreedi(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
-                             _ptr(inc_off), _ptr(inc_mem), k, m, part_seed, _ptr(part), _ptr(ls),
-                             _ptr(lg), _ptr(lc), _ptr(lv), _stream(stream))
-    _check(st, "im_randgreedi")
+    _call_ws(lib().im_randgreedi, "im_randgreedi",
+             (n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total, _ptr(inc_off),
+              _ptr(inc_mem), k, m, part_seed, _ptr(part), _ptr(ls), _ptr(lg), _ptr(lc),
+              _ptr(lv)), stream, workspace_size(WS_RANDGREEDI, n=n, count=rrr.count, k=k, m=m))
     return part, ls, lg, lc, lv
 
 
@@ -309,10 +412,12 @@ def stream_cover(n: int, count: int, inc_off, inc_mem, lseeds, lcount, lcover, k
     nsel = torch.empty(1, dtype=torch.int32, device=dev)
     cov = torch.empty(1, dtype=torch.int64, device=dev)
     info = torch.empty(4, dtype=torch.int32, device=dev)
-    st = lib().im_stream_cover(n, count, _ptr(inc_off), _ptr(inc_mem), k, m, _ptr(lseeds),
-                               _ptr(lcount), _ptr(lcover), delta, alpha, _ptr(seeds),
-                               _ptr(nsel), _ptr(cov), _ptr(info), _stream(stream))
-    _check(st, "im_stream_cover")
+    hint = (workspace_size(WS_STREAM, n=n, count=count, k=k, m=m, delta=delta)
+            if 0.0 < delta < 0.5 else 0)
+    _call_ws(lib().im_stream_cover, "im_stream_cover",
+             (n, count, _ptr(inc_off), _ptr(inc_mem), k, m, _ptr(lseeds), _ptr(lcount),
+              _ptr(lcover), delta, alpha, _ptr(seeds), _ptr(nsel), _ptr(cov), _ptr(info)),
+             stream, hint)
     return seeds, nsel, cov, info
 
 
@@ -328,11 +433,11 @@ def greedi_offline(n: int, rrr: RRR, inc_off, inc_mem, lseeds, lcount, lcover, k
     cov = torch.empty(1, dtype=torch.int64, device=dev)
     info = torch.empty(4, dtype=torch.int32, device=dev)
     gcov = torch.empty(1, dtype=torch.int64, device=dev)
-    st = lib().im_greedi_offline(n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total,
-                                 _ptr(inc_off), _ptr(inc_mem), k, m, _ptr(lseeds), _ptr(lcount),
-                                 _ptr(lcover), alpha, _ptr(seeds), _ptr(nsel), _ptr(cov),
-                                 _ptr(info), _ptr(gcov), _stream(stream))
-    _check(st, "im_greedi_offline")
+    _call_ws(lib().im_greedi_offline, "im_greedi_offline",
+             (n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total, _ptr(inc_off),
+              _ptr(inc_mem), k, m, _ptr(lseeds), _ptr(lcount), _ptr(lcover), alpha, _ptr(seeds),
+              _ptr(nsel), _ptr(cov), _ptr(info), _ptr(gcov)), stream,
+             workspace_size(WS_OFFLINE, n=n, count=rrr.count, k=k, m=m))
     return seeds, nsel, cov, info, gcov
 
 
@@ -349,10 +454,10 @@ def prepare_forward(g: Graph, stream=None) -> Forward:
     out_off = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
     out_eid = torch.empty(max(g.num_edges, 1), dtype=torch.int32, device=dev)
     edge_dst = torch.empty(max(g.num_edges, 1), dtype=torch.int32, device=dev)
-    st = lib().im_prepare_forward(g.n, g.num_edges, _ptr(g.in_off),
-                                  _ptr(g.in_src) if g.num_edges else None, _ptr(out_off),
-                                  _ptr(out_eid), _ptr(edge_dst), _stream(stream))
-    _check(st, "im_prepare_forward")
+    _call_ws(lib().im_prepare_forward, "im_prepare_forward",
+             (g.n, g.num_edges, _ptr(g.in_off), _ptr(g.in_src) if g.num_edges else None,
+              _ptr(out_off), _ptr(out_eid), _ptr(edge_dst)), stream,
+             workspace_size(WS_FORWARD, n=g.n))
     return Forward(out_off, out_eid, edge_dst)
 
 
@@ -364,10 +469,10 @@ def influence(g: Graph, fwd: Forward, seed: int, stream_tag: int, first: int, ns
     arr = (C.c_int32 * max(len(sd), 1))(*sd)
     counts = torch.empty(max(nsims, 1), dtype=torch.int64, device=g.in_off.device)
     gs = g.struct()
-    st = lib().im_influence(C.byref(gs), _ptr(fwd.out_off), _ptr(fwd.out_eid),
-                            _ptr(fwd.edge_dst), seed, stream_tag, first, nsims, arr, len(sd),
-                            _ptr(counts), _stream(stream))
-    _check(st, "im_influence")
+    _call_ws(lib().im_influence, "im_influence",
+             (C.byref(gs), _ptr(fwd.out_off), _ptr(fwd.out_eid), _ptr(fwd.edge_dst), seed,
+              stream_tag, first, nsims, arr, len(sd), _ptr(counts)), stream,
+             workspace_size(WS_INFLUENCE, n=g.n, count=nsims, k=len(sd)))
     return counts[:nsims]
 
 
@@ -378,8 +483,8 @@ def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,
     res = _SolveResult()
     seeds = (C.c_int32 * k)()
     gs = g.struct()
-    st = lib().im_solve(C.byref(gs), k, eps, C.byref(o), seeds, C.byref(res), _stream(stream))
-    _check(st, "im_solve")
+    _call_ws(lib().im_solve, "im_solve", (C.byref(gs), k, eps, C.byref(o), seeds, C.byref(res)),
+             stream)
     out = {f: getattr(res, f) for f, _ in _SolveResult._fields_}
     out["seeds"] = list(seeds)[:res.nsel]
     return out
@@ -393,9 +498,8 @@ def opim(g: Graph, k: int, eps: float, fail: float, theta_cap: int,
     res = _OpimResult()
     seeds = (C.c_int32 * k)()
     gs = g.struct()
-    st = lib().im_opim(C.byref(gs), k, eps, fail, theta_cap, C.byref(o), seeds, C.byref(res),
-                       _stream(stream))
-    _check(st, "im_opim")
+    _call_ws(lib().im_opim, "im_opim",
+             (C.byref(gs), k, eps, fail, theta_cap, C.byref(o), seeds, C.byref(res)), stream)
     out = {f: getattr(res, f) for f, _ in _OpimResult._fields_}
     out["seeds"] = list(seeds)[:res.nsel]
     return out
@@ -417,9 +521,8 @@ def solve_batch(tasks, stream=None):
     nsel = torch.empty(nt, dtype=torch.int32, device=dev)
     cov = torch.empty(nt, dtype=torch.int64, device=dev)
     st = _BatchStats()
-    rc = lib().im_solve_batch(arr, nt, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov),
-                              C.byref(st), _stream(stream))
-    _check(rc, "im_solve_batch")
+    _call_ws(lib().im_solve_batch, "im_solve_batch",
+             (arr, nt, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov), C.byref(st)), stream)
     s_h, g_h, n_h, c_h = (seeds.cpu().tolist(), gains.cpu().tolist(), nsel.cpu().tolist(),
                           cov.cpu().tolist())
     out, o = [], 0
@@ -458,13 +561,6 @@ def imm_plan(n: int, k: int, eps: float) -> ImmPlan:
     return ImmPlan(n, k, eps)
 
 
-def scratch_bytes(stream=None) -> int:
-    """Device bytes of library scratch held for the stream."""
-    b = C.c_size_t()
-    _check(lib().im_scratch_bytes(_stream(stream), C.byref(b)), "im_scratch_bytes")
-    return int(b.value)
-
-
 def sample_into(g: Graph, seed: int, stream_tag: int, first: int, count: int,
                 off: torch.Tensor, mem: torch.Tensor, stream=None):
     """Samples sets [first, first+count) into caller tensors: off (count+1
@@ -472,16 +568,20 @@ def sample_into(g: Graph, seed: int, stream_tag: int, first: int, count: int,
     Returns the member total, or -total if mem was too small (IM_ERANGE)."""
     gs = g.struct()
     total = C.c_int64()
-    st = lib().im_sample_rrr(C.byref(gs), seed, stream_tag, first, count, _ptr(off), _ptr(mem),
-                             mem.numel(), C.byref(total), None, _stream(stream))
+    hint = workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=count, total=mem.numel())
+    st = _call_ws(lib().im_sample_rrr, "im_sample_rrr",
+                  (C.byref(gs), seed, stream_tag, first, count, _ptr(off), _ptr(mem),
+                   mem.numel(), C.byref(total), None), stream, hint, ok=(IM_OK, IM_ERANGE))
     if st == IM_ERANGE:
         return -int(total.value)
-    _check(st, "im_sample_rrr")
     return int(total.value)
 
 
 def release():
+    """Waits for the device, drops the cached workspaces and the library's
+    captured cover graphs."""
     _check(lib().im_release(), "im_release")
+    drop_workspaces()
 
 
 def tune_set(key: int, value: int):

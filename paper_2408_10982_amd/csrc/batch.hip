@@ -20,6 +20,13 @@
 
 namespace im {
 
+// tables | off | inc_off | cnt | covered | gmax | done
+static size_t batch_bytes(int32_t nt, int64_t S, int64_t V, int32_t max_k) {
+  const size_t tab = (size_t)(nt + 1) * 16 + (size_t)nt * 12 + 256;
+  return ws_align(tab + (size_t)(S + 1) * 8 + (size_t)(V + 1) * 8 + (size_t)V * 4 + (size_t)S +
+                  (size_t)max_k * nt * 8 + 64 + 8 * 64);
+}
+
 static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32_t* seeds,
                        int64_t* gains, int32_t* nsel, int64_t* coverage, im_batch_stats* st,
                        hipStream_t s) {
@@ -46,12 +53,8 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   sb[nt] = S;
   vb[nt] = V;
   if (S >= ((int64_t)1 << 32) || V >= ((int64_t)1 << 31)) return IM_EINVAL;
-  // tables | off | inc_off | cnt | covered | gmax | done
-  const size_t tab = (size_t)(nt + 1) * 16 + (size_t)nt * 12 + 256;
-  const size_t bytes = tab + (size_t)(S + 1) * 8 + (size_t)(V + 1) * 8 + (size_t)V * 4 +
-                       (size_t)S + (size_t)max_k * nt * 8 + 64 + 8 * 64;
   void* p = nullptr;
-  IM_TRY(scratch(s, kSlotBatch, bytes, &p));
+  IM_TRY(scratch(s, kSlotBatch, batch_bytes(nt, S, V, max_k), &p));
   char* c = (char*)p;
   auto take = [&](size_t b) {
     char* r = c;
@@ -81,27 +84,17 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
       for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[j]);
     }
   } guard{ev};
-  // sampling (members land in a grow-only scratch buffer)
-  static thread_local int64_t last_total = 0;
-  int64_t cap = std::max<int64_t>(last_total, S * 4);
-  int64_t total = 0;
-  im_sample_stats ss{};
+  // sampling: the sets are staged in the arena, then gathered into a member
+  // buffer of exactly their total
+  ArenaRun R;
   IM_HIP(hipEventRecord(ev[0], s));
-  int32_t* mem = nullptr;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    void* mp = nullptr;
-    IM_TRY(scratch(s, kSlotBatchMem, (size_t)std::max<int64_t>(cap, 1) * 4, &mp));
-    mem = (int32_t*)mp;
-    const int rc = sample_tasks(td.data(), nt, S, max_n, off, mem, cap, &total, &ss, true, s);
-    if (rc == IM_ERANGE) {
-      cap = total;
-      continue;
-    }
-    IM_TRY(rc);
-    break;
-  }
-  if (total > cap) return IM_ENOMEM;
-  last_total = total;
+  IM_TRY(sample_to_arena(td.data(), nt, S, max_n, off, 0, 0, true, false, &R, s));
+  const int64_t total = R.total;
+  void* mp = nullptr;
+  IM_TRY(scratch(s, kSlotBatchMem, (size_t)std::max<int64_t>(total, 1) * 4, &mp));
+  int32_t* mem = (int32_t*)mp;
+  IM_TRY(gather_arena(R, off, mem, nullptr, s));
+  release_sampling();
   IM_HIP(hipEventRecord(ev[1], s));
   // covering subsets of every task, by global vertex position
   void* ip = nullptr;
@@ -144,8 +137,8 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
     IM_HIP(hipEventElapsedTime(&c2, ev[2], ev[3]));
     st->sets += S;
     st->total += total;
-    st->examined += ss.examined;
-    st->live += ss.live;
+    st->examined += R.examined;
+    st->live += R.live;
     st->ms_sample += a;
     st->ms_incidence += b;
     st->ms_cover += c2;
@@ -153,18 +146,42 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   return IM_OK;
 }
 
+size_t ws_batch(int num_cus, int32_t nt, int64_t S, int64_t V, int64_t total, int32_t max_n,
+                int32_t max_k, int32_t model, bool full) {
+  if (nt <= 0) return 0;
+  const size_t own = batch_bytes(nt, S, V, max_k) + ws_align((size_t)std::max<int64_t>(total, 1) * 4);
+  const size_t inc = ws_align((size_t)std::max<int64_t>(total, 1) * 4) +
+                     ws_incidence((int32_t)std::min<int64_t>(V, INT32_MAX), total, nt, full);
+  return own + std::max(ws_sample(num_cus, S, total, max_n, model, full), inc);
+}
+
 }  // namespace im
 
 extern "C" int im_solve_batch(const im_task* tasks, int32_t ntasks, int32_t* seeds,
                               int64_t* gains, int32_t* nsel, int64_t* coverage,
-                              im_batch_stats* stats, void* stream) {
+                              im_batch_stats* stats, void* ws, size_t ws_bytes, void* stream) {
   using namespace im;
   if (!tasks || ntasks <= 0 || !seeds || !gains || !nsel || !coverage) return IM_EINVAL;
+  int64_t S = 0, V = 0;
+  int32_t max_n = 1, max_k = 1, model = IM_IC;
   for (int32_t t = 0; t < ntasks; ++t) {
     const im_task& q = tasks[t];
     if (!graph_ok(&q.graph) || q.k <= 0 || q.theta < 0 || q.theta >= ((int64_t)1 << 32))
       return IM_EINVAL;
+    if (t < kMaxParts) {  // the first chunk: a lower bound for the whole call
+      S += q.theta;
+      V += q.graph.n;
+    }
+    max_n = std::max(max_n, q.graph.n);
+    max_k = std::max(max_k, q.k);
+    if (q.graph.model == IM_LT) model = IM_LT;
   }
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_batch(di.num_cus, std::min(ntasks, kMaxParts), S, V, S, max_n, max_k, model,
+                            false)))
+    return IM_ENOMEM;
   if (stats) *stats = im_batch_stats{};
   hipStream_t s = (hipStream_t)stream;
   int64_t out = 0;

@@ -232,11 +232,59 @@ void set_error_text(const std::string& text);
     if (_s != IM_OK) return _s;      \
   } while (0)
 
-// Grow-only scratch buffers kept per (device, stream, slot).  Returns IM_OK
-// and sets *ptr; contents are undefined on return.
+// The caller's workspace for the current entry point (see WsScope).
+// scratch: a region of at least `bytes` for `slot`, kept while later requests
+// fit it; contents undefined.  IM_ENOMEM when the workspace is exhausted (the
+// shortfall is kept for im_workspace_need).  Regions are used on the call's
+// stream only.
 int scratch(hipStream_t stream, int slot, size_t bytes, void** ptr);
-// Same, and reports whether the buffer was (re)allocated by this call.
-int scratch_fresh(hipStream_t stream, int slot, size_t bytes, void** ptr, bool* fresh);
+// Same, keeping the first `keep` bytes of the slot's previous region (grown
+// in place when it is the topmost, else copied on `stream`).
+int scratch_grow(hipStream_t stream, int slot, size_t keep, size_t bytes, void** ptr);
+// Returns the slot's region to the workspace (its contents are then dead).
+void scratch_release(int slot);
+// Bytes of workspace above the highest region carved so far.
+size_t scratch_room();
+// The largest region one request could get now (a free hole or the room).
+size_t scratch_largest();
+// Records that the call needs `more` bytes beyond its highest region.
+void scratch_need(size_t more);
+// Records that `more` bytes beyond the highest region would have let the
+// call take a faster launch shape (reported by im_workspace_need).
+void scratch_wish(size_t more);
+// `bytes` rounded up to the workspace's alignment (256).
+size_t ws_align(size_t bytes);
+
+// Workspace bytes of the entry points (the op of im_workspace_size);
+// sampling, covering subsets and the cover kernels declare theirs beside
+// their launches.
+size_t ws_forward(int32_t n);
+size_t ws_influence(int32_t n, int64_t nsims, int32_t nseeds);
+size_t ws_solve(int num_cus, int32_t n, int32_t model, int64_t count, int64_t total, int32_t k,
+                int32_t selector, int32_t m, double delta, bool full);
+size_t ws_opim(int num_cus, int32_t n, int32_t model, int64_t count, int64_t total, int32_t k,
+               int32_t selector, int32_t m, double delta, bool full);
+size_t ws_batch(int num_cus, int32_t nt, int64_t S, int64_t V, int64_t total, int32_t max_n,
+                int32_t max_k, int32_t model, bool full);
+
+// Installs the caller's workspace (ws, ws_bytes) for an entry point, unless
+// an outer entry point of this thread already did (then its workspace
+// serves).  check(need): the outermost call's workspace holds `need` bytes
+// (else the shortfall is recorded and the call returns IM_ENOMEM before any
+// device work).
+class WsScope {
+ public:
+  WsScope(void* ws, size_t bytes);
+  ~WsScope();
+  WsScope(const WsScope&) = delete;
+  WsScope& operator=(const WsScope&) = delete;
+  bool nested() const { return nested_; }
+  bool check(size_t need) const;
+
+ private:
+  bool nested_ = false;
+  void* ctx_ = nullptr;
+};
 
 // Scratch slots (each caller of a slot owns it for the duration of its call).
 enum Slot {
@@ -265,6 +313,10 @@ enum Slot {
   kSlotOpim,
   kSlotOpimIncOff,
   kSlotOpimInc,
+  kSlotPoolOff0,
+  kSlotPoolMem0,
+  kSlotPoolOff1,
+  kSlotPoolMem1,
   kSlotCount
 };
 

@@ -51,4 +51,12 @@ void release_cover_graphs();
 // one-partition cover).  gains must be zeroed first.
 int launch_cover(CoverArgs& A, hipStream_t s);
 
+// Workspace bytes of im_greedy_cover and im_randgreedi (each call's scratch
+// and the scans it runs).
+size_t ws_greedy(int32_t n, int64_t count, int32_t k);
+size_t ws_randgreedi(int32_t n, int64_t count, int32_t k, int32_t m);
+// Workspace bytes of im_stream_cover and im_greedi_offline.
+size_t ws_stream(int32_t n, int64_t count, int32_t k, int32_t m, double delta);
+size_t ws_offline(int32_t n, int64_t count, int32_t k, int32_t m);
+
 }  // namespace im

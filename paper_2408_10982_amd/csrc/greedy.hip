@@ -693,6 +693,32 @@ int launch_cover(CoverArgs& A, hipStream_t s) {
   return rc;
 }
 
+// Scratch of one standard greedy: done | gmax (k) | cnt (n) | covered (count).
+static size_t greedy_bytes(int32_t n, int64_t count, int32_t k) {
+  return 64 + (size_t)k * 8 + 64 + (size_t)n * 4 + (size_t)count + 64;
+}
+
+// Scratch of one RandGreedi local step: gmax (k m) | done | pbase (m + 1) |
+// hist (m) | order, pos_of, cnt (n each) | covered (m count) | M, Moff (the
+// partition counts per chunk of kPartChunk vertices and their scan).
+static size_t randgreedi_bytes(int32_t n, int64_t count, int32_t k, int32_t m) {
+  const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
+  const size_t cells = (size_t)m * (size_t)nch;
+  return (size_t)m * k * 8 + 64 + 64 + (size_t)(m + 1) * 8 + (size_t)m * 4 + 64 +
+         (size_t)n * 12 + (size_t)m * (size_t)count + 256 + (cells * 4 + 64) / 64 * 64 +
+         (cells + 1) * 8 + 64;
+}
+
+size_t ws_greedy(int32_t n, int64_t count, int32_t k) {
+  return ws_align(greedy_bytes(n, count, k));
+}
+
+size_t ws_randgreedi(int32_t n, int64_t count, int32_t k, int32_t m) {
+  const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
+  return ws_align(randgreedi_bytes(n, count, k, m)) +
+         ws_align((size_t)(((int64_t)m * nch) / 8192 + 2) * 8);
+}
+
 }  // namespace im
 
 using namespace im;
@@ -700,12 +726,14 @@ using namespace im;
 extern "C" int im_greedy_cover(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                                int64_t total, const int64_t* inc_off, const int32_t* inc_mem,
                                int32_t k, int32_t* seeds, int64_t* gains, int32_t* nsel,
-                               int64_t* coverage, void* stream) {
+                               int64_t* coverage, void* ws, size_t ws_bytes, void* stream) {
   if (n <= 0 || count < 0 || count >= ((int64_t)1 << 31) || total < 0 || k <= 0 || !off ||
       !inc_off || !seeds || !gains || !nsel || !coverage || (total > 0 && (!mem || !inc_mem)))
     return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_greedy(n, count, k))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
-  const size_t bytes = 64 + (size_t)k * 8 + 64 + (size_t)n * 4 + (size_t)count + 64;
+  const size_t bytes = greedy_bytes(n, count, k);
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotGreedy, bytes, &p));
   char* c = (char*)p;
@@ -737,11 +765,13 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
                              int64_t total, const int64_t* inc_off, const int32_t* inc_mem,
                              int32_t k, int32_t m, uint64_t part_seed, uint8_t* part,
                              int32_t* lseeds, int64_t* lgains, int32_t* lcount, int64_t* lcover,
-                             void* stream) {
+                             void* ws, size_t ws_bytes, void* stream) {
   if (n <= 0 || count < 0 || count >= ((int64_t)1 << 31) || total < 0 || k <= 0 || m < 1 ||
       m > kMaxParts || !off || !inc_off || !part || !lseeds || !lgains || !lcount || !lcover ||
       (total > 0 && (!mem || !inc_mem)))
     return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_randgreedi(n, count, k, m))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   k_partition<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
       n, m, (uint32_t)part_seed, (uint32_t)(part_seed >> 32), part);
@@ -750,11 +780,8 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   // covered(m*count) | M(m*nch) | Moff(m*nch+1)
   const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
   const size_t cells = (size_t)m * (size_t)nch;
-  const size_t bytes = (size_t)m * k * 8 + 64 + 64 + (size_t)(m + 1) * 8 + (size_t)m * 4 + 64 +
-                       (size_t)n * 12 + (size_t)m * (size_t)count + 256 +
-                       (cells * 4 + 64) / 64 * 64 + (cells + 1) * 8 + 64;
   void* p = nullptr;
-  IM_TRY(scratch(s, kSlotLocal, bytes, &p));
+  IM_TRY(scratch(s, kSlotLocal, randgreedi_bytes(n, count, k, m), &p));
   char* c = (char*)p;
   unsigned long long* gmax = (unsigned long long*)c;
   c += ((size_t)m * k * 8 + 63) / 64 * 64;

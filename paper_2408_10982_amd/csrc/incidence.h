@@ -25,5 +25,8 @@ struct IncSrc {
 // Members outside [0, nv) are skipped.  Asynchronous on s.
 int build_incidence(const IncSrc& src, int32_t nv, int64_t* inc_off, int32_t* inc_mem,
                     hipStream_t s);
+// Workspace bytes of build_incidence: the least (a 2^24-pair round) or, with
+// `full`, room to transpose every pair in one round.
+size_t ws_incidence(int32_t nv, int64_t total, int32_t ntasks, bool full);
 
 }  // namespace im

@@ -604,25 +604,21 @@ static int build_incidence_dense(const IncSrc& S, int32_t nv, int64_t* inc_off,
   return IM_OK;
 }
 
-// Pair budget: the (vertex, sample) pairs of one round of buckets.  A
-// collection whose pairs exceed it is transposed in rounds of consecutive
-// buckets, each round re-walking the members once.
+// Pair budget: the (vertex, sample) pairs of one round of buckets, as many as
+// the workspace holds beside the scan of `cells` counts (at least 2^24, or
+// the total when smaller).  A collection whose pairs exceed it is transposed
+// in rounds of consecutive buckets, each round re-walking the members once.
 // IM_INCIDENCE_PAIR_BUDGET (pairs, >= 1) overrides it, to exercise the rounds.
-static int64_t pair_budget(int64_t total) {
+static int64_t pair_budget(int64_t total, int64_t cells) {
   if (const char* env = getenv("IM_INCIDENCE_PAIR_BUDGET")) {
     const long long b = atoll(env);
     if (b >= 1) return std::min<int64_t>(total, (int64_t)b);
   }
-  // up to 1 GiB of pairs needs no query of free memory (a driver call on
-  // every transpose otherwise)
-  if (total <= ((int64_t)1 << 27)) return std::max<int64_t>(total, (int64_t)1 << 24);
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
-    (void)hipGetLastError();
-    return total;
-  }
-  const int64_t fit = (int64_t)(free_b / 8 / 5 * 2);  // 40% of free HBM, 8 bytes per pair
-  return std::max<int64_t>(std::min<int64_t>(total, fit), (int64_t)1 << 24);
+  const size_t scan = ws_align((size_t)(cells / 8192 + 2) * 8) + 512;
+  const size_t room = scratch_largest();
+  const int64_t fit = room > scan ? (int64_t)((room - scan) / 8) : 0;
+  return std::max<int64_t>(std::min<int64_t>(total, (int64_t)1 << 24),
+                           std::min<int64_t>(total, fit));
 }
 
 // Members per vertex above which a collection takes the dense form
@@ -647,11 +643,13 @@ int build_incidence(const IncSrc& S, int32_t nv, int64_t* inc_off, int32_t* inc_
   const int64_t chunk = std::max<int64_t>(kMinChunk, (int64_t)64 * nb);
   const int64_t nchunks = (S.total + chunk - 1) / chunk;
   const int64_t cells = (int64_t)nb * nchunks;
-  const int64_t budget = pair_budget(S.total);
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t bM = up((size_t)cells * 4), bMoff = up((size_t)(cells + 1) * 8);
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotIncidence, bM + bMoff, &p));
+  const int64_t budget = pair_budget(S.total, cells);
+  if (budget < S.total)  // one round would have been enough with room for every pair
+    scratch_wish(2 * ws_align((size_t)S.total * 4) + ws_align((size_t)(cells / 8192 + 2) * 8));
   uint32_t* M = (uint32_t*)p;
   int64_t* Moff = (int64_t*)((char*)p + bM);
   int32_t *pv = nullptr, *pj = nullptr;
@@ -706,15 +704,34 @@ int build_incidence(const IncSrc& S, int32_t nv, int64_t* inc_off, int32_t* inc_
   return IM_OK;
 }
 
+static size_t ws_scan(int64_t n) { return ws_align((size_t)(n / 8192 + 2) * 8); }
+
+size_t ws_incidence(int32_t nv, int64_t total, int32_t ntasks, bool full) {
+  if (total <= 0) return 0;
+  if (total > dense_ratio() * (int64_t)nv)  // either dense form
+    return ws_align((size_t)nv * 8) + ws_align((size_t)(std::max(ntasks, 1) + 1) * 8) +
+           ws_align((size_t)nv * 8) + ws_scan(nv);
+  int bits = kMinBucketBits;
+  while ((((int64_t)nv - 1) >> bits) + 1 > kMaxBuckets) ++bits;
+  const int64_t nb = (((int64_t)nv - 1) >> bits) + 1;
+  const int64_t chunk = std::max<int64_t>(kMinChunk, (int64_t)64 * nb);
+  const int64_t cells = nb * ((total + chunk - 1) / chunk);
+  const int64_t pairs = full ? total : std::min<int64_t>(total, (int64_t)1 << 24);
+  return ws_align((size_t)cells * 4) + ws_align((size_t)(cells + 1) * 8) +
+         2 * ws_align((size_t)pairs * 4) + ws_scan(cells) + 1024;
+}
+
 }  // namespace im
 
 extern "C" int im_build_incidence(int32_t n, int64_t count, const int64_t* off,
                                   const int32_t* mem, int64_t total, int64_t* inc_off,
-                                  int32_t* inc_mem, void* stream) {
+                                  int32_t* inc_mem, void* ws, size_t ws_bytes, void* stream) {
   using namespace im;
   if (n <= 0 || count < 0 || total < 0 || !off || !inc_off || (total > 0 && (!mem || !inc_mem)) ||
       count >= ((int64_t)1 << 31) || (total > 0 && count == 0))
     return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_incidence(n, total, 0, false))) return IM_ENOMEM;
   const IncSrc S{off, count, mem, total, nullptr, nullptr, 0, n};
   return build_incidence(S, n, inc_off, inc_mem, (hipStream_t)stream);
 }

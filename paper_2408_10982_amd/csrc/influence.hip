@@ -225,16 +225,40 @@ __global__ void k_counts_out(const unsigned long long* __restrict__ cnt, int32_t
   if (b < nb) out[b] = (int64_t)cnt[b];
 }
 
+constexpr int kMaxLevelsBuf = 1 << 16;
+
+// Scratch of a simulation batch of nb_max cascades: visited bits, two level
+// queues of (simulation, vertex) entries, per-level counts, per-simulation
+// counts and the seeds.
+static size_t influence_bytes(int32_t n, int32_t nb_max, int32_t nseeds) {
+  const int64_t words = ((int64_t)n + 31) / 32;
+  const int64_t qcap = (int64_t)nb_max * n;  // a simulation reaches each vertex once
+  return ws_align((size_t)nb_max * words * 4) + 2 * ws_align((size_t)qcap * 8) +
+         ws_align((size_t)kMaxLevelsBuf * 8) + ws_align((size_t)nb_max * 8) +
+         ws_align((size_t)std::max(nseeds, 1) * 4);
+}
+
+size_t ws_forward(int32_t n) {
+  return ws_align((size_t)n * 8 + 64) + ws_align((size_t)(n / 8192 + 2) * 8);
+}
+
+size_t ws_influence(int32_t n, int64_t nsims, int32_t nseeds) {
+  if (nsims <= 0) return 0;
+  return influence_bytes(n, (int32_t)std::min<int64_t>(nsims, kSimBatch), nseeds);
+}
+
 }  // namespace im
 
 using namespace im;
 
 extern "C" int im_prepare_forward(int32_t n, int64_t num_edges, const int32_t* in_off,
                                   const int32_t* in_src, int64_t* out_off, int32_t* out_eid,
-                                  int32_t* edge_dst, void* stream) {
+                                  int32_t* edge_dst, void* ws, size_t ws_bytes, void* stream) {
   if (n <= 0 || num_edges < 0 || num_edges >= (int64_t)0x7FFFFFFF || !in_off || !out_off ||
       (num_edges > 0 && (!in_src || !out_eid || !edge_dst)))
     return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_forward(n))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotForward, (size_t)n * 8 + 64, &p));
@@ -264,7 +288,7 @@ extern "C" int im_prepare_forward(int32_t n, int64_t num_edges, const int32_t* i
 extern "C" int im_influence(const im_graph* g, const int64_t* out_off, const int32_t* out_eid,
                             const int32_t* edge_dst, uint64_t seed, uint32_t stream_tag,
                             int64_t first, int64_t nsims, const int32_t* seeds, int32_t nseeds,
-                            int64_t* counts, void* stream) {
+                            int64_t* counts, void* ws, size_t ws_bytes, void* stream) {
   if (!g || g->n <= 0 || !g->in_off || !out_off || (g->num_edges > 0 && (!out_eid || !edge_dst ||
                                                                          !g->thr)) ||
       (g->model != IM_IC && g->model != IM_LT) || first < 0 || nsims < 0 ||
@@ -274,6 +298,8 @@ extern "C" int im_influence(const im_graph* g, const int64_t* out_off, const int
   for (int32_t j = 0; j < nseeds; ++j)
     if (seeds[j] < 0 || seeds[j] >= g->n) return IM_EINVAL;
   if (nsims == 0) return IM_OK;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_influence(g->n, nsims, nseeds))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   DeviceInfo di;
   IM_TRY(device_info(&di));
@@ -281,13 +307,9 @@ extern "C" int im_influence(const im_graph* g, const int64_t* out_off, const int
   const int64_t words = ((int64_t)n + 31) / 32;
   const int32_t nb_max = (int32_t)std::min<int64_t>(nsims, kSimBatch);
   const int64_t qcap = (int64_t)nb_max * n;  // a simulation reaches each vertex once
-  constexpr int kMaxLevelsBuf = 1 << 16;
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t bytes = up((size_t)nb_max * words * 4) + 2 * up((size_t)qcap * 8) +
-                       up((size_t)kMaxLevelsBuf * 8) + up((size_t)nb_max * 8) +
-                       up((size_t)std::max(nseeds, 1) * 4);
   void* p = nullptr;
-  IM_TRY(scratch(s, kSlotForward, bytes, &p));
+  IM_TRY(scratch(s, kSlotForward, influence_bytes(n, nb_max, nseeds), &p));
   char* c = (char*)p;
   auto take = [&](size_t b) {
     char* r = c;

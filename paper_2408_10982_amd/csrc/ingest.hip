@@ -115,11 +115,14 @@ __global__ __launch_bounds__(256) void k_ic_skip(int32_t n, const int32_t* __res
 
 extern "C" int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off,
                                 const int32_t* in_src, const float* weight, int32_t model,
-                                uint32_t* thr, double* skip, void* stream) {
+                                uint32_t* thr, double* skip, void* ws, size_t ws_bytes,
+                                void* stream) {
   using namespace im;
   if (n <= 0 || num_edges < 0 || num_edges >= (int64_t)0x7FFFFFFF || !in_off || !thr ||
       (num_edges > 0 && (!weight || !in_src)) || (model != IM_IC && model != IM_LT))
     return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_align(64))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotScan, 64, &p));

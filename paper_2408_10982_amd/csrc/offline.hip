@@ -90,6 +90,18 @@ __global__ __launch_bounds__(256) void k_offline_final(int32_t m, int32_t k, int
   }
 }
 
+// Scratch of one call gathering nc local seeds: order, pos_of, cnt, covered,
+// the greedy's gmax, seeds and gains, and three flags.
+static size_t offline_bytes(int32_t n, int64_t count, int32_t k, int64_t nc) {
+  const size_t c = (size_t)std::max<int64_t>(nc, 1) * 4;
+  return ws_align(c) + ws_align((size_t)n * 4) + ws_align(c) + ws_align((size_t)count + 1) +
+         ws_align((size_t)k * 8) * 3 + ws_align(64) * 3;
+}
+
+size_t ws_offline(int32_t n, int64_t count, int32_t k, int32_t m) {
+  return offline_bytes(n, count, k, (int64_t)k * m);
+}
+
 }  // namespace im
 
 using namespace im;
@@ -99,11 +111,13 @@ extern "C" int im_greedi_offline(int32_t n, int64_t count, const int64_t* off, c
                                  int32_t k, int32_t m, const int32_t* lseeds, const int32_t* lcount,
                                  const int64_t* lcover, double alpha, int32_t* seeds,
                                  int32_t* nsel, int64_t* coverage, int32_t* info,
-                                 int64_t* gcover, void* stream) {
+                                 int64_t* gcover, void* ws, size_t ws_bytes, void* stream) {
   if (n <= 0 || count < 0 || count >= ((int64_t)1 << 31) || total < 0 || k <= 0 || m < 1 ||
       m > kMaxParts || !off || !inc_off || !lseeds || !lcount || !lcover || !seeds || !nsel ||
       !coverage || !info || (total > 0 && (!mem || !inc_mem)) || !(alpha > 0.0 && alpha <= 1.0))
     return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_offline(n, count, k, m))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   int32_t T = (int32_t)ceil(alpha * (double)k);
   T = std::max(1, std::min(T, k));
@@ -114,11 +128,8 @@ extern "C" int im_greedi_offline(int32_t n, int64_t count, const int64_t* off, c
   int64_t nc = 0;
   for (int p = 0; p < m; ++p) nc += std::max(0, std::min(T, lc[p]));
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t bytes = up((size_t)std::max<int64_t>(nc, 1) * 4) + up((size_t)n * 4) +
-                       up((size_t)std::max<int64_t>(nc, 1) * 4) + up((size_t)count + 1) +
-                       up((size_t)k * 8) * 3 + up(64) * 3;
   void* p = nullptr;
-  IM_TRY(scratch(s, kSlotOffline, bytes, &p));
+  IM_TRY(scratch(s, kSlotOffline, offline_bytes(n, count, k, nc), &p));
   char* c = (char*)p;
   auto take = [&](size_t b) {
     char* r = c;

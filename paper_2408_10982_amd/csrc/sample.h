@@ -45,18 +45,27 @@ struct ArenaRun {
   double ms_main = 0.0, ms_large = 0.0;  // only when timed
 };
 
-// Phase 1: samples every task into the stream's arena and writes the
+// Phase 1: samples every task into the call's arena and writes the
 // canonical offsets (off, count_total + 1 entries).  expect: a guess of the
-// member total used to size the arena (0: none).  Synchronises s.
+// member total used to size the arena (0: none).  stop_above > 0: a total
+// above it is only counted (the sets need not be kept: the caller reports
+// IM_ERANGE), so a short arena is not refilled.  Synchronises s.
 int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
-                    int64_t* off, int64_t expect, bool sort_all, bool timed, ArenaRun* R,
-                    hipStream_t s);
+                    int64_t* off, int64_t expect, int64_t stop_above, bool sort_all, bool timed,
+                    ArenaRun* R, hipStream_t s);
 // Phase 2: copies the sets into mem (R.total entries at off).  The stream's
 // arena must be untouched since phase 1.  ms (optional) gets the device time
 // and then the call waits for the copy.
 int gather_arena(const ArenaRun& R, const int64_t* off, int32_t* mem, double* ms, hipStream_t s);
 
 int graph_ok(const im_graph* g);
+// Returns the sampling slots (task table, metadata, arena, walk lists,
+// large-set workers) to the workspace once the sets have been gathered.
+void release_sampling();
+// Workspace bytes of one sampling call (ws_sample): `full` with every
+// large-set worker the launch can use, else the minimum (one worker).
+size_t ws_sample(int num_cus, int64_t count, int64_t capacity, int32_t max_n, int32_t model,
+                 bool full);
 TaskDesc task_of(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t first,
                  int64_t count, int64_t sample_base);
 

@@ -1546,6 +1546,34 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
 }
 
 // ------------------------------------------------------------------ host
+// Arena entries beyond the sets themselves: the unused tails of the chunks
+// the wavefronts reserve.  Every reservation holds at least one set and
+// exceeds its sets by at most 4 kChunk, which bounds the tails by
+// 4 kChunk per set; over many sets they stay below 4 kChunk per resident
+// wavefront slot (measured).
+static uint64_t arena_slack(int num_cus, uint64_t sets) {
+  return std::min<uint64_t>((uint64_t)num_cus * 32 * 4 * kChunk, sets * 4 * kChunk);
+}
+
+// Workgroups of the LT launch: the knob's count per CU, or fewer when there
+// are fewer walks than lanes to give them out (each wavefront claims
+// lt_grab at a time).
+static int lt_blocks(int num_cus, int64_t walks) {
+  const int64_t per_block = (int64_t)(kLtBlock / kWave) * tune(IM_TUNE_LT_GRAB);
+  const int64_t want = (walks + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)num_cus * tune(IM_TUNE_LT_BLOCKS),
+                                                     want));
+}
+
+static size_t lt_lane_bytes(int blocks) {
+  return ws_align((size_t)blocks * kLtBlock * kLtCap * sizeof(int32_t));
+}
+
+// One large-set worker: an n-bit bitmap and an n-entry queue.
+static size_t big_worker_bytes(int32_t max_n) {
+  return (size_t)((max_n + 31) / 32) * 4 + (size_t)max_n * 4;
+}
+
 // Phase 1 of sampling every task of a table into one canonical CSR over output
 // positions (task t's sets at [sample_base, sample_base + count)).  IC tasks
 // share one main launch, LT tasks another; both hand oversized sets to one
@@ -1555,8 +1583,8 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(uint32_t count,
 // and LT tasks share the output); otherwise only LT sets are sorted there.
 // expect: a guess of the member total (0: none), used to size the arena.
 int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
-                    int64_t* off, int64_t expect, bool sort_all, bool timed, ArenaRun* R,
-                    hipStream_t s) {
+                    int64_t* off, int64_t expect, int64_t stop_above, bool sort_all, bool timed,
+                    ArenaRun* R, hipStream_t s) {
   *R = ArenaRun{};
   DeviceInfo di;
   IM_TRY(device_info(&di));
@@ -1614,15 +1642,24 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
   uint32_t* big_list = (uint32_t*)(lens + cnt);
   Handoff* handoff = (Handoff*)(((uintptr_t)(big_list + cnt) + 63) & ~(uintptr_t)63);
 
-  static thread_local int64_t last_total = 0;
-  // room for the sets plus the unfilled tails of the per-wave arena chunks;
-  // with no better guess, 64 members per set (one pass is worth more than
-  // the memory: an arena that turns out short means sampling again)
-  const uint64_t slack = (uint64_t)di.num_cus * 32 * 4 * kChunk;
-  const int64_t guess = expect > 0 ? expect + expect / 8
-                                   : std::min<int64_t>(count_total * 64, (int64_t)1 << 30);
-  uint64_t arena_cap =
-      (uint64_t)std::max<int64_t>(std::max<int64_t>(guess, last_total), count_total * 2) + slack;
+  // room for the sets plus the unfilled tails of the per-wave arena chunks
+  // (each wavefront holds at most one partly used chunk); the guess of the
+  // member total: `expect` (the caller's capacity, or an estimate), else up
+  // to 64 members per set within what the workspace leaves, so that one pass
+  // usually suffices (an arena that turns out short means sampling again)
+  const uint64_t slack = arena_slack(di.num_cus, cnt);
+  // carved after the arena: the LT walks' lists, one large-set worker, the scan
+  const size_t later = (any_lt ? lt_lane_bytes(lt_blocks(di.num_cus, seg_lt.back())) : 0) +
+                       ws_align(big_worker_bytes(max_n)) +
+                       ws_align((size_t)(cnt / 8192 + 2) * 8) + 4096;
+  const size_t room = scratch_room();
+  const int64_t room_entries =
+      room > later ? (int64_t)((room - later) / 4) - (int64_t)slack : (int64_t)0;
+  const int64_t guess =
+      expect > 0 ? expect + expect / 8
+                 : std::max<int64_t>(count_total * 2,
+                                     std::min<int64_t>(count_total * 64, room_entries / 2));
+  uint64_t arena_cap = (uint64_t)std::max<int64_t>(guess, count_total * 2) + slack;
   unsigned long long hc[16] = {0};
   // device times of the launches, only when statistics are requested
   hipEvent_t ev[4] = {};
@@ -1669,7 +1706,7 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
       Al.nseg = (int32_t)task_lt.size();
       Al.count = (uint64_t)seg_lt.back();
       Al.lt_grab = (uint32_t)tune(IM_TUNE_LT_GRAB);
-      const int blocks = di.num_cus * (int)tune(IM_TUNE_LT_BLOCKS);
+      const int blocks = lt_blocks(di.num_cus, Al.count);
       const size_t lanes = (size_t)blocks * kLtBlock;
       void* hp = nullptr;
       IM_TRY(scratch(s, kSlotSampleLtLane, lanes * kLtCap * sizeof(int32_t), &hp));
@@ -1697,31 +1734,31 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
       const uint32_t max_workers =
           (uint32_t)di.num_cus * (narrow ? BigNarrow::kPerCu : BigWide::kPerCu);
       const size_t budget = (size_t)IM_BIG_BUDGET_GIB << 30;
-      const uint32_t cap_workers = (uint32_t)std::max<size_t>(
-          1, std::min<size_t>(max_workers, budget / per_worker));
-      const uint32_t workers = std::min<uint32_t>(nbig, cap_workers);
+      // within the budget and what the workspace leaves beside the offset
+      // scan that follows (at least one worker)
+      const size_t scan = ws_align((size_t)(cnt / 8192 + 2) * 8) + 256;
+      const size_t room = scratch_largest();
+      const size_t fit = room > scan ? (room - scan) / per_worker : 0;
+      if (fit < 1) {
+        scratch_need(per_worker + scan);
+        set_error_text("workspace too small for one large-set worker (" +
+                       std::to_string(per_worker) + " bytes; im_workspace_need)");
+        return IM_ENOMEM;
+      }
+      const uint32_t best = (uint32_t)std::min<size_t>(
+          std::min<size_t>(max_workers, budget / per_worker), (size_t)nbig);
+      const uint32_t workers = (uint32_t)std::max<size_t>(1, std::min<size_t>(best, fit));
+      if (workers < best) scratch_wish((size_t)best * per_worker + 4096);
       void* bp = nullptr;
-      bool bfresh = false;
-      IM_TRY(scratch_fresh(s, kSlotSampleBig, (size_t)cap_workers * per_worker, &bp, &bfresh));
+      IM_TRY(scratch(s, kSlotSampleBig, (size_t)workers * per_worker, &bp));
       BigArgs Bg;
       Bg.nwords = nwords;
       Bg.qcap = (uint32_t)max_n;
       Bg.bitmaps = (uint32_t*)bp;
-      Bg.queues = (int32_t*)((char*)bp + (size_t)cap_workers * nwords * 4);
-      // the zero invariant only holds for the layout that last used the buffer
-      static std::mutex layout_mu;
-      static std::map<std::pair<void*, uintptr_t>, std::pair<uint32_t, uint32_t>> layouts;
-      bool same_layout = false;
-      {
-        std::lock_guard<std::mutex> lk(layout_mu);
-        auto key = std::make_pair(bp, (uintptr_t)s);
-        auto it = layouts.find(key);
-        same_layout = !bfresh && it != layouts.end() && it->second.first == nwords &&
-                      it->second.second == cap_workers;
-        layouts[key] = std::make_pair(nwords, cap_workers);
-      }
-      if (!same_layout)
-        IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)cap_workers * nwords * 4, s));
+      Bg.queues = (int32_t*)((char*)bp + (size_t)workers * nwords * 4);
+      // every worker's bitmap starts empty (each set clears its own bits
+      // again before the worker takes the next one)
+      IM_HIP(hipMemsetAsync(Bg.bitmaps, 0, (size_t)workers * nwords * 4, s));
       if (timed) IM_HIP(hipEventRecord(ev[2], s));
       if (narrow)
         k_sample_big<BigNarrow><<<dim3(workers), dim3(BigNarrow::kBlock), 0, s>>>(A, Bg);
@@ -1735,6 +1772,9 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
     }
     R->passes = attempt + 1;
     if (hc[1] <= arena_cap) break;
+    // more members than the caller can take: the call reports the total and
+    // returns IM_ERANGE, so the sets need not be kept
+    if (stop_above > 0 && (int64_t)hc[10] > stop_above) break;
     if (attempt == 2) {
       set_error_text("im_sample_rrr: arena still short after 3 passes (needed " +
                      std::to_string(hc[1]) + " of " + std::to_string(arena_cap) + " entries)");
@@ -1744,7 +1784,6 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
     arena_cap = hc[1] + hc[1] / 8 + slack;
   }
   const int64_t tot = (int64_t)hc[10];
-  last_total = std::max<int64_t>(tot, 0);
   IM_TRY(exclusive_scan_i32_to_i64(lens, (int64_t)cnt, off, s));
   R->cnt = cnt;
   R->arena = (const int32_t*)ap;
@@ -1818,7 +1857,7 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
                  int64_t* off, int32_t* mem, int64_t capacity, int64_t* total,
                  im_sample_stats* stats, bool sort_all, hipStream_t s) {
   ArenaRun R;
-  IM_TRY(sample_to_arena(h_tasks, ntasks, count_total, max_n, off, capacity, sort_all,
+  IM_TRY(sample_to_arena(h_tasks, ntasks, count_total, max_n, off, capacity, capacity, sort_all,
                          stats != nullptr, &R, s));
   *total = R.total;
   if (R.total > capacity) {
@@ -1831,6 +1870,41 @@ int sample_tasks(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32
   IM_HIP(hipStreamSynchronize(s));
   fill_stats(R, ms_canon, stats);
   return IM_OK;
+}
+
+void release_sampling() {
+  for (int slot : {kSlotSampleTasks, kSlotSampleMeta, kSlotSampleArena, kSlotSampleLtLane,
+                   kSlotSampleBig})
+    scratch_release(slot);
+}
+
+// Workspace of one sampling call (one task): the task table, per-set
+// metadata, the staging arena for `capacity` members, the LT walks' lists,
+// large-set workers (one at least; `full`: as many as the launch can use
+// within IM_BIG_BUDGET_GIB, 16 for LT whose walks rarely overflow) and the
+// offset scan.
+size_t ws_sample(int num_cus, int64_t count, int64_t capacity, int32_t max_n, int32_t model,
+                 bool full) {
+  if (count <= 0) return 0;
+  const uint64_t cnt = (uint64_t)count;
+  size_t b = ws_align(sizeof(TaskDesc) + 64 + 256) + 64;  // task table, segments
+  const uint32_t nhand = (uint32_t)std::min<uint64_t>(cnt, kMaxHandoff);
+  b += ws_align((size_t)cnt * 16 + 512 + (size_t)nhand * sizeof(Handoff) + 64);
+  const int64_t guess = capacity > 0 ? capacity + capacity / 8 : 0;
+  const uint64_t arena = (uint64_t)std::max<int64_t>(guess, count * 2) + arena_slack(num_cus, cnt);
+  b += ws_align((size_t)arena * 4);
+  if (model == IM_LT) b += lt_lane_bytes(lt_blocks(num_cus, count));
+  const size_t per_worker = big_worker_bytes(max_n);
+  size_t workers = 1;
+  if (full) {
+    const size_t budget = (size_t)IM_BIG_BUDGET_GIB << 30;
+    const size_t most = model == IM_LT ? 16 : (size_t)num_cus * BigNarrow::kPerCu;
+    workers = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(most, budget / per_worker),
+                                                   (size_t)count));
+  }
+  b += ws_align(workers * per_worker);
+  b += ws_align((size_t)(cnt / 8192 + 2) * 8) + 8192;
+  return b;
 }
 
 int graph_ok(const im_graph* g) {
@@ -1864,12 +1938,17 @@ TaskDesc task_of(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t 
 // ------------------------------------------------------------------ entry
 extern "C" int im_sample_rrr(const im_graph* g, uint64_t seed, uint32_t stream_tag,
                              int64_t first, int64_t count, int64_t* off, int32_t* mem,
-                             int64_t capacity, int64_t* total, im_sample_stats* stats,
-                             void* stream) {
+                             int64_t capacity, int64_t* total, im_sample_stats* stats, void* ws,
+                             size_t ws_bytes, void* stream) {
   using namespace im;
   if (!off || !total || first < 0 || count < 0 || capacity < 0 ||
       first + count > (int64_t)1 << 32 || (capacity > 0 && !mem) || !graph_ok(g))
     return IM_EINVAL;
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_sample(di.num_cus, count, capacity, g->n, g->model, false)))
+    return IM_ENOMEM;
   const TaskDesc T = task_of(g, seed, stream_tag, first, count, 0);
   return sample_tasks(&T, 1, count, g->n, off, mem, capacity, total, stats, false,
                       (hipStream_t)stream);

@@ -13,6 +13,8 @@
 #include <vector>
 
 #include "common.h"
+#include "cover.h"
+#include "incidence.h"
 #include "sample.h"
 
 namespace im {
@@ -22,32 +24,23 @@ __global__ void k_add_base(int64_t* __restrict__ off, int64_t n, int64_t base) {
   if (i < n) off[i] += base;
 }
 
-// A growable device pool of RRR sets owned by one im_solve call.
+// A growable pool of RRR sets owned by one im_solve or im_opim call, held in
+// two workspace slots (offsets and members) that are returned when the pool
+// goes out of scope.
 struct Pool {
+  int32_t slot_off, slot_mem;
   int64_t count = 0, total = 0;
   int64_t cap_sets = 0, cap_mem = 0;
   int64_t* off = nullptr;
   int32_t* mem = nullptr;
+  Pool(int32_t so, int32_t sm) : slot_off(so), slot_mem(sm) {}
   ~Pool() {
-    if (off) (void)hipFree(off);
-    if (mem) (void)hipFree(mem);
+    scratch_release(slot_off);
+    scratch_release(slot_mem);
   }
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
 };
-
-static int grow(void** p, size_t old_bytes, size_t new_bytes, hipStream_t s) {
-  void* q = nullptr;
-  if (hipMalloc(&q, new_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return IM_ENOMEM;
-  }
-  if (*p) {
-    if (old_bytes) IM_HIP(hipMemcpyAsync(q, *p, old_bytes, hipMemcpyDeviceToDevice, s));
-    IM_HIP(hipStreamSynchronize(s));
-    IM_HIP(hipFree(*p));
-  }
-  *p = q;
-  return IM_OK;
-}
 
 // Device times and exact counters of the sampling and selection calls of
 // one im_solve.
@@ -65,8 +58,11 @@ static int pool_extend(Pool& P, const im_graph* g, uint64_t seed, uint32_t tag, 
                        double mean_hint, SolveTally* tally, hipStream_t s) {
   if (want <= P.count) return IM_OK;
   if (want + 1 > P.cap_sets) {
-    int64_t nc = std::max<int64_t>(want + 1, P.cap_sets * 2);
-    IM_TRY(grow((void**)&P.off, (size_t)(P.count + 1) * 8, (size_t)nc * 8, s));
+    const int64_t nc = want + 1;
+    void* p = nullptr;
+    IM_TRY(scratch_grow(s, P.slot_off, P.count > 0 ? (size_t)(P.count + 1) * 8 : 0,
+                        (size_t)nc * 8, &p));
+    P.off = (int64_t*)p;
     P.cap_sets = nc;
   }
   if (P.count == 0) IM_HIP(hipMemsetAsync(P.off, 0, 8, s));
@@ -74,10 +70,13 @@ static int pool_extend(Pool& P, const im_graph* g, uint64_t seed, uint32_t tag, 
   const TaskDesc T = task_of(g, seed, tag, P.count, add, 0);
   ArenaRun R;
   const int64_t expect = mean_hint > 0.0 ? (int64_t)(mean_hint * (double)add) : 0;
-  IM_TRY(sample_to_arena(&T, 1, add, g->n, P.off + P.count, expect, false, true, &R, s));
-  if (P.cap_mem - P.total < R.total) {
-    const int64_t nc = std::max<int64_t>(P.total + R.total + R.total / 4, P.cap_mem * 2);
-    IM_TRY(grow((void**)&P.mem, (size_t)P.total * 4, (size_t)std::max<int64_t>(nc, 1) * 4, s));
+  IM_TRY(sample_to_arena(&T, 1, add, g->n, P.off + P.count, expect, 0, false, true, &R, s));
+  if (P.cap_mem - P.total < R.total || !P.mem) {
+    const int64_t nc = P.total + R.total;
+    void* p = nullptr;
+    IM_TRY(scratch_grow(s, P.slot_mem, (size_t)P.total * 4, (size_t)std::max<int64_t>(nc, 1) * 4,
+                        &p));
+    P.mem = (int32_t*)p;
     P.cap_mem = nc;
   }
   double ms_g = 0.0;
@@ -87,6 +86,7 @@ static int pool_extend(Pool& P, const im_graph* g, uint64_t seed, uint32_t tag, 
                                                                            add + 1, P.total);
     IM_HIP(hipGetLastError());
   }
+  release_sampling();
   P.total += R.total;
   P.count = want;
   if (tally) {
@@ -129,7 +129,7 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
   IM_TRY(scratch(s, kSlotSolveInc, (size_t)std::max<int64_t>(P.total, 1) * 4, &pim));
   int64_t* inc_off = (int64_t*)pio;
   int32_t* inc_mem = (int32_t*)pim;
-  IM_TRY(im_build_incidence(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, s));
+  IM_TRY(im_build_incidence(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, nullptr, 0, s));
   IM_HIP(hipEventRecord(ev[1], s));
   // outputs: seeds k, coverage, nsel, info 4, global cover
   IM_TRY(scratch(s, kSlotSolveOut, (size_t)k * 12 + 128, &pout));
@@ -143,7 +143,7 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
     void* pg = nullptr;
     IM_TRY(scratch(s, kSlotSolveLocal, (size_t)k * 8, &pg));
     IM_TRY(im_greedy_cover(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, d_seeds,
-                           (int64_t*)pg, d_nsel, d_cov, s));
+                           (int64_t*)pg, d_nsel, d_cov, nullptr, 0, s));
     IM_HIP(hipEventRecord(ev[2], s));
   } else {
     const int32_t m = o->m;
@@ -156,15 +156,15 @@ static int select_on(const Pool& P, int32_t n, int32_t k, const im_solve_opts* o
     int32_t* lcount = lseeds + (size_t)m * k;
     uint8_t* part = (uint8_t*)(lcount + m);
     IM_TRY(im_randgreedi(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, m, o->part_seed,
-                         part, lseeds, lgains, lcount, lcover, s));
+                         part, lseeds, lgains, lcount, lcover, nullptr, 0, s));
     IM_HIP(hipEventRecord(ev[2], s));
     if (o->selector == IM_SEL_GREEDIRIS)
       IM_TRY(im_stream_cover(n, P.count, inc_off, inc_mem, k, m, lseeds, lcount, lcover, o->delta,
-                             o->alpha, d_seeds, d_nsel, d_cov, d_info, s));
+                             o->alpha, d_seeds, d_nsel, d_cov, d_info, nullptr, 0, s));
     else
       IM_TRY(im_greedi_offline(n, P.count, P.off, P.mem, P.total, inc_off, inc_mem, k, m, lseeds,
                                lcount, lcover, o->alpha, d_seeds, d_nsel, d_cov, d_info, d_gcov,
-                               s));
+                               nullptr, 0, s));
   }
   IM_HIP(hipEventRecord(ev[3], s));
   int32_t h_nsel = 0, h_info[4] = {-1, 0, -1, 0};
@@ -403,6 +403,52 @@ static int cover_and_marginals(int32_t n, int64_t count, const int64_t* inc_off,
   return IM_OK;
 }
 
+// Workspace of the selection on a pool of `count` sets and `total` members:
+// the covering subsets and their build, the outputs, the local step and the
+// selector's own scratch.
+static size_t ws_select(int32_t n, int64_t count, int64_t total, int32_t k, int32_t selector,
+                        int32_t m, double delta, bool full) {
+  size_t b = ws_align((size_t)(n + 1) * 8) + ws_align((size_t)std::max<int64_t>(total, 1) * 4) +
+             ws_align((size_t)k * 12 + 128);
+  size_t inner = ws_incidence(n, total, 0, full);
+  if (selector == IM_SEL_GREEDY) {
+    b += ws_align((size_t)k * 8);
+    inner = std::max(inner, ws_greedy(n, count, k));
+  } else {
+    b += ws_align((size_t)n + 64 + (size_t)m * k * 12 + (size_t)m * 12 + 64);
+    const size_t global = selector == IM_SEL_GREEDIRIS ? ws_stream(n, count, k, m, delta)
+                                                       : ws_offline(n, count, k, m);
+    // the local step's scratch stays while the global step runs
+    inner = std::max(inner, ws_randgreedi(n, count, k, m) + global);
+  }
+  return b + inner;
+}
+
+// Workspace of a pool of `count` sets with `total` members.
+static size_t ws_pool(int64_t count, int64_t total) {
+  return ws_align((size_t)(count + 1) * 8) + ws_align((size_t)std::max<int64_t>(total, 1) * 4);
+}
+
+size_t ws_solve(int num_cus, int32_t n, int32_t model, int64_t count, int64_t total, int32_t k,
+                int32_t selector, int32_t m, double delta, bool full) {
+  const size_t pool = ws_pool(count, total);
+  const size_t samp = ws_sample(num_cus, count, total, n, model, full);
+  const size_t sel = ws_select(n, count, total, k, selector, m, delta, full);
+  // one pool at a time; a grown pool is copied from its previous region
+  return pool + pool / 2 + std::max(samp, sel) + ((size_t)1 << 20);
+}
+
+size_t ws_opim(int num_cus, int32_t n, int32_t model, int64_t count, int64_t total, int32_t k,
+               int32_t selector, int32_t m, double delta, bool full) {
+  const size_t pool = ws_pool(count, total);
+  const size_t samp = ws_sample(num_cus, count, total, n, model, full);
+  // both pools, R1's covering subsets kept while R2's are built, flags and marginals
+  const size_t sel = ws_select(n, count, total, k, selector, m, delta, full) +
+                     ws_align((size_t)(n + 1) * 8) + ws_align((size_t)std::max<int64_t>(total, 1) * 4) +
+                     ws_align((size_t)count + 256) + ws_align((size_t)n * 4 + 2048 * 8 + (size_t)k * 4 + 256);
+  return 2 * (pool + pool / 2) + std::max(samp, sel) + ((size_t)1 << 20);
+}
+
 }  // namespace im
 
 extern "C" int im_imm_plan(int32_t n, int32_t k, double eps, im_imm_plan_t* out) {
@@ -456,7 +502,8 @@ extern "C" int im_imm_theta(const im_imm_plan_t* plan, double lb, int64_t* theta
 }
 
 extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve_opts* o,
-                        int32_t* seeds, im_solve_result* res, void* stream) {
+                        int32_t* seeds, im_solve_result* res, void* ws, size_t ws_bytes,
+                        void* stream) {
   using namespace im;
   if (!g || !o || !seeds || !res || k <= 0 || g->n <= 1 || k > g->n || !(eps > 0.0 && eps < 1.0) ||
       (o->selector != IM_SEL_GREEDY && o->selector != IM_SEL_GREEDIRIS &&
@@ -473,6 +520,14 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   im_imm_plan_t plan;
   IM_TRY(im_imm_plan(n, k, eps, &plan));
   const int32_t rounds = plan.rounds;
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  // at least the first round's pool with one member per set
+  WsScope scope(ws, ws_bytes);
+  const int64_t first = o->theta > 0 ? o->theta : plan.theta1;
+  if (!scope.check(ws_solve(di.num_cus, n, g->model, first, first, k, o->selector, o->m, o->delta,
+                            false)))
+    return IM_ENOMEM;
 
   *res = im_solve_result{};
   res->bucket = -1;
@@ -485,7 +540,7 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
   if (o->theta > 0) {
     theta = o->theta;
   } else {
-    Pool P;
+    Pool P(kSlotPoolOff0, kSlotPoolMem0);
     int64_t th = plan.theta1;
     for (int32_t i = 1; i <= rounds; ++i) {
       if (i > 1) th *= 2;
@@ -506,7 +561,7 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
     IM_TRY(im_imm_theta(&plan, lb, &theta));
   }
   if (theta >= ((int64_t)1 << 31)) return IM_ERANGE;
-  Pool F;
+  Pool F(kSlotPoolOff1, kSlotPoolMem1);
   IM_TRY(pool_extend(F, g, o->seed, 1u, theta, mean, &tally, s));
   IM_TRY(select_on(F, n, k, o, &sel, &tally, s));
   for (int32_t j = 0; j < k; ++j) seeds[j] = sel.seeds[j];
@@ -536,8 +591,8 @@ extern "C" int im_solve(const im_graph* g, int32_t k, double eps, const im_solve
 }
 
 extern "C" int im_opim(const im_graph* g, int32_t k, double eps, double fail, int64_t theta_cap,
-                       const im_solve_opts* o, int32_t* seeds, im_opim_result* res,
-                       void* stream) {
+                       const im_solve_opts* o, int32_t* seeds, im_opim_result* res, void* ws,
+                       size_t ws_bytes, void* stream) {
   using namespace im;
   if (!g || !o || !seeds || !res || k <= 0 || g->n <= 1 || k > g->n ||
       !(eps > 0.0 && eps < 1.0) || !(fail > 0.0 && fail < 1.0) || theta_cap < 1 ||
@@ -563,13 +618,19 @@ extern "C" int im_opim(const im_graph* g, int32_t k, double eps, double fail, in
   int64_t theta = (int64_t)ceil(theta_max * eps * eps * (double)k / nd);
   int32_t i_max = (int32_t)ceil(log2(theta_max / (double)theta));
   if (i_max < 1) i_max = 1;
+  DeviceInfo di;
+  IM_TRY(device_info(&di));
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_opim(di.num_cus, n, g->model, theta, theta, k, o->selector, o->m, o->delta,
+                           false)))
+    return IM_ENOMEM;
   const double a = log(3.0 * (double)i_max / fail);
   *res = im_opim_result{};
   res->theta_max = theta_max;
   res->i_max = i_max;
   res->bucket = -1;
   res->global_won = -1;
-  Pool R1, R2;
+  Pool R1(kSlotPoolOff0, kSlotPoolMem0), R2(kSlotPoolOff1, kSlotPoolMem1);
   Selection sel;
   double mean = 0.0;
   for (int32_t i = 1;; ++i) {
@@ -605,7 +666,7 @@ extern "C" int im_opim(const im_graph* g, int32_t k, double eps, double fail, in
     IM_TRY(scratch(s, kSlotOpimIncOff, (size_t)(n + 1) * 8, &pio2));
     IM_TRY(scratch(s, kSlotOpimInc, (size_t)std::max<int64_t>(R2.total, 1) * 4, &pim2));
     IM_TRY(im_build_incidence(n, R2.count, R2.off, R2.mem, R2.total, (int64_t*)pio2,
-                              (int32_t*)pim2, s));
+                              (int32_t*)pim2, nullptr, 0, s));
     int64_t c2 = 0;
     IM_TRY(cover_and_marginals(n, R2.count, (const int64_t*)pio2, (const int32_t*)pim2, d_seeds,
                                sel.nsel, flags, dwork, &c2, nullptr, s));

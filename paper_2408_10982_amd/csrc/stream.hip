@@ -226,6 +226,31 @@ __global__ __launch_bounds__(256) void k_stream_final(StreamArgs A) {
   }
 }
 
+// Truncation length T, bucket count B and scratch bytes of one call:
+// stream (x, a, b per entry) | header | thresholds | bucket seeds, counts and
+// covers | bucket bitmaps when they do not fit in LDS.
+static size_t stream_layout(int64_t count, int32_t k, int32_t m, double delta, double alpha,
+                            int32_t* T_out, int32_t* B_out) {
+  int32_t T = (int32_t)ceil(alpha * (double)k);
+  T = std::max(1, std::min(T, k));
+  int32_t B = (int32_t)ceil(log((double)k) / log(1.0 + delta));
+  if (B < 1) B = 1;
+  *T_out = T;
+  *B_out = B;
+  const int64_t L = (int64_t)T * m;  // longest possible stream
+  const int64_t words = (count + 31) / 32;
+  const bool lds = words <= kLdsWords;
+  return ws_align((size_t)L * 4) + ws_align((size_t)L * 8) * 2 + ws_align(16) +
+         ws_align((size_t)B * 8) + ws_align((size_t)B * k * 4) + ws_align((size_t)B * 4) +
+         ws_align((size_t)B * 8) + (lds ? 0 : (size_t)B * (size_t)words * 4);
+}
+
+size_t ws_stream(int32_t, int64_t count, int32_t k, int32_t m, double delta) {
+  int32_t T = 0, B = 0;
+  const size_t b = stream_layout(count, k, m, delta, 1.0, &T, &B);
+  return B > kMaxStreamBuckets ? 0 : ws_align(b);
+}
+
 }  // namespace im
 
 extern "C" int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off,
@@ -233,26 +258,23 @@ extern "C" int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off,
                                const int32_t* lseeds, const int32_t* lcount,
                                const int64_t* lcover, double delta, double alpha,
                                int32_t* seeds, int32_t* nsel, int64_t* coverage, int32_t* info,
-                               void* stream) {
+                               void* ws, size_t ws_bytes, void* stream) {
   using namespace im;
   if (n <= 0 || count < 0 || count >= ((int64_t)1 << 31) || k <= 0 || m < 1 || m > 256 ||
       !inc_off || !lseeds || !lcount || !lcover || !seeds || !nsel || !coverage || !info ||
       !(delta > 0.0 && delta < 0.5) || !(alpha > 0.0 && alpha <= 1.0))
     return IM_EINVAL;
   // truncation length and bucket count (fp64 on the host)
-  int32_t T = (int32_t)ceil(alpha * (double)k);
-  T = std::max(1, std::min(T, k));
-  int32_t B = (int32_t)ceil(log((double)k) / log(1.0 + delta));
-  if (B < 1) B = 1;
+  int32_t T = 0, B = 0;
+  const size_t bytes = stream_layout(count, k, m, delta, alpha, &T, &B);
   if (B > kMaxStreamBuckets) return IM_EINVAL;
+  WsScope scope(ws, ws_bytes);
+  if (!scope.check(ws_align(bytes))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int64_t L = (int64_t)T * m;  // longest possible stream
   const int64_t words = (count + 31) / 32;
   const bool lds = words <= kLdsWords;
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t bytes = up((size_t)L * 4) + up((size_t)L * 8) * 2 + up(16) + up((size_t)B * 8) +
-                       up((size_t)B * k * 4) + up((size_t)B * 4) + up((size_t)B * 8) +
-                       (lds ? 0 : (size_t)B * (size_t)words * 4);
   void* p = nullptr;
   IM_TRY(scratch(s, kSlotStream, bytes, &p));
   char* c = (char*)p;

@@ -11,11 +11,12 @@ device-resident RRR pools and continuous batching.
   schedule and every round decision come from the library (im_imm_plan,
   im_imm_round, im_imm_theta), the same calls im_solve makes.
 * Server runs queries in S slots.  Each slot is a thread with its own HIP
-  stream (the library keeps scratch per stream and releases the GIL inside
-  its calls), so the work of queries admitted together overlaps on the GPU.
-  A query is admitted when a slot is free and its HBM footprint estimate fits
-  what the budget leaves after the resident bytes (pools and the library's
-  per-stream scratch, both measured); others wait in arrival order.
+  stream and its own workspace (the binding keeps one per stream; the
+  library allocates nothing and releases the GIL inside its calls), so the
+  work of queries admitted together overlaps on the GPU.  A query is
+  admitted when a slot is free and its HBM footprint estimate fits what the
+  budget leaves after the resident bytes (pools and the slots' workspaces,
+  both measured); others wait in arrival order.
 Every step on the device is a library kernel; this module schedules them.
 """
 from __future__ import annotations
@@ -150,8 +151,8 @@ class Admission:
     """Arrival-order admission by slots and HBM footprint (host logic only).
 
     A query is admitted when fewer than `slots` queries are in flight and its
-    footprint fits what the resident bytes (`held`: pools and library
-    scratch) and the in-flight queries leave of `budget`; the head of the
+    footprint fits what the resident bytes (`held`: pools and the slots'
+    workspaces) and the in-flight queries leave of `budget`; the head of the
     line is never overtaken.  A query larger than all that is admitted alone."""
 
     def __init__(self, slots: int, budget: int):
@@ -203,9 +204,9 @@ class Server:
     (graph, stream).  slots: queries in flight at once.  hbm_budget: bytes
     that admitted queries' footprint estimates may sum to.  streams: the
     slots' streams (one per slot, default priority), to be reused across
-    servers: the library keeps scratch per stream, so a server on streams
-    that served before starts with that scratch in place; None creates new
-    ones."""
+    servers: the binding keeps a workspace per stream, so a server on
+    streams that served before starts with those workspaces in place; None
+    creates new ones."""
 
     def __init__(self, graphs: dict, seed: int, slots: int = 4, hbm_budget: int = 64 << 30,
                  streams=None):
@@ -253,10 +254,10 @@ class Server:
         return cover + extension
 
     def resident_bytes(self) -> int:
-        """Pools plus the library's scratch on the slots' streams (measured)."""
+        """Pools plus the workspaces of the slots' streams (measured)."""
         with self.pools_lock:
             pools = sum(p0.nbytes() + p1.nbytes() for p0, p1 in self.pools.values())
-        return pools + sum(B.scratch_bytes(s) for s in self.streams)
+        return pools + sum(B.workspace_bytes(s) for s in self.streams)
 
     @property
     def max_in_flight(self) -> int:

@@ -21,8 +21,9 @@ def oracle_lib():
 
 
 def pytest_sessionfinish(session, exitstatus):
-    """Wait for the device and hand the library's scratch back before the
-    interpreter exits, so no HIP memory is freed by exit-time teardown."""
+    """Wait for the device and drop the cached workspaces and captured graphs
+    before the interpreter exits, so no HIP memory is freed by exit-time
+    teardown."""
     mod = sys.modules.get("paper_2408_10982_amd.binding")
     if mod is None or mod._lib is None:
         return

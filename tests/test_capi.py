@@ -46,18 +46,126 @@ def test_invalid_arguments_rejected_before_device_work():
     L = ctypes.CDLL(LIB)
     L.im_greedy_cover.restype = ctypes.c_int
     # k = 0 is invalid
+    z = ctypes.c_size_t(0)
     st = L.im_greedy_cover(ctypes.c_int32(10), ctypes.c_int64(5), None, None, ctypes.c_int64(0),
-                           None, None, ctypes.c_int32(0), None, None, None, None, None)
+                           None, None, ctypes.c_int32(0), None, None, None, None, None, z, None)
     assert st == -1
     L.im_stream_cover.restype = ctypes.c_int
     st = L.im_stream_cover(ctypes.c_int32(10), ctypes.c_int64(5), None, None, ctypes.c_int32(3),
                            ctypes.c_int32(2), None, None, None, ctypes.c_double(0.7),
-                           ctypes.c_double(1.0), None, None, None, None, None)
+                           ctypes.c_double(1.0), None, None, None, None, None, z, None)
     assert st == -1
     L.im_sample_rrr.restype = ctypes.c_int
     st = L.im_sample_rrr(None, ctypes.c_uint64(0), ctypes.c_uint32(0), ctypes.c_int64(0),
-                         ctypes.c_int64(1), None, None, ctypes.c_int64(0), None, None, None)
+                         ctypes.c_int64(1), None, None, ctypes.c_int64(0), None, None, None, z,
+                         None)
     assert st == -1
+
+
+class _WsShape(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("model", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("total", ctypes.c_int64), ("k", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("selector", ctypes.c_int32),
+                ("ntasks", ctypes.c_int32), ("full", ctypes.c_int32), ("num_cus", ctypes.c_int32)]
+
+
+def _ws_lib():
+    L = ctypes.CDLL(LIB)
+    L.im_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(_WsShape),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    L.im_workspace_need.argtypes = [ctypes.POINTER(ctypes.c_size_t),
+                                    ctypes.POINTER(ctypes.c_size_t)]
+    L.im_last_error.restype = ctypes.c_char_p
+    return L
+
+
+def _ws_size(L, op, **kw):
+    kw.setdefault("num_cus", 256)
+    sh = _WsShape(**kw)
+    b = ctypes.c_size_t()
+    assert L.im_workspace_size(op, ctypes.byref(sh), ctypes.byref(b)) == 0
+    return b.value
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_workspace_sizes_host_only():
+    """im_workspace_size is host arithmetic (num_cus given): it grows with
+    the problem, a full-speed workspace is at least the least one, and bad
+    shapes are rejected."""
+    L = _ws_lib()
+    WS_SAMPLE, WS_INCIDENCE, WS_GREEDY, WS_RANDGREEDI, WS_STREAM, WS_SOLVE = 1, 2, 3, 4, 5, 9
+    a = _ws_size(L, WS_SAMPLE, n=1 << 20, model=1, count=1 << 16, total=1 << 20)
+    b = _ws_size(L, WS_SAMPLE, n=1 << 20, model=1, count=1 << 17, total=1 << 21)
+    assert 0 < a < b
+    # staging: 4 bytes per member of capacity at least
+    assert a >= 4 * (1 << 20)
+    lo = _ws_size(L, WS_SAMPLE, n=1 << 22, model=0, count=1 << 20, total=1 << 24)
+    hi = _ws_size(L, WS_SAMPLE, n=1 << 22, model=0, count=1 << 20, total=1 << 24, full=1)
+    assert hi > lo and hi <= lo + (17 << 30)
+    assert _ws_size(L, WS_INCIDENCE, n=1 << 20, total=1 << 28, full=1) > \
+        _ws_size(L, WS_INCIDENCE, n=1 << 20, total=1 << 28)
+    assert _ws_size(L, WS_GREEDY, n=1000, count=5000, k=10) >= 4 * 1000 + 5000 + 80
+    assert _ws_size(L, WS_RANDGREEDI, n=1000, count=5000, k=10, m=8) >= 12 * 1000 + 8 * 5000
+    assert _ws_size(L, WS_STREAM, n=1000, count=5000, k=10, m=8, delta=0.077) > 0
+    g = _ws_size(L, WS_SOLVE, n=1 << 16, model=0, count=1 << 16, total=1 << 20, k=50,
+                 selector=1, m=8, delta=0.077)
+    assert g > 4 * (1 << 20) + 8 * (1 << 16)
+    b = ctypes.c_size_t()
+    bad = _WsShape(n=100, count=-1, num_cus=256)
+    assert L.im_workspace_size(3, ctypes.byref(bad), ctypes.byref(b)) == -1
+    assert L.im_workspace_size(12, ctypes.byref(_WsShape(n=1, num_cus=256)), ctypes.byref(b)) == -1
+    # GreediRIS sizes need a valid delta
+    assert L.im_workspace_size(5, ctypes.byref(_WsShape(n=10, count=10, k=4, m=2, num_cus=256)),
+                               ctypes.byref(b)) == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")
+def test_short_workspace_rejected_before_device_work():
+    """A workspace below a call's minimum returns IM_ENOMEM before any HIP
+    call (so this runs without a GPU), and im_workspace_need then reports
+    the bytes im_workspace_size gives for the same shape."""
+    L = _ws_lib()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: the call stops first
+    need = ctypes.c_size_t()
+    n, count, k, m = 1000, 5000, 10, 8
+    L.im_greedy_cover.restype = ctypes.c_int
+    st = L.im_greedy_cover(ctypes.c_int32(n), ctypes.c_int64(count), fake, fake,
+                           ctypes.c_int64(100), fake, fake, ctypes.c_int32(k), fake, fake, fake,
+                           fake, None, ctypes.c_size_t(0), None)
+    assert st == -3
+    assert L.im_workspace_need(ctypes.byref(need), None) == 0
+    assert need.value == _ws_size(L, 3, n=n, count=count, k=k)
+    assert b"im_workspace_size" in L.im_last_error()
+    # one byte short of the reported size is still short
+    st = L.im_greedy_cover(ctypes.c_int32(n), ctypes.c_int64(count), fake, fake,
+                           ctypes.c_int64(100), fake, fake, ctypes.c_int32(k), fake, fake, fake,
+                           fake, ctypes.c_void_p(1 << 30), ctypes.c_size_t(need.value - 1), None)
+    assert st == -3
+    L.im_randgreedi.restype = ctypes.c_int
+    st = L.im_randgreedi(ctypes.c_int32(n), ctypes.c_int64(count), fake, fake,
+                         ctypes.c_int64(100), fake, fake, ctypes.c_int32(k), ctypes.c_int32(m),
+                         ctypes.c_uint64(1), fake, fake, fake, fake, fake, None,
+                         ctypes.c_size_t(4096), None)
+    assert st == -3
+    assert L.im_workspace_need(ctypes.byref(need), None) == 0
+    assert need.value == _ws_size(L, 4, n=n, count=count, k=k, m=m)
+    L.im_stream_cover.restype = ctypes.c_int
+    st = L.im_stream_cover(ctypes.c_int32(n), ctypes.c_int64(count), fake, fake, ctypes.c_int32(k),
+                           ctypes.c_int32(m), fake, fake, fake, ctypes.c_double(0.077),
+                           ctypes.c_double(1.0), fake, fake, fake, fake, None, ctypes.c_size_t(0),
+                           None)
+    assert st == -3
+    assert L.im_workspace_need(ctypes.byref(need), None) == 0
+    assert need.value == _ws_size(L, 5, n=n, count=count, k=k, m=m, delta=0.077)
+    L.im_build_incidence.restype = ctypes.c_int
+    st = L.im_build_incidence(ctypes.c_int32(n), ctypes.c_int64(count), fake, fake,
+                              ctypes.c_int64(1 << 20), fake, fake, None, ctypes.c_size_t(0), None)
+    assert st == -3
+    assert L.im_workspace_need(ctypes.byref(need), None) == 0
+    assert need.value == _ws_size(L, 2, n=n, total=1 << 20)
+    want = ctypes.c_size_t()
+    assert L.im_workspace_need(None, ctypes.byref(want)) == 0 and want.value >= need.value
+    assert L.im_workspace_need(None, None) == -1
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libim.so not built")

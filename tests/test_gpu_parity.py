@@ -456,6 +456,90 @@ def test_solve_imm(im, name, k, eps, selector):
     assert got["stream_len"] == exp["stream_len"]
 
 
+def _ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def test_workspace_minimum_and_short(im):
+    """Through the C ABI with caller workspaces: one byte under the size
+    im_workspace_size reports is rejected (IM_ENOMEM, nothing written), the
+    reported minimum (one large-set worker, 2^24-pair incidence rounds)
+    gives the oracle's sets and covering subsets, and an im_solve given a
+    workspace far too small is rejected or runs short, reports what it
+    needs, and with that much (grown as the binding grows it) returns the
+    oracle's seeds."""
+    import ctypes as C
+    from paper_2408_10982_amd import binding as B
+    L = B.lib()
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    g = W.random_small_graph(49153, 4 * 49153, seed=11, p_hi=0.6)  # large IC sets
+    G = _prep(im, g)
+    gs = G.struct()
+    count = 300
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), 4242, 0, 0, count)
+    cap = int(o.off[-1])
+    need = im.workspace_size(im.WS_SAMPLE, n=g.n, model=g.model, count=count, total=cap)
+    _say("workspace sample", need)
+    off = torch.full((count + 1,), -7, dtype=torch.int64, device="cuda")
+    mem = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    total = C.c_int64(-1)
+    rc = L.im_sample_rrr(C.byref(gs), 4242, 0, 0, count, _ptr(off), _ptr(mem), cap,
+                         C.byref(total), None, _ptr(ws), need - 1, s)
+    assert rc == B.IM_ENOMEM and total.value == -1
+    assert B.workspace_need()[0] == need
+    torch.cuda.synchronize()
+    assert bool((off == -7).all())  # rejected before any device work
+    rc = L.im_sample_rrr(C.byref(gs), 4242, 0, 0, count, _ptr(off), _ptr(mem), cap,
+                         C.byref(total), None, _ptr(ws), need, s)
+    assert rc == B.IM_OK and total.value == cap
+    assert np.array_equal(_np(off), o.off) and np.array_equal(_np(mem), o.mem)
+    # the large sets asked for more workers than the minimum holds
+    assert B.workspace_need()[1] > need
+    # covering subsets at their minimum workspace
+    n = g.n
+    need = im.workspace_size(im.WS_INCIDENCE, n=n, total=cap)
+    _say("workspace incidence", need)
+    inc_off = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    inc_mem = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rc = L.im_build_incidence(n, count, _ptr(off), _ptr(mem), cap, _ptr(inc_off),
+                              _ptr(inc_mem), _ptr(ws), need, s)
+    assert rc == B.IM_OK
+    io, imem = O.incidence(n, o)
+    assert np.array_equal(_np(inc_off), io)
+    got, exp = _np(inc_mem), imem
+    for v in range(0, n, 97):
+        a, b = io[v], io[v + 1]
+        assert sorted(got[a:b]) == sorted(exp[a:b])
+    # IMM: a 1 MiB workspace is short; grow by the reported need
+    h = GRAPHS["lt_small"]()
+    H = _prep(im, h)
+    hs = H.struct()
+    kw = dict(selector=O.SEL_GREEDIRIS, m=8, delta=0.077, alpha=0.5, seed=3003, part_seed=4003)
+    exp = O.imm(h.model, h.in_off, h.in_src, _oracle_thr(h), 8, 0.4, **kw)
+    opts = B._SolveOpts(kw["selector"], kw["m"], kw["delta"], kw["alpha"], kw["seed"],
+                        kw["part_seed"], 0)
+    res = B._SolveResult()
+    seeds = (C.c_int32 * 8)()
+    size, tries = 1 << 20, 0
+    while True:
+        ws = torch.empty(size, dtype=torch.uint8, device="cuda")
+        rc = L.im_solve(C.byref(hs), 8, 0.4, C.byref(opts), seeds, C.byref(res), _ptr(ws), size,
+                        s)
+        tries += 1
+        _say("workspace solve", size, rc)
+        if rc != B.IM_ENOMEM:
+            break
+        nd = B.workspace_need()[0]
+        assert nd > size and tries < 8
+        size = nd + nd // 4
+    assert rc == B.IM_OK and tries >= 2
+    assert list(seeds)[:res.nsel] == exp["seeds"].tolist()
+    assert res.coverage == exp["coverage"] and res.theta == exp["theta"]
+
+
 @pytest.mark.parametrize("name,k,eps,selector,cap", [
     ("ic_sparse", 5, 0.3, O.SEL_GREEDY, 1 << 20), ("lt_small", 8, 0.2, O.SEL_GREEDIRIS, 1 << 20),
     ("rmat12", 16, 0.1, O.SEL_GREEDY, 1 << 16), ("rmat12", 16, 0.1, O.SEL_GREEDIRIS, 1 << 16),
@@ -519,7 +603,7 @@ def test_serving_results_equal_alone(im):
     """Queries served together from shared, growing sample pools (3 slots on
     3 streams) return exactly what im_solve returns for each query alone;
     with a one-byte HBM budget admission serialises them, same results.  The
-    second server runs on the first one's streams (and their scratch)."""
+    second server runs on the first one's streams (and their workspaces)."""
     _say("serving")
     from paper_2408_10982_amd import serve as S
     gs = {"ic": W.random_small_graph(3000, 15000, seed=21, p_hi=0.2),

@@ -41,7 +41,7 @@ def test_admission_refuses_over_budget_and_keeps_order():
 
 
 def test_admission_counts_resident_bytes():
-    """Resident bytes (pools, library scratch) come off the budget before the
+    """Resident bytes (pools, workspaces) come off the budget before the
     in-flight queries' footprints; the first query is admitted regardless."""
     A = _admission()(slots=4, budget=100)
     for j in range(3):
