@@ -84,6 +84,9 @@ typedef struct {
   const uint32_t* thr;     /* [device] round_up(E, 4) entries from im_prepare_graph */
   int32_t model;           /* IM_IC or IM_LT, as given to im_prepare_graph */
   const double* skip;      /* [device] n entries from im_prepare_graph (IC), or NULL */
+  const uint32_t* lt_index;  /* [device] im_lt_index_size(E) entries from im_prepare_graph
+                                (LT), or NULL (the kept edge is then found by binary
+                                search; the sets are the same either way) */
 } im_graph;
 
 /* Sampling statistics of one im_sample_rrr call.  The counts are exact and
@@ -222,6 +225,14 @@ int im_tune_get(int32_t key, int64_t* value);
  *      in-edges of v up to and including e, 0xFFFFFFFF) (live-edge reading of
  *      LT: v keeps in-edge e with probability w_e, none with 1 - sum w).
  *  thr[E .. round_up(E,4)) is written 0.
+ *  LT search index (lt_index may be NULL): level k = 1..7 holds, for every
+ *      window of 16^k consecutive edge ids, the threshold of its last edge
+ *      (of edge E-1 for the final partial window), padded to whole groups of
+ *      16 entries (64 bytes), levels one after the other.  The sampler finds
+ *      the kept in-edge of v by a 16-ary search: one 64-byte group per level
+ *      from the lowest level whose window holds all of v's in-edges, down to
+ *      the edges themselves -- about log16(indeg) + 1 dependent loads instead
+ *      of log2(indeg).
  *  IC run-length table (skip may be NULL: one coin per in-edge everywhere):
  *      skip[v] = 1 / log(1 - q/2^32) when v has >= 2 in-edges that all share
  *      one threshold q with 0 < q < 0xFFFFFFFF (weighted cascade gives every
@@ -235,6 +246,7 @@ int im_tune_get(int32_t key, int64_t* value);
  *      bit for bit.
  * in_off [device] n+1; in_src [device] E; weight [device] E fp32;
  * thr [device] round_up(E,4); skip [device] n fp64 or NULL (ignored for LT);
+ * lt_index [device] im_lt_index_size(E) uint32 or NULL (ignored for IC);
  * ws [device] 256 bytes.  Synchronises `stream`; returns IM_EINVAL if
  * in_off is not a valid CSR offset array (nothing else is then read), or if a
  * source id is outside [0,n), or a weight is NaN, negative, infinite, or (IC)
@@ -242,7 +254,10 @@ int im_tune_get(int32_t key, int64_t* value);
  */
 int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off, const int32_t* in_src,
                      const float* weight, int32_t model, uint32_t* thr, double* skip,
-                     void* ws, size_t ws_bytes, void* stream);
+                     uint32_t* lt_index, void* ws, size_t ws_bytes, void* stream);
+/* Entries of the LT search index for num_edges edges (host only):
+ * sum over k = 1..7 of round_up(ceil(E / 16^k), 16). */
+int im_lt_index_size(int64_t num_edges, int64_t* entries);
 
 /*
  * RRR sampling (Def. 2.3 and Sec. 2.1; Alg. 1 Sample, Alg. 3 sampling step).

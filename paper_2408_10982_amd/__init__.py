@@ -11,7 +11,7 @@ from .binding import (IC, LT, SEL_GREEDIRIS, SEL_GREEDY, SEL_RANDGREEDI, EXPORTS
                       WS_BATCH, WS_FORWARD, WS_GREEDY, WS_INCIDENCE, WS_INFLUENCE, WS_OFFLINE,
                       WS_OPIM, WS_PREPARE_GRAPH, WS_RANDGREEDI, WS_SAMPLE, WS_SOLVE, WS_STREAM,
                       build_incidence, drop_workspaces, greedi_offline, greedy_cover,
-                      greedy_cover_static, imm_plan, influence, lib, opim, prepare_forward,
+                      greedy_cover_static, imm_plan, influence, lib, lt_index_size, opim, prepare_forward,
                       prepare_graph, randgreedi, release, sample_into, sample_rrr, solve,
                       solve_batch, stream_cover, tune_get, tune_set, version, workspace_bytes,
                       workspace_need, workspace_size)
@@ -22,7 +22,7 @@ __all__ = ["IC", "LT", "SEL_GREEDY", "SEL_GREEDIRIS", "SEL_RANDGREEDI", "EXPORTS
            "WS_FORWARD", "WS_GREEDY", "WS_INCIDENCE", "WS_INFLUENCE", "WS_OFFLINE", "WS_OPIM",
            "WS_PREPARE_GRAPH", "WS_RANDGREEDI", "WS_SAMPLE", "WS_SOLVE", "WS_STREAM",
            "build_incidence", "drop_workspaces", "greedi_offline", "greedy_cover",
-           "greedy_cover_static", "imm_plan", "influence", "lib", "opim", "prepare_forward",
+           "greedy_cover_static", "imm_plan", "influence", "lib", "lt_index_size", "opim", "prepare_forward",
            "prepare_graph", "randgreedi", "release", "sample_into", "sample_rrr", "solve",
            "solve_batch", "stream_cover", "tune_get", "tune_set", "version", "workspace_bytes",
            "workspace_need", "workspace_size"]

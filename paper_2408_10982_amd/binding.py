@@ -37,7 +37,8 @@ EXPORTS = ("im_version", "im_last_error", "im_release", "im_prepare_graph", "im_
            "im_build_incidence", "im_greedy_cover", "im_greedy_cover_static", "im_randgreedi", "im_stream_cover", "im_greedi_offline",
            "im_prepare_forward", "im_influence", "im_opim",
            "im_solve", "im_solve_batch", "im_imm_plan", "im_imm_round", "im_imm_theta",
-           "im_workspace_size", "im_workspace_need", "im_tune_set", "im_tune_get")
+           "im_workspace_size", "im_workspace_need", "im_lt_index_size", "im_tune_set",
+           "im_tune_get")
 
 
 class ImError(RuntimeError):
@@ -50,7 +51,7 @@ class ImError(RuntimeError):
 class _Graph(C.Structure):
     _fields_ = [("n", C.c_int32), ("num_edges", C.c_int64), ("in_off", C.c_void_p),
                 ("in_src", C.c_void_p), ("thr", C.c_void_p), ("model", C.c_int32),
-                ("skip", C.c_void_p)]
+                ("skip", C.c_void_p), ("lt_index", C.c_void_p)]
 
 
 class _Stats(C.Structure):
@@ -130,7 +131,8 @@ def lib():
         L.im_last_error.restype = C.c_char_p
         L.im_release.argtypes = []
         W = [P, C.c_size_t]  # (ws, ws_bytes)
-        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P] + W + [P]
+        L.im_prepare_graph.argtypes = [I32, I64, P, P, P, I32, P, P, P] + W + [P]
+        L.im_lt_index_size.argtypes = [I64, C.POINTER(C.c_int64)]
         L.im_sample_rrr.argtypes = [C.POINTER(_Graph), U64, U32, I64, I64, P, P, I64,
                                     C.POINTER(C.c_int64), C.POINTER(_Stats)] + W + [P]
         L.im_build_incidence.argtypes = [I32, I64, P, P, I64, P, P] + W + [P]
@@ -280,22 +282,33 @@ class Graph:
     in_src: torch.Tensor   # int32 [E]
     thr: torch.Tensor      # int32 storage of uint32 thresholds, [round_up(E, 4)]
     skip: torch.Tensor | None = None   # float64 [n]: IC run-length table
+    lt_index: torch.Tensor | None = None   # int32 storage of the LT search index
 
     def struct(self) -> _Graph:
         return _Graph(self.n, self.num_edges, self.in_off.data_ptr(),
                       self.in_src.data_ptr() if self.num_edges else None,
                       self.thr.data_ptr(), self.model,
-                      self.skip.data_ptr() if self.skip is not None else None)
+                      self.skip.data_ptr() if self.skip is not None else None,
+                      self.lt_index.data_ptr() if self.lt_index is not None else None)
 
     def hbm_bytes(self) -> int:
         return (4 * (self.in_off.numel() + self.in_src.numel() + self.thr.numel()) +
-                (8 * self.skip.numel() if self.skip is not None else 0))
+                (8 * self.skip.numel() if self.skip is not None else 0) +
+                (4 * self.lt_index.numel() if self.lt_index is not None else 0))
+
+
+def lt_index_size(num_edges: int) -> int:
+    """Entries of the LT search index for num_edges edges (im_lt_index_size)."""
+    e = C.c_int64()
+    _check(lib().im_lt_index_size(num_edges, C.byref(e)), "im_lt_index_size")
+    return int(e.value)
 
 
 def prepare_graph(in_off, in_src, weight, model: int, device="cuda", stream=None,
-                  run_length: bool = True) -> Graph:
+                  run_length: bool = True, lt_index: bool = True) -> Graph:
     """Uploads an in-edge CSR with fp32 weights and derives the thresholds
-    (and, for IC, the run-length table unless run_length is False)."""
+    (and, for IC, the run-length table unless run_length is False; for LT,
+    the search index unless lt_index is False)."""
     in_off = torch.as_tensor(in_off, dtype=torch.int32).to(device).contiguous()
     in_src = torch.as_tensor(in_src, dtype=torch.int32).to(device).contiguous()
     weight = torch.as_tensor(weight, dtype=torch.float32).to(device).contiguous()
@@ -304,10 +317,12 @@ def prepare_graph(in_off, in_src, weight, model: int, device="cuda", stream=None
     thr = torch.empty(max((E + 3) // 4 * 4, 4), dtype=torch.int32, device=device)
     skip = (torch.empty(n, dtype=torch.float64, device=device)
             if model == IC and run_length else None)
+    index = (torch.empty(max(lt_index_size(E), 16), dtype=torch.int32, device=device)
+             if model == LT and lt_index else None)
     _call_ws(lib().im_prepare_graph, "im_prepare_graph",
              (n, E, _ptr(in_off), _ptr(in_src) if E else None, _ptr(weight) if E else None,
-              model, _ptr(thr), _ptr(skip)), stream)
-    return Graph(n, E, model, in_off, in_src, thr, skip)
+              model, _ptr(thr), _ptr(skip), _ptr(index)), stream)
+    return Graph(n, E, model, in_off, in_src, thr, skip, index)
 
 
 @dataclass

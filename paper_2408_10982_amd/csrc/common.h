@@ -20,6 +20,9 @@ constexpr int kWave = 64;
 // Random-number domains and counter layout (key = seed, counter =
 // (id >> 2, sample, tag, stream), word id & 3).
 constexpr uint32_t kTagRoot = 0, kTagEdge = 1, kTagVert = 2, kTagPart = 3;
+// Levels of the LT search index (16^7 edge ids per top window: every vertex's
+// in-edges lie in one aligned group of 16 top windows, as E < 2^31).
+constexpr int kLtLevels = 7;
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Each 32x32 product is
 // formed as one 64-bit product (a single v_mad_u64_u32 on gfx950) rather than
@@ -254,6 +257,9 @@ void scratch_need(size_t more);
 void scratch_wish(size_t more);
 // `bytes` rounded up to the workspace's alignment (256).
 size_t ws_align(size_t bytes);
+
+// Entries of the LT search index for E edges (im_lt_index_size).
+int64_t lt_index_entries(int64_t E);
 
 // Workspace bytes of the entry points (the op of im_workspace_size);
 // sampling, covering subsets and the cover kernels declare theirs beside

@@ -5,6 +5,8 @@
 // read as the live-edge process, each vertex keeps in-edge e with probability
 // w_e; the inclusive integer prefix of floor(w * 2^32) over v's in-edges lets
 // the sampler pick the kept edge with one draw and a search.
+#include <algorithm>
+
 #include "common.h"
 
 namespace im {
@@ -111,12 +113,38 @@ __global__ __launch_bounds__(256) void k_ic_skip(int32_t n, const int32_t* __res
   skip[v] = out;
 }
 
+// LT search index, level k: entry w = threshold of the last edge of window w
+// (16^k edge ids), clamped to edge E-1; padding entries 0.
+__global__ void k_lt_index(const uint32_t* __restrict__ thr, int64_t E, int k, int64_t nw,
+                           int64_t nw_pad, uint32_t* __restrict__ out) {
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw_pad;
+       w += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t last = ((w + 1) << (4 * k)) - 1;
+    out[w] = w < nw ? thr[last < E ? last : E - 1] : 0u;
+  }
+}
+
+int64_t lt_index_entries(int64_t E) {
+  int64_t t = 0;
+  for (int k = 1; k <= kLtLevels; ++k) {
+    const int64_t nw = (E + ((int64_t)1 << (4 * k)) - 1) >> (4 * k);
+    t += (nw + 15) & ~(int64_t)15;
+  }
+  return t;
+}
+
 }  // namespace im
+
+extern "C" int im_lt_index_size(int64_t num_edges, int64_t* entries) {
+  if (num_edges < 0 || !entries) return IM_EINVAL;
+  *entries = im::lt_index_entries(num_edges);
+  return IM_OK;
+}
 
 extern "C" int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_off,
                                 const int32_t* in_src, const float* weight, int32_t model,
-                                uint32_t* thr, double* skip, void* ws, size_t ws_bytes,
-                                void* stream) {
+                                uint32_t* thr, double* skip, uint32_t* lt_index, void* ws,
+                                size_t ws_bytes, void* stream) {
   using namespace im;
   if (n <= 0 || num_edges < 0 || num_edges >= (int64_t)0x7FFFFFFF || !in_off || !thr ||
       (num_edges > 0 && (!weight || !in_src)) || (model != IM_IC && model != IM_LT))
@@ -150,6 +178,18 @@ extern "C" int im_prepare_graph(int32_t n, int64_t num_edges, const int32_t* in_
   if (model == IM_IC && skip) {
     k_ic_skip<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, in_off, thr, skip);
     IM_HIP(hipGetLastError());
+  }
+  if (model == IM_LT && lt_index && E > 0) {
+    int64_t base = 0;
+    for (int k = 1; k <= kLtLevels; ++k) {
+      const int64_t nw = (E + ((int64_t)1 << (4 * k)) - 1) >> (4 * k);
+      const int64_t nw_pad = (nw + 15) & ~(int64_t)15;
+      const int64_t blocks = std::min<int64_t>((nw_pad + 255) / 256, 65536);
+      k_lt_index<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(thr, E, k, nw, nw_pad,
+                                                             lt_index + base);
+      IM_HIP(hipGetLastError());
+      base += nw_pad;
+    }
   }
   IM_HIP(hipMemcpyAsync(&hf, flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   IM_HIP(hipStreamSynchronize(s));

@@ -14,6 +14,8 @@ struct TaskDesc {
   const int32_t* in_src;
   const uint32_t* thr;
   const double* skip;      // IC run-length table or nullptr
+  const uint32_t* lt_index;  // LT search index or nullptr
+  int64_t num_edges;
   int32_t n;
   int32_t model;
   uint32_t seed_lo, seed_hi;

@@ -108,6 +108,8 @@ struct GView {
   const int32_t* in_src;
   const uint32_t* thr;
   const double* skip;
+  const uint32_t* lt_index;
+  int64_t ne;  // edges
   uint32_t n, seed_lo, seed_hi, stream;
 };
 
@@ -117,6 +119,8 @@ __device__ __forceinline__ GView view_of(const TaskDesc& T) {
   g.in_src = T.in_src;
   g.thr = T.thr;
   g.skip = T.model == IM_IC ? T.skip : nullptr;
+  g.lt_index = T.model == IM_LT ? T.lt_index : nullptr;
+  g.ne = T.num_edges;
   g.n = (uint32_t)T.n;
   g.seed_lo = T.seed_lo;
   g.seed_hi = T.seed_hi;
@@ -318,6 +322,111 @@ __device__ __forceinline__ void rl_walks(bool rl, uint32_t v, int32_t a, int32_t
 __device__ __forceinline__ uint32_t ceil_log2_plus1(int32_t d) {
   // ceil(log2(d + 1)) for d >= 1
   return 32u - (uint32_t)__clz((uint32_t)d);
+}
+
+// ----------------------------------------------------------- LT kept edge
+// Vertex v keeps its first in-edge e (in [a, b)) with thr[e] > r or thr[e]
+// saturated; thr is non-decreasing over [a, b), so "taken" is false on a
+// prefix and true after it.
+__device__ __forceinline__ bool lt_taken(uint32_t c, uint32_t r) {
+  return c > r || c == 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint32_t u4_at(const uint4 (&g)[4], int q) {
+  const uint4 x = g[q >> 2];
+  return (q & 3) == 0 ? x.x : (q & 3) == 1 ? x.y : (q & 3) == 2 ? x.z : x.w;
+}
+
+// Entries of the 16-entry group g at positions [lo, hi) that are not taken.
+__device__ __forceinline__ int not_taken16(const uint4 (&g)[4], int lo, int hi, uint32_t r) {
+  int c = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) c += (q >= lo && q < hi && !lt_taken(u4_at(g, q), r)) ? 1 : 0;
+  return c;
+}
+
+__device__ __forceinline__ int64_t lt_level_base(int64_t E, int k) {
+  int64_t base = 0;
+  for (int j = 1; j < k; ++j) {
+    const int64_t nw = (E + ((int64_t)1 << (4 * j)) - 1) >> (4 * j);
+    base += (nw + 15) & ~(int64_t)15;
+  }
+  return base;
+}
+
+// The kept in-edge of a vertex with in-edges [a, b) (a < b) under draw r:
+// its id, or b if none; *src = its source.  With the graph's search index,
+// a 16-ary descent: the top level is the lowest whose aligned group of 16
+// windows holds all of [a, b); at each level the windows before the first
+// whose last edge is taken are counted in one 64-byte group (the windows
+// entirely inside [a, b) only: the one holding b - 1 is where the search
+// ends if no earlier one is taken); the last group holds the edges
+// themselves, loaded with their sources.  Without the index, a binary search.
+__device__ __forceinline__ int32_t lt_pick(const GView& G, int32_t a, int32_t b, uint32_t r,
+                                           int32_t* src) {
+  if (!G.lt_index) {
+    int32_t lo = a, hi = b;
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if (lt_taken(G.thr[mid], r))
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    if (lo < b) *src = G.in_src[lo];
+    return lo;
+  }
+  const int64_t A = a, Bm = (int64_t)b - 1;
+  int K = 0;
+  while (K < kLtLevels && (A >> (4 * (K + 1))) != (Bm >> (4 * (K + 1)))) ++K;
+  int64_t w = A >> 4;  // group of edges searched last (a level-1 window)
+  if (K > 0) {
+    int64_t base = lt_level_base(G.ne, K);
+    {  // top level: windows [wa, wb) of one group
+      const int64_t wa = A >> (4 * K), wb = Bm >> (4 * K), g = wa >> 4;
+      const uint4* p = reinterpret_cast<const uint4*>(G.lt_index + base + 16 * g);
+      const uint4 q[4] = {p[0], p[1], p[2], p[3]};
+      w = wa + not_taken16(q, (int)(wa - 16 * g), (int)(wb - 16 * g), r);
+    }
+    for (int k = K - 1; k >= 1; --k) {
+      base -= ((((G.ne + ((int64_t)1 << (4 * k)) - 1) >> (4 * k)) + 15) & ~(int64_t)15);
+      const int64_t wa = A >> (4 * k), wb = Bm >> (4 * k);
+      const int64_t lo = max(16 * w, wa), hi = min(16 * w + 16, wb);
+      const uint4* p = reinterpret_cast<const uint4*>(G.lt_index + base + 16 * w);
+      const uint4 q[4] = {p[0], p[1], p[2], p[3]};
+      w = lo + not_taken16(q, (int)(lo - 16 * w), (int)(hi - 16 * w), r);
+    }
+  }
+  // the edges: group w within [a, b)
+  const int64_t e0 = 16 * w;
+  const int lo = (int)(max(e0, A) - e0), hi = (int)(min(e0 + 16, (int64_t)b) - e0);
+  const int64_t e4 = (G.ne + 3) & ~(int64_t)3;  // thr holds round_up(E, 4) entries
+  const uint4* pt = reinterpret_cast<const uint4*>(G.thr + e0);
+  uint4 t[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = e0 + 4 * q < e4 ? pt[q] : make_uint4(0u, 0u, 0u, 0u);
+  const bool vec_src = e0 + 16 <= G.ne && ((uintptr_t)G.in_src & 15u) == 0;
+  int4 sv[4] = {};
+  if (vec_src) {
+    const int4* ps = reinterpret_cast<const int4*>(G.in_src + e0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sv[q] = ps[q];
+  }
+  const int idx = lo + not_taken16(t, lo, hi, r);
+  if (idx >= hi) return b;
+  if (vec_src) {
+    int32_t u = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int4 x = sv[q >> 2];
+      const int32_t y = (q & 3) == 0 ? x.x : (q & 3) == 1 ? x.y : (q & 3) == 2 ? x.z : x.w;
+      u = q == idx ? y : u;
+    }
+    *src = u;
+  } else {
+    *src = G.in_src[e0 + idx];
+  }
+  return (int32_t)(e0 + idx);
 }
 
 // A set handed from the small to the large path resumes from the state it had
@@ -1147,18 +1256,9 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         if (a == b) break;
         s_ex += ceil_log2_plus1(b - a);
         const uint32_t r = draw1(seed, kTagVert, G.stream, i, (uint32_t)v);
-        int32_t lo = a, hi = b;
-        while (lo < hi) {
-          const int32_t mid = lo + ((hi - lo) >> 1);
-          const uint32_t c = G.thr[mid];
-          if (c > r || c == 0xFFFFFFFFu)
-            hi = mid;
-          else
-            lo = mid + 1;
-        }
-        if (lo == b) break;
+        int32_t u = 0;
+        if (lt_pick(G, a, b, r, &u) == b) break;
         ++s_lv;
-        const int32_t u = G.in_src[lo];
         const uint32_t bit = 1u << (u & 31);
         if (bm[u >> 5] & bit) break;
         bm[u >> 5] |= bit;
@@ -1284,9 +1384,12 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
 // A walk's members are kept twice per lane: in order in the lane's list in
 // HBM (what is written out), and as a 256-bit Bloom filter in registers.  A
 // clear filter bit proves a vertex new, so the common step appends without
-// reading anything back; only on a set bit is the list scanned (16-byte
-// loads, eight members each round) for an exact answer.  Nothing has to be
-// cleared between walks.
+// reading anything back; only on a set bit is the list scanned for an exact
+// answer.  A short list (kLtOwnScan members) is scanned by its own lane; a
+// longer one by the whole wavefront, 256 members per round (one 1 KB
+// coalesced load), since the filter fills up on long walks and a lane
+// scanning its own list would make such a walk quadratic in its length.
+// Nothing has to be cleared between walks.
 struct Bloom {
   uint64_t w0, w1, w2, w3;
 };
@@ -1325,6 +1428,8 @@ __device__ __forceinline__ bool list_has(const int32_t* Ls, int32_t len, int32_t
   }
   return false;
 }
+
+constexpr int32_t kLtOwnScan = 32;
 
 // One lane per walk.  Lanes take new samples as their walks end (aggregated
 // per wave), so a long walk does not hold up the other 63 lanes.
@@ -1380,7 +1485,9 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
       pnext += min(avail, (unsigned long long)__popcll(need));
     }
     if (!__any(have)) break;
-    bool fin = false, over = false;
+    bool fin = false, over = false, cand = false, seen = false, wide = false;
+    int32_t u = 0;
+    uint32_t h = 0;
     if (have) {
       const int32_t a = G.in_off[v], b = G.in_off[v + 1];
       if (a == b) {
@@ -1388,32 +1495,49 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
       } else {
         s_ex += ceil_log2_plus1(b - a);
         const uint32_t r = draw1(seed, kTagVert, G.stream, i, (uint32_t)v);
-        int32_t lo = a, hi = b;
-        while (lo < hi) {
-          const int32_t mid = lo + ((hi - lo) >> 1);
-          const uint32_t c = G.thr[mid];
-          if (c > r || c == 0xFFFFFFFFu)
-            hi = mid;
-          else
-            lo = mid + 1;
-        }
-        if (lo == b) {
+        if (lt_pick(G, a, b, r, &u) == b) {
           fin = true;
         } else {
           ++s_lv;
-          const int32_t u = G.in_src[lo];
-          const uint32_t h = bloom_bit(u);
-          if (bloom_has(bl, h) && list_has(Ls, len, u)) {
-            fin = true;
-          } else if (len == kLtCap) {
-            fin = true;
-            over = true;
-          } else {
-            bloom_add(bl, h);
-            Ls[len++] = u;
-            v = u;
+          h = bloom_bit(u);
+          cand = true;
+          if (bloom_has(bl, h)) {
+            if (len <= kLtOwnScan)
+              seen = list_has(Ls, len, u);
+            else
+              wide = true;
           }
         }
+      }
+    }
+    // long lists: the wavefront scans each in turn (a lane's list entries
+    // were stored by that lane in earlier rounds of this loop)
+    uint64_t pend = __ballot(wide);
+    if (pend) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    while (pend) {
+      const int j = __ffsll((long long)pend) - 1;
+      pend &= pend - 1;
+      const int32_t lj = __shfl(len, j, kWave), uj = __shfl(u, j, kWave);
+      const int32_t* Lj = lane_list + (gl - (size_t)lane + (size_t)j) * kLtCap;
+      bool hit = false;
+      for (int32_t p = 4 * lane; p < lj; p += 4 * kWave) {
+        const int4 x = *reinterpret_cast<const int4*>(Lj + p);
+        hit |= (x.x == uj) | ((p + 1 < lj) & (x.y == uj)) | ((p + 2 < lj) & (x.z == uj)) |
+               ((p + 3 < lj) & (x.w == uj));
+      }
+      const bool any = __any(hit);
+      if (lane == j) seen = any;
+    }
+    if (cand) {
+      if (seen) {
+        fin = true;
+      } else if (len == kLtCap) {
+        fin = true;
+        over = true;
+      } else {
+        bloom_add(bl, h);
+        Ls[len++] = u;
+        v = u;
       }
     }
     const bool emit = fin && !over;
@@ -1910,7 +2034,8 @@ size_t ws_sample(int num_cus, int64_t count, int64_t capacity, int32_t max_n, in
 int graph_ok(const im_graph* g) {
   if (!g || g->n <= 0 || g->num_edges < 0 || g->num_edges >= (int64_t)0x7FFFFFFF ||
       !g->in_off || (g->num_edges > 0 && (!g->in_src || !g->thr)) ||
-      (g->model != IM_IC && g->model != IM_LT) || ((uintptr_t)g->thr & 15u))
+      (g->model != IM_IC && g->model != IM_LT) || ((uintptr_t)g->thr & 15u) ||
+      ((uintptr_t)g->lt_index & 15u))
     return 0;
   return 1;
 }
@@ -1922,6 +2047,8 @@ TaskDesc task_of(const im_graph* g, uint64_t seed, uint32_t stream_tag, int64_t 
   T.in_src = g->in_src;
   T.thr = g->thr;
   T.skip = g->skip;
+  T.lt_index = g->lt_index;
+  T.num_edges = g->num_edges;
   T.n = g->n;
   T.model = g->model;
   T.seed_lo = (uint32_t)seed;

@@ -106,6 +106,40 @@ def test_sample_large_sets_bitmap_tiers(im, n, shape):
     assert (r.examined, r.live) == (o.examined, o.live)
 
 
+def test_lt_index_hub_degrees(im):
+    """LT kept edges through the search index (a 16-ary descent over up to
+    five levels here) equal binary search's and the oracle's at every
+    in-degree: a 70,000-edge hub every walk can step to, and 2,000 vertices of
+    in-degree 1..600 whose edge ranges straddle 16-, 256- and 4096-edge
+    boundaries at every alignment; weights sum to 0.9 per vertex, so some
+    vertices keep no edge."""
+    _say("lt index hub degrees")
+    rng = np.random.default_rng(21)
+    n = 70001
+    src = [np.arange(1, n), np.zeros(n - 1, np.int64)]
+    dst = [np.zeros(n - 1, np.int64), np.arange(1, n)]
+    for v in range(1, 2001):
+        d = int(rng.integers(1, 601))
+        src.append(rng.integers(0, n, d))
+        dst.append(np.full(d, v))
+    edges = np.stack([np.concatenate(src), np.concatenate(dst)], axis=1)
+    g = W.tiny_graph(n, edges, np.ones(edges.shape[0], np.float32), model=W.LT)
+    g.weight = (W.lt_normalized_weights(g.in_off, 22) * np.float32(0.9)).astype(np.float32)
+    assert int(np.diff(g.in_off).max()) == 70000
+    Gi = im.prepare_graph(g.in_off, g.in_src, g.weight, g.model)
+    Gb = im.prepare_graph(g.in_off, g.in_src, g.weight, g.model, lt_index=False)
+    assert Gi.lt_index is not None and Gb.lt_index is None
+    assert Gi.lt_index.numel() == im.lt_index_size(g.num_edges)
+    o = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), 5150, 0, 0, 6000)
+    for G in (Gi, Gb):
+        r = im.sample_rrr(G, seed=5150, stream_tag=0, first=0, count=6000)
+        assert np.array_equal(_np(r.off), o.off)
+        assert np.array_equal(_np(r.mem), o.mem)
+        assert (r.examined, r.live) == (o.examined, o.live)
+    # most walks pass through the hub
+    assert int((o.mem == 0).sum()) > 3000
+
+
 def test_sample_edge_cases(im):
     _say("sample edge cases")
     g = GRAPHS["ic_sparse"]()
