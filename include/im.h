@@ -126,7 +126,7 @@ typedef enum {
   IM_WS_SAMPLE = 1,         /* im_sample_rrr: n, model, count, total = capacity */
   IM_WS_INCIDENCE = 2,      /* im_build_incidence: n, total */
   IM_WS_GREEDY = 3,         /* im_greedy_cover: n, count, k */
-  IM_WS_RANDGREEDI = 4,     /* im_randgreedi: n, count, k, m */
+  IM_WS_RANDGREEDI = 4,     /* im_randgreedi: n, count, total, k, m */
   IM_WS_STREAM = 5,         /* im_stream_cover: count, k, m, delta (alpha = 1 bound) */
   IM_WS_OFFLINE = 6,        /* im_greedi_offline: n, count, k, m */
   IM_WS_FORWARD = 7,        /* im_prepare_forward: n */
@@ -346,7 +346,9 @@ int im_greedy_cover_static(int32_t n, int64_t count, const int64_t* off, const i
  * lseeds [device] m*k int32, row p = part p's picks in order, -1 past
  * lcount[p]; lgains [device] m*k int64; lcount [device] m int32;
  * lcover [device] m int64 = C(S_p).  1 <= m <= 256.  Workspace: 12n + m count
- * + 8mk bytes and change.  Asynchronous.
+ * + 4 total + 8mk bytes and change (the count position of every member is
+ * stored beside the members once, so the local steps' member walks find the
+ * partition and the count without random lookups).  Asynchronous.
  */
 int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const int32_t* mem,
                   int64_t total, const int64_t* inc_off, const int32_t* inc_mem, int32_t k,

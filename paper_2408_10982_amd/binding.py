@@ -413,7 +413,8 @@ def randgreedi(n: int, rrr: RRR, inc_off, inc_mem, k: int, m: int, part_seed: in
     _call_ws(lib().im_randgreedi, "im_randgreedi",
              (n, rrr.count, _ptr(rrr.off), _ptr(rrr.mem), rrr.total, _ptr(inc_off),
               _ptr(inc_mem), k, m, part_seed, _ptr(part), _ptr(ls), _ptr(lg), _ptr(lc),
-              _ptr(lv)), stream, workspace_size(WS_RANDGREEDI, n=n, count=rrr.count, k=k, m=m))
+              _ptr(lv)), stream,
+             workspace_size(WS_RANDGREEDI, n=n, count=rrr.count, total=rrr.total, k=k, m=m))
     return part, ls, lg, lc, lv
 
 

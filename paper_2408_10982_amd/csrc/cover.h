@@ -25,11 +25,17 @@ struct CoverArgs {
   const int32_t* __restrict__ order;     // n: vertex at each position (nullptr: identity)
   const int32_t* __restrict__ pos_of;    // n: position of each vertex (nullptr: identity)
   const uint8_t* __restrict__ part;      // n: partition of each vertex (RandGreedi), or nullptr
+  const int32_t* __restrict__ mpos;      // off[count]: count position of each member
+                                         // (RandGreedi: read in place of mem, part and
+                                         // pos_of), or nullptr
   const int64_t* __restrict__ pbase;     // m+1: positions of partition p (nullptr: [0, n))
   const int32_t* __restrict__ kpart;     // m: picks per partition (nullptr: k)
   const int64_t* __restrict__ koff;      // m: first output slot (nullptr: p * k)
   const int64_t* __restrict__ sbase;     // m+1: samples of partition p (nullptr: shared)
   int32_t local_ids;                     // members and seeds are partition-local ids
+  int32_t pos_keys;                      // argmax keys carry the position, not the vertex
+                                         // (order ascending within each partition, so the
+                                         // lowest position of a count is its lowest id)
   uint32_t* __restrict__ cnt;            // n, by position: uncovered samples of the vertex
   uint8_t* __restrict__ covered;         // sbase ? count : m * count
   unsigned long long* __restrict__ gmax; // k * m argmax keys, one row per pick
@@ -54,7 +60,7 @@ int launch_cover(CoverArgs& A, hipStream_t s);
 // Workspace bytes of im_greedy_cover and im_randgreedi (each call's scratch
 // and the scans it runs).
 size_t ws_greedy(int32_t n, int64_t count, int32_t k);
-size_t ws_randgreedi(int32_t n, int64_t count, int32_t k, int32_t m);
+size_t ws_randgreedi(int32_t n, int64_t count, int64_t total, int32_t k, int32_t m);
 // Workspace bytes of im_stream_cover and im_greedi_offline.
 size_t ws_stream(int32_t n, int64_t count, int32_t k, int32_t m, double delta);
 size_t ws_offline(int32_t n, int64_t count, int32_t k, int32_t m);

@@ -86,46 +86,55 @@ __global__ __launch_bounds__(kGBlock) void k_cover_init(CoverArgs A) {
 // argmax key (count << 32 | ~v) of each partition it overlaps.
 __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
   __shared__ unsigned long long red[kGBlock / kWave];
+  __shared__ int64_t s_pb[kMaxParts + 1];  // partition bounds
+  __shared__ int32_t s_k[kMaxParts];       // picks per partition
+  constexpr int kQ = kArgTile / kGBlock;
   const int32_t done = *A.done;  // uniform; checked only before the atomic, so the
                                  // count loads do not wait for it
   const int64_t b0 = (int64_t)blockIdx.x * kArgTile;
   const int64_t b1 = min((int64_t)A.n, b0 + kArgTile);
-  int p = 0;
-  if (A.m > 1) {  // first partition overlapping the tile
-    int lo = 0, hi = A.m - 1;
+  // the tile's counts (and ids) first: they do not depend on the partitions
+  uint32_t c[kQ];
+  int32_t vv[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int64_t pos = b0 + threadIdx.x + (int64_t)q * kGBlock;
+    c[q] = 0u;
+    vv[q] = 0;
+    if (pos < b1) {
+      c[q] = A.cnt[pos];
+      vv[q] = A.order && !A.pos_keys ? A.order[pos] : (int32_t)pos;
+    }
+  }
+  const int m = A.m;
+  for (int j = threadIdx.x; j <= m; j += kGBlock) {
+    s_pb[j] = A.pbase ? A.pbase[j] : (j == 0 ? 0 : (int64_t)A.n);
+    if (j < m) s_k[j] = A.kpart ? A.kpart[j] : A.k;
+  }
+  __syncthreads();
+  int p = 0;  // first partition overlapping the tile
+  {
+    int lo = 0, hi = m - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (A.pbase[mid] <= b0)
+      if (s_pb[mid] <= b0)
         lo = mid;
       else
         hi = mid - 1;
     }
     p = lo;
   }
-  for (; p < A.m; ++p) {
-    const int64_t lo = max(b0, part_lo(A, p)), hi = min(b1, part_hi(A, p));
+  for (; p < m; ++p) {
+    const int64_t lo = max(b0, s_pb[p]), hi = min(b1, s_pb[p + 1]);
     if (lo >= b1) break;
-    if (it >= part_k(A, p)) continue;  // this partition has made all its picks (uniform)
+    if (it >= s_k[p]) continue;  // this partition has made all its picks (uniform)
     unsigned long long best = 0ull;
-    for (int64_t base = lo + threadIdx.x; base < hi; base += (int64_t)kArgTile) {
-      uint32_t c[kArgTile / kGBlock];
-      int32_t vv[kArgTile / kGBlock];
 #pragma unroll
-      for (int q = 0; q < kArgTile / kGBlock; ++q) {  // all loads first
-        const int64_t pos = base + (int64_t)q * kGBlock;
-        c[q] = 0u;
-        vv[q] = 0;
-        if (pos < hi) {
-          c[q] = A.cnt[pos];
-          vv[q] = A.order ? A.order[pos] : (int32_t)pos;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kArgTile / kGBlock; ++q) {
-        if (base + (int64_t)q * kGBlock < hi) {
-          const unsigned long long key = argmax_key(c[q], (uint32_t)vv[q]);
-          best = key > best ? key : best;
-        }
+    for (int q = 0; q < kQ; ++q) {
+      const int64_t pos = b0 + threadIdx.x + (int64_t)q * kGBlock;
+      if (pos >= lo && pos < hi) {
+        const unsigned long long key = argmax_key(c[q], (uint32_t)vv[q]);
+        best = key > best ? key : best;
       }
     }
     best = block_max_u64(best, red);
@@ -150,6 +159,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   __shared__ int64_t pre[kMaxParts + 1];
   __shared__ int64_t part_scan[kApplyBlock / kWave + 1];
   __shared__ int64_t ppos[kMaxParts];  // count position of each partition's pick
+  __shared__ uint32_t pvert[kMaxParts];  // its vertex
   const int tid = threadIdx.x, lane = lane_id();
   const int m = A.m;
   const unsigned long long* gm = A.gmax + (int64_t)it * m;
@@ -161,10 +171,13 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
     const unsigned long long b = it < part_k(A, tid) ? gm[tid] : 0ull;
     pbest[tid] = b;
     ppos[tid] = -1;
+    pvert[tid] = 0u;
     if (key_count(b) > 0) {
-      const uint32_t v = key_vertex(b);
+      const uint32_t x = key_vertex(b);
+      const uint32_t v = A.pos_keys ? (uint32_t)A.order[x] : x;
       sz = A.inc_off[v + 1] - A.inc_off[v];
-      ppos[tid] = A.pos_of ? (int64_t)A.pos_of[v] : (int64_t)v;
+      ppos[tid] = A.pos_keys ? (int64_t)x : (A.pos_of ? (int64_t)A.pos_of[v] : (int64_t)v);
+      pvert[tid] = v;
     }
   }
   {  // pre = exclusive prefix of the sizes, pre[m] = total
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
     for (int p = tid; p < m; p += kApplyBlock) {
       const unsigned long long b = pbest[p];
       if (key_count(b) > 0) {
-        const int64_t v = key_vertex(b);
+        const int64_t v = pvert[p];
         A.seeds[part_out(A, p) + it] = (int32_t)(A.local_ids ? v - part_lo(A, p) : v);
         A.gains[part_out(A, p) + it] = (int64_t)key_count(b);
         // every sample of S(v*) ends up covered, so the pick's own count
@@ -227,7 +240,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
           hi = mid - 1;
       }
       p = lo;
-      const uint32_t v = key_vertex(pbest[p]);
+      const uint32_t v = pvert[p];
       smp = A.inc_mem[A.inc_off[v] + (f - pre[p])];
       // flag index: a global sample position when each partition owns its
       // own samples, else one flag array per partition over all samples
@@ -253,9 +266,14 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
       const int64_t skip = ppos[s_p];
       const int64_t a = __shfl(ma, src, kWave), b = __shfl(mb, src, kWave);
       for (int64_t t = a + lane; t < b; t += kWave) {
+        // RandGreedi: only members of the covering partition lose a count;
+        // their count positions, stored beside the members, say which
+        if (A.mpos) {
+          const int64_t pos = A.mpos[t];
+          if (pos >= lo_p && pos < hi_p && pos != skip) atomicSub(&A.cnt[pos], 1u);
+          continue;
+        }
         const int32_t u = A.mem[t];
-        // RandGreedi: only members of the covering partition lose a count; the
-        // one-byte partition id is checked before the position lookup
         if (A.part && A.part[u] != (uint8_t)s_p) continue;
         const int64_t pos = A.local_ids ? lo_p + u : (A.pos_of ? A.pos_of[u] : u);
         if (pos >= lo_p && pos < hi_p && pos != skip) atomicSub(&A.cnt[pos], 1u);
@@ -554,6 +572,15 @@ __global__ __launch_bounds__(kPartBlock) void k_part_scatter(int32_t n, int32_t 
   }
 }
 
+// The count position of every member of the sample collection, beside the
+// members (its partition is the range the position falls in).
+__global__ void k_member_pos(const int32_t* __restrict__ mem, int64_t total,
+                             const int32_t* __restrict__ pos_of, int32_t* __restrict__ mpos) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x)
+    mpos[t] = pos_of[mem[t]];
+}
+
 __global__ void k_pos_of(int32_t n, const int32_t* __restrict__ order,
                          int32_t* __restrict__ pos_of) {
   const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -701,21 +728,21 @@ static size_t greedy_bytes(int32_t n, int64_t count, int32_t k) {
 // Scratch of one RandGreedi local step: gmax (k m) | done | pbase (m + 1) |
 // hist (m) | order, pos_of, cnt (n each) | covered (m count) | M, Moff (the
 // partition counts per chunk of kPartChunk vertices and their scan).
-static size_t randgreedi_bytes(int32_t n, int64_t count, int32_t k, int32_t m) {
+static size_t randgreedi_bytes(int32_t n, int64_t count, int64_t total, int32_t k, int32_t m) {
   const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
   const size_t cells = (size_t)m * (size_t)nch;
   return (size_t)m * k * 8 + 64 + 64 + (size_t)(m + 1) * 8 + (size_t)m * 4 + 64 +
          (size_t)n * 12 + (size_t)m * (size_t)count + 256 + (cells * 4 + 64) / 64 * 64 +
-         (cells + 1) * 8 + 64;
+         (cells + 1) * 8 + 64 + (size_t)total * 4 + 64;
 }
 
 size_t ws_greedy(int32_t n, int64_t count, int32_t k) {
   return ws_align(greedy_bytes(n, count, k));
 }
 
-size_t ws_randgreedi(int32_t n, int64_t count, int32_t k, int32_t m) {
+size_t ws_randgreedi(int32_t n, int64_t count, int64_t total, int32_t k, int32_t m) {
   const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
-  return ws_align(randgreedi_bytes(n, count, k, m)) +
+  return ws_align(randgreedi_bytes(n, count, total, k, m)) +
          ws_align((size_t)(((int64_t)m * nch) / 8192 + 2) * 8);
 }
 
@@ -771,7 +798,7 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
       (total > 0 && (!mem || !inc_mem)))
     return IM_EINVAL;
   WsScope scope(ws, ws_bytes);
-  if (!scope.check(ws_randgreedi(n, count, k, m))) return IM_ENOMEM;
+  if (!scope.check(ws_randgreedi(n, count, total, k, m))) return IM_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   k_partition<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
       n, m, (uint32_t)part_seed, (uint32_t)(part_seed >> 32), part);
@@ -781,7 +808,7 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
   const size_t cells = (size_t)m * (size_t)nch;
   void* p = nullptr;
-  IM_TRY(scratch(s, kSlotLocal, randgreedi_bytes(n, count, k, m), &p));
+  IM_TRY(scratch(s, kSlotLocal, randgreedi_bytes(n, count, total, k, m), &p));
   char* c = (char*)p;
   unsigned long long* gmax = (unsigned long long*)c;
   c += ((size_t)m * k * 8 + 63) / 64 * 64;
@@ -803,6 +830,9 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   uint32_t* M = (uint32_t*)c;
   c += (cells * 4 + 63) / 64 * 64;
   int64_t* Moff = (int64_t*)c;
+  c += (cells + 1) * 8;
+  c = (char*)(((uintptr_t)c + 63) / 64 * 64);
+  int32_t* mpos = (int32_t*)c;
   IM_HIP(hipMemsetAsync(hist, 0, (size_t)m * 4, s));
   k_part_count<<<dim3((unsigned)nch), dim3(kPartBlock), 0, s>>>(n, m, part, nch, M, hist);
   IM_HIP(hipGetLastError());
@@ -818,6 +848,13 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   IM_HIP(hipGetLastError());
   k_pos_of<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, order, pos_of);
   IM_HIP(hipGetLastError());
+  if (total > 0) {
+    DeviceInfo di;
+    IM_TRY(device_info(&di));
+    const int64_t mb = std::min<int64_t>((total + 255) / 256, (int64_t)di.num_cus * 16);
+    k_member_pos<<<dim3((unsigned)mb), dim3(256), 0, s>>>(mem, total, pos_of, mpos);
+    IM_HIP(hipGetLastError());
+  }
   CoverArgs A{};
   A.n = n;
   A.m = m;
@@ -829,7 +866,9 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   A.inc_mem = inc_mem;
   A.order = order;
   A.pos_of = pos_of;
+  A.pos_keys = 1;  // the partition scatter keeps each partition in ascending id order
   A.part = part;
+  A.mpos = total > 0 ? mpos : nullptr;
   A.pbase = pbase;
   A.cnt = cnt;
   A.covered = covered;

@@ -402,7 +402,7 @@ int im_workspace_size(int32_t op, const im_ws_shape* sh, size_t* bytes) {
     case IM_WS_SAMPLE: b = ws_sample(cus, sh->count, sh->total, sh->n, sh->model, full); break;
     case IM_WS_INCIDENCE: b = ws_incidence(sh->n, sh->total, 0, full); break;
     case IM_WS_GREEDY: b = ws_greedy(sh->n, sh->count, k); break;
-    case IM_WS_RANDGREEDI: b = ws_randgreedi(sh->n, sh->count, k, m); break;
+    case IM_WS_RANDGREEDI: b = ws_randgreedi(sh->n, sh->count, sh->total, k, m); break;
     case IM_WS_STREAM: b = ws_stream(sh->n, sh->count, k, m, sh->delta); break;
     case IM_WS_OFFLINE: b = ws_offline(sh->n, sh->count, k, m); break;
     case IM_WS_FORWARD: b = ws_forward(sh->n); break;

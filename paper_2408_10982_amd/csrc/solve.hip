@@ -419,7 +419,7 @@ static size_t ws_select(int32_t n, int64_t count, int64_t total, int32_t k, int3
     const size_t global = selector == IM_SEL_GREEDIRIS ? ws_stream(n, count, k, m, delta)
                                                        : ws_offline(n, count, k, m);
     // the local step's scratch stays while the global step runs
-    inner = std::max(inner, ws_randgreedi(n, count, k, m) + global);
+    inner = std::max(inner, ws_randgreedi(n, count, total, k, m) + global);
   }
   return b + inner;
 }

@@ -148,7 +148,7 @@ def test_short_workspace_rejected_before_device_work():
                          ctypes.c_size_t(4096), None)
     assert st == -3
     assert L.im_workspace_need(ctypes.byref(need), None) == 0
-    assert need.value == _ws_size(L, 4, n=n, count=count, k=k, m=m)
+    assert need.value == _ws_size(L, 4, n=n, count=count, total=100, k=k, m=m)
     L.im_stream_cover.restype = ctypes.c_int
     st = L.im_stream_cover(ctypes.c_int32(n), ctypes.c_int64(count), fake, fake, ctypes.c_int32(k),
                            ctypes.c_int32(m), fake, fake, fake, ctypes.c_double(0.077),
