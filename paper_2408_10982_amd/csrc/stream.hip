@@ -6,13 +6,14 @@
 // reads only its own seeds S_b and cover C_b.  So every bucket is one
 // workgroup on its own CU, keeping C_b as a bitmap over the samples (in LDS
 // when it fits, else in HBM), and all buckets walk the same stream at once.
-// A bucket changes only when it accepts a set, so a workgroup evaluates a
-// window of consecutive stream entries together -- one per wavefront, each
-// counting |S(x) minus C_b| with LDS bit tests -- and takes the first entry
-// that passes; the entries after it are evaluated again from the new state.
-// A set with |S(x)| below the bucket's threshold cannot pass and is rejected
-// without counting.  The decisions are exactly those of one pass in stream
-// order.
+// A bucket changes only when it accepts a set, so a workgroup counts
+// |S(x) minus C_b| for a window of consecutive stream entries together (their
+// ids spread evenly over the threads, LDS bit tests) and takes the first entry
+// that passes; the entries after it are counted again from the ids still in
+// registers, and so on until no entry of the window passes.  A set with
+// |S(x)| below the bucket's threshold cannot pass and is rejected without
+// counting, and a set that fails once never passes later (its gain only
+// falls).  The decisions are exactly those of one pass in stream order.
 //
 // Launches (all asynchronous, no host round trip):
 //   k_stream_build   one workgroup: the stream in its fixed order (compacted),
@@ -31,10 +32,17 @@
 namespace im {
 
 constexpr int kSBlock = 1024;
-constexpr int kWin = kSBlock / kWave;         // stream entries evaluated together
 constexpr int64_t kLdsWords = 36864;          // 144 KB: C_b in LDS up to 1,179,648 samples
 constexpr int kMaxStreamBuckets = 4096;
 constexpr int kBuildBlock = 1024;
+// dynamic LDS of k_stream_bucket: 160 KB less the static part and a margin
+constexpr size_t kStreamLds = 160 * 1024 - 4096;
+
+// Lets a kernel take `bytes` of dynamic LDS (above the default limit).
+static int allow_dynamic_lds(const void* kernel, size_t bytes) {
+  IM_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return IM_OK;
+}
 
 struct StreamArgs {
   int64_t count;                         // samples (universe)
@@ -53,6 +61,9 @@ struct StreamArgs {
   int64_t* __restrict__ thr;             // B thresholds
   uint32_t* __restrict__ gbits;          // B bitmaps of `words` words (HBM form only)
   int64_t words;
+  int32_t cache;                         // stream entries whose ranges k_stream_bucket
+                                         // keeps in LDS
+  int32_t vec;                           // inc_mem is 16-byte aligned
   int32_t* __restrict__ bseeds;          // B * k
   int32_t* __restrict__ bcount;          // B
   int64_t* __restrict__ bcover;          // B
@@ -123,69 +134,227 @@ __device__ __forceinline__ uint32_t bitmap_word(const uint32_t* bits, uint32_t i
     return __hip_atomic_load(&bits[i >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One bucket per workgroup: walk the stream, kWin entries per round.
+// Four ids of S(x) = inc_mem[a .. e) at positions q0 .. q0 + 3 (q0 a multiple
+// of 4), 0xFFFFFFFF for positions outside [a, e): one vector load when all
+// four lie before e (so never past the array), else one load per id.
+__device__ __forceinline__ int4 load_group(const int32_t* __restrict__ mem, bool vec, int64_t q0,
+                                           int64_t a, int64_t e) {
+  int4 x;
+  if (vec && q0 + 3 < e && q0 >= a) {
+    x = *reinterpret_cast<const int4*>(mem + q0);
+  } else {
+    x.x = q0 >= a && q0 < e ? mem[q0] : -1;
+    x.y = q0 + 1 >= a && q0 + 1 < e ? mem[q0 + 1] : -1;
+    x.z = q0 + 2 >= a && q0 + 2 < e ? mem[q0 + 2] : -1;
+    x.w = q0 + 3 >= a && q0 + 3 < e ? mem[q0 + 3] : -1;
+  }
+  return x;
+}
+
+// The ids of S(x) = inc_mem[a .. e), four at a time from 16-byte aligned
+// positions: f(id) for each.  Position q0 (a multiple of 4) covers ids
+// q0 .. q0 + 3; a vector load is used only when all four lie before e (so
+// never past the array), the rest of a partial group is loaded one by one.
+template <typename F>
+__device__ __forceinline__ void for_group(const int32_t* __restrict__ mem, bool vec, int64_t q0,
+                                          int64_t a, int64_t e, F f) {
+  if (vec && q0 + 3 < e) {
+    const int4 x = *reinterpret_cast<const int4*>(mem + q0);
+    if (q0 >= a) f((uint32_t)x.x);
+    if (q0 + 1 >= a) f((uint32_t)x.y);
+    if (q0 + 2 >= a) f((uint32_t)x.z);
+    f((uint32_t)x.w);
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (q0 + u >= a && q0 + u < e) f((uint32_t)mem[q0 + u]);
+  }
+}
+
+// One bucket per workgroup: walk the stream a window at a time.  A window is
+// up to 64 consecutive entries, as many as hold kRoundGroups groups of 4 ids
+// of the sets that can still pass (|S(x)| >= thr; at least one entry).  The
+// window's ids are spread evenly over the workgroup, each thread loading up
+// to kGroupsPer groups before testing any bit, and the counts are summed per
+// entry in LDS; the first entry that passes is taken (its bits set by the
+// threads that hold its ids) and the next window starts right after it.  The
+// stream's ranges are cached in LDS as far as they fit beside the bitmap.
+constexpr int kGroupsPer = 8;
+constexpr int kRoundGroups = kSBlock * kGroupsPer;
+
 template <bool kLds>
 __global__ __launch_bounds__(kSBlock) void k_stream_bucket(StreamArgs A) {
-  __shared__ uint32_t lbits[kLds ? kLdsWords : 1];
-  __shared__ int32_t s_gain[kWin];
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ int64_t w_q[kWave];   // first group position of each window entry
+  __shared__ int64_t w_a[kWave], w_e[kWave];
+  __shared__ int32_t w_gp[kWave + 1];  // exclusive prefix of the entries' groups
+  __shared__ int32_t w_cnt[kWave];
+  __shared__ int32_t s_W, s_first;
+  uint32_t* lbits = reinterpret_cast<uint32_t*>(dyn);
+  const int64_t bm_bytes = kLds ? (A.words * 4 + 15) / 16 * 16 : 0;
+  int64_t* s_a = reinterpret_cast<int64_t*>(dyn + bm_bytes);
+  int32_t* s_n = reinterpret_cast<int32_t*>(dyn + bm_bytes + (int64_t)A.cache * 8);
+  int32_t* s_x = s_n + A.cache;
   const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
   uint32_t* bits = kLds ? lbits : A.gbits + (int64_t)b * A.words;
   for (int64_t j = tid; j < A.words; j += kSBlock) bits[j] = 0u;
   const int64_t thr = A.thr[b];
   const int32_t L = A.hdr[0] > 0 ? (int32_t)A.hdr[1] : 0;  // l = 0: nothing can pass
+  const int32_t nc = min(L, A.cache);
+  for (int32_t j = tid; j < nc; j += kSBlock) {
+    const int64_t a = A.sa[j];
+    s_a[j] = a;
+    s_n[j] = (int32_t)(A.sb[j] - a);
+    s_x[j] = A.sx[j];
+  }
   int32_t* out = A.bseeds + (int64_t)b * A.k;
+  const bool vec = A.vec != 0;
+  const int32_t* __restrict__ mem = A.inc_mem;
   __syncthreads();
   int32_t ns = 0;
   int64_t csz = 0;
   int32_t pos = 0;
   while (pos < L && ns < A.k) {  // uniform over the workgroup
-    const int32_t j = pos + w;
-    int32_t g = -1;
-    if (j < L) {
-      const int64_t a = A.sa[j], e = A.sb[j];
-      if (e - a >= thr) {
-        int32_t c = 0;
-        constexpr int kU = 8;  // ids loaded together, then their bits tested
-        for (int64_t q0 = a + lane; q0 < e; q0 += kU * kWave) {
-          uint32_t ids[kU];
+    if (w == 0) {  // the window: entries pos + lane
+      const int32_t j = pos + lane;
+      int64_t a = 0, e = 0;
+      if (j < L) {
+        a = j < nc ? s_a[j] : A.sa[j];
+        e = a + (j < nc ? (int64_t)s_n[j] : A.sb[j] - a);
+      }
+      const bool elig = j < L && e - a >= thr;
+      const int64_t q = a & ~(int64_t)3;
+      const int32_t ng = elig ? (int32_t)((e - q + 3) >> 2) : 0;
+      const int32_t inc = wave_inclusive_scan(ng);
+      // entries while the groups fit the round (the first one always)
+      const bool in = j < L && (lane == 0 || inc <= kRoundGroups);
+      const int32_t W = (int32_t)__popcll(__ballot(in));
+      w_q[lane] = q;
+      w_a[lane] = a;
+      w_e[lane] = e;
+      w_gp[lane] = inc - ng;
+      w_cnt[lane] = elig ? 0 : -1;
+      if (lane == W - 1) w_gp[W] = inc;
+      if (lane == 0) s_W = W;
+    }
+    __syncthreads();
+    const int32_t W = s_W, G = w_gp[W];
+    // count: groups g = tid + r * kSBlock of each batch
+    int4 x[kGroupsPer];
+    int32_t je[kGroupsPer];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int64_t q = q0 + (int64_t)u * kWave;
-            ids[u] = q < e ? (uint32_t)A.inc_mem[q] : 0xFFFFFFFFu;
+    for (int r = 0; r < kGroupsPer; ++r) {
+      je[r] = -1;
+      x[r] = make_int4(-1, -1, -1, -1);
+    }
+    for (int32_t gb = 0; gb < G; gb += kRoundGroups) {
+#pragma unroll
+      for (int r = 0; r < kGroupsPer; ++r) {
+        const int32_t g = gb + tid + r * kSBlock;
+        je[r] = -1;
+        x[r] = make_int4(-1, -1, -1, -1);
+        if (g < G) {
+          int lo = 0, hi = W - 1;  // entry holding group g
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (w_gp[mid] <= g)
+              lo = mid;
+            else
+              hi = mid - 1;
           }
-#pragma unroll
-          for (int u = 0; u < kU; ++u)
-            if (ids[u] != 0xFFFFFFFFu)
-              c += (int32_t)(((bitmap_word<kLds>(bits, ids[u]) >> (ids[u] & 31u)) & 1u) ^ 1u);
+          je[r] = lo;
+          x[r] = load_group(mem, vec, w_q[lo] + 4 * (int64_t)(g - w_gp[lo]), w_a[lo], w_e[lo]);
         }
-        c = wave_sum(c);
-        g = (int64_t)c >= thr ? c : -1;
+      }
+#pragma unroll
+      for (int r = 0; r < kGroupsPer; ++r) {
+        int32_t c = 0;
+        const uint32_t id4[4] = {(uint32_t)x[r].x, (uint32_t)x[r].y, (uint32_t)x[r].z,
+                                 (uint32_t)x[r].w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (id4[u] != 0xFFFFFFFFu)
+            c += (int32_t)(((bitmap_word<kLds>(bits, id4[u]) >> (id4[u] & 31u)) & 1u) ^ 1u);
+        // one atomic per wavefront when all its lanes count for one entry
+        const int32_t j0 = __shfl(je[r], 0, kWave);
+        if (__all(je[r] == j0)) {
+          c = wave_sum(c);
+          if (lane == 0 && j0 >= 0 && c) atomicAdd(&w_cnt[j0], c);
+        } else if (je[r] >= 0 && c) {
+          atomicAdd(&w_cnt[je[r]], c);
+        }
       }
     }
-    if (lane == 0) s_gain[w] = g;
     __syncthreads();
-    int first = -1;
-    for (int q = 0; q < kWin; ++q)
-      if (s_gain[q] >= 0) {
-        first = q;
+    // take the first entry that passes; when the whole window's ids are in
+    // registers, recount the entries after it from them and go on taking in
+    // the same window (an entry that fails never passes later: its gain only
+    // falls), so the window is done when nothing more passes
+    const bool held = G <= kRoundGroups;
+    int after = -1;  // entries up to here are decided
+    for (;;) {
+      if (w == 0) {
+        const bool pass =
+            lane > after && lane < W && w_cnt[lane] >= 0 && (int64_t)w_cnt[lane] >= thr;
+        const unsigned long long pm = __ballot(pass);
+        if (lane == 0) s_first = pm ? __ffsll((long long)pm) - 1 : -1;
+      }
+      __syncthreads();
+      const int first = s_first;
+      if (first < 0) {
+        pos += W;
         break;
       }
-    if (first >= 0) {
       const int32_t ja = pos + first;
-      const int64_t a = A.sa[ja], e = A.sb[ja];
-      if (tid == 0) out[ns] = A.sx[ja];
+      if (tid == 0) out[ns] = ja < nc ? s_x[ja] : A.sx[ja];
       ns += 1;
-      csz += s_gain[first];
-      for (int64_t q = a + tid; q < e; q += kSBlock) {
-        const uint32_t i = (uint32_t)A.inc_mem[q];
-        atomicOr(&bits[i >> 5], 1u << (i & 31u));
+      csz += w_cnt[first];
+      if (held) {
+#pragma unroll
+        for (int r = 0; r < kGroupsPer; ++r)
+          if (je[r] == first) {
+            const uint32_t id4[4] = {(uint32_t)x[r].x, (uint32_t)x[r].y, (uint32_t)x[r].z,
+                                     (uint32_t)x[r].w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (id4[u] != 0xFFFFFFFFu) atomicOr(&bits[id4[u] >> 5], 1u << (id4[u] & 31u));
+          }
+      } else {
+        const int64_t a = w_a[first], e = w_e[first];
+        for (int64_t q0 = w_q[first] + 4 * tid; q0 < e; q0 += 4 * kSBlock)
+          for_group(mem, vec, q0, a, e,
+                    [&](uint32_t id) { atomicOr(&bits[id >> 5], 1u << (id & 31u)); });
       }
-      pos = ja + 1;
-    } else {
-      pos += kWin;
+      if (!held || ns >= A.k || first == W - 1) {
+        pos = ja + 1;
+        break;
+      }
+      after = first;
+      if (w == 0 && lane > after && lane < W && w_cnt[lane] >= 0) w_cnt[lane] = 0;
+      __syncthreads();  // the new bits and the cleared counts
+#pragma unroll
+      for (int r = 0; r < kGroupsPer; ++r) {
+        int32_t c = 0;
+        const bool mine = je[r] > after;
+        const uint32_t id4[4] = {(uint32_t)x[r].x, (uint32_t)x[r].y, (uint32_t)x[r].z,
+                                 (uint32_t)x[r].w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (mine && id4[u] != 0xFFFFFFFFu)
+            c += (int32_t)(((bitmap_word<kLds>(bits, id4[u]) >> (id4[u] & 31u)) & 1u) ^ 1u);
+        const int32_t jr = mine ? je[r] : -1;
+        const int32_t j0 = __shfl(jr, 0, kWave);
+        if (__all(jr == j0)) {
+          c = wave_sum(c);
+          if (lane == 0 && j0 >= 0 && c) atomicAdd(&w_cnt[j0], c);
+        } else if (jr >= 0 && c) {
+          atomicAdd(&w_cnt[jr], c);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();  // bits and s_gain settled before the next round
+    __syncthreads();  // bits and the window settled before the next round
   }
   if (tid == 0) {
     A.bcount[b] = ns;
@@ -309,12 +478,22 @@ extern "C" int im_stream_cover(int32_t n, int64_t count, const int64_t* inc_off,
   A.nsel = nsel;
   A.coverage = coverage;
   A.info = info;
+  A.vec = ((uintptr_t)inc_mem & 15u) == 0 ? 1 : 0;
+  // LDS: the bitmap (in-LDS form), then the ranges and vertices of as many
+  // stream entries as fit (16 bytes each)
+  const size_t bm_bytes = lds ? ((size_t)words * 4 + 15) / 16 * 16 : 0;
+  const size_t room = kStreamLds > bm_bytes ? kStreamLds - bm_bytes : 0;
+  A.cache = (int32_t)std::min<int64_t>(L, (int64_t)(room / 16));
+  const size_t dyn = bm_bytes + (size_t)A.cache * 16;
   k_stream_build<<<1, kBuildBlock, 0, s>>>(A);
   IM_HIP(hipGetLastError());
-  if (lds)
-    k_stream_bucket<true><<<dim3((unsigned)B), dim3(kSBlock), 0, s>>>(A);
-  else
-    k_stream_bucket<false><<<dim3((unsigned)B), dim3(kSBlock), 0, s>>>(A);
+  if (lds) {
+    IM_TRY(allow_dynamic_lds((const void*)k_stream_bucket<true>, dyn));
+    k_stream_bucket<true><<<dim3((unsigned)B), dim3(kSBlock), dyn, s>>>(A);
+  } else {
+    IM_TRY(allow_dynamic_lds((const void*)k_stream_bucket<false>, dyn));
+    k_stream_bucket<false><<<dim3((unsigned)B), dim3(kSBlock), dyn, s>>>(A);
+  }
   IM_HIP(hipGetLastError());
   k_stream_final<<<1, 256, 0, s>>>(A);
   IM_HIP(hipGetLastError());
