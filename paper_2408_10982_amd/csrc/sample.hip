@@ -1415,21 +1415,24 @@ __device__ __forceinline__ void bloom_add(Bloom& b, uint32_t h) {
     b.w3 |= m;
 }
 
-// Is u among the first len entries of the lane's list (16-byte aligned)?
-__device__ __forceinline__ bool list_has(const int32_t* Ls, int32_t len, int32_t u) {
-  for (int32_t j0 = 0; j0 < len; j0 += 8) {
-    const int4 x = *reinterpret_cast<const int4*>(Ls + j0);
-    const int4 y = *reinterpret_cast<const int4*>(Ls + j0 + 4);
-    const int32_t v[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
-    bool hit = false;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) hit |= (j0 + q < len) & (v[q] == u);
-    if (hit) return true;
-  }
-  return false;
-}
-
+// Is u among the first len (<= kLtOwnScan) entries of the lane's list
+// (16-byte aligned)?  All of its loads are issued before any compare.
 constexpr int32_t kLtOwnScan = 32;
+
+__device__ __forceinline__ bool list_has(const int32_t* Ls, int32_t len, int32_t u) {
+  int4 x[kLtOwnScan / 4];
+#pragma unroll
+  for (int q = 0; q < kLtOwnScan / 4; ++q)
+    x[q] = 4 * q < len ? *reinterpret_cast<const int4*>(Ls + 4 * q) : make_int4(-1, -1, -1, -1);
+  bool hit = false;
+#pragma unroll
+  for (int q = 0; q < kLtOwnScan / 4; ++q) {
+    const int j = 4 * q;
+    hit |= (j < len && x[q].x == u) | (j + 1 < len && x[q].y == u) |
+           (j + 2 < len && x[q].z == u) | (j + 3 < len && x[q].w == u);
+  }
+  return hit;
+}
 
 // One lane per walk.  Lanes take new samples as their walks end (aggregated
 // per wave), so a long walk does not hold up the other 63 lanes.
@@ -1520,10 +1523,19 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
       const int32_t lj = __shfl(len, j, kWave), uj = __shfl(u, j, kWave);
       const int32_t* Lj = lane_list + (gl - (size_t)lane + (size_t)j) * kLtCap;
       bool hit = false;
-      for (int32_t p = 4 * lane; p < lj; p += 4 * kWave) {
-        const int4 x = *reinterpret_cast<const int4*>(Lj + p);
-        hit |= (x.x == uj) | ((p + 1 < lj) & (x.y == uj)) | ((p + 2 < lj) & (x.z == uj)) |
-               ((p + 3 < lj) & (x.w == uj));
+      // a whole list (kLtCap entries) in one batch of loads: 4 x 16 bytes per lane
+      constexpr int kR = kLtCap / (4 * kWave);
+      int4 xs[kR];
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const int32_t p = 4 * lane + r * 4 * kWave;
+        xs[r] = p < lj ? *reinterpret_cast<const int4*>(Lj + p) : make_int4(-1, -1, -1, -1);
+      }
+#pragma unroll
+      for (int r = 0; r < kR; ++r) {
+        const int32_t p = 4 * lane + r * 4 * kWave;
+        hit |= (p < lj && xs[r].x == uj) | (p + 1 < lj && xs[r].y == uj) |
+               (p + 2 < lj && xs[r].z == uj) | (p + 3 < lj && xs[r].w == uj);
       }
       const bool any = __any(hit);
       if (lane == j) seen = any;
