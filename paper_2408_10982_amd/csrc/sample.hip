@@ -1576,13 +1576,20 @@ __global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* l
         A.len[il] = -1;
       } else {
         if (pos + (unsigned long long)len <= A.arena_cap) {
-          for (int32_t j0 = 0; j0 < len; j0 += 8) {  // eight members per round
-            const int4 x = *reinterpret_cast<const int4*>(Ls + j0);
-            const int4 y = *reinterpret_cast<const int4*>(Ls + j0 + 4);
-            const int32_t m8[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+          for (int32_t j0 = 0; j0 < len; j0 += 32) {  // 32 members per round, loads first
+            int4 x[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-              if (j0 + q < len) A.arena[pos + j0 + q] = m8[q];
+              x[q] = j0 + 4 * q < len ? *reinterpret_cast<const int4*>(Ls + j0 + 4 * q)
+                                      : make_int4(0, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int32_t j = j0 + 4 * q;
+              if (j < len) A.arena[pos + j] = x[q].x;
+              if (j + 1 < len) A.arena[pos + j + 1] = x[q].y;
+              if (j + 2 < len) A.arena[pos + j + 2] = x[q].z;
+              if (j + 3 < len) A.arena[pos + j + 3] = x[q].w;
+            }
           }
         }
         A.start[il] = (int64_t)pos;
