@@ -208,6 +208,15 @@ def workspace_need():
     return int(need.value), int(want.value)
 
 
+def _sampling_hint(g: "Graph") -> int:
+    """Workspace for one sampling call on g with room for every large-set
+    worker the launch can use (up to 16 GiB): a smaller workspace would run
+    a first call with few workers, which on graphs with many large sets is
+    orders of magnitude slower."""
+    return workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=1 << 20, total=1 << 20,
+                          full=True)
+
+
 def _ws_tensor(s, want: int) -> torch.Tensor:
     key = (s.device.index, s.cuda_stream)
     with _WS_LOCK:
@@ -349,7 +358,8 @@ def sample_rrr(g: Graph, seed: int, stream_tag: int, first: int, count: int,
         mem = torch.empty(max(cap, 1), dtype=torch.int32, device=g.in_off.device)
         total = C.c_int64()
         stats = _Stats()
-        hint = workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=count, total=cap)
+        hint = max(workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=count, total=cap),
+                   _sampling_hint(g))
         st = _call_ws(lib().im_sample_rrr, "im_sample_rrr",
                       (C.byref(gs), seed, stream_tag, first, count, _ptr(off), _ptr(mem), cap,
                        C.byref(total), C.byref(stats)), stream, hint, ok=(IM_OK, IM_ERANGE))
@@ -500,7 +510,7 @@ def solve(g: Graph, k: int, eps: float, selector: int = SEL_GREEDY, m: int = 1,
     seeds = (C.c_int32 * k)()
     gs = g.struct()
     _call_ws(lib().im_solve, "im_solve", (C.byref(gs), k, eps, C.byref(o), seeds, C.byref(res)),
-             stream)
+             stream, _sampling_hint(g))
     out = {f: getattr(res, f) for f, _ in _SolveResult._fields_}
     out["seeds"] = list(seeds)[:res.nsel]
     return out
@@ -515,7 +525,8 @@ def opim(g: Graph, k: int, eps: float, fail: float, theta_cap: int,
     seeds = (C.c_int32 * k)()
     gs = g.struct()
     _call_ws(lib().im_opim, "im_opim",
-             (C.byref(gs), k, eps, fail, theta_cap, C.byref(o), seeds, C.byref(res)), stream)
+             (C.byref(gs), k, eps, fail, theta_cap, C.byref(o), seeds, C.byref(res)), stream,
+             _sampling_hint(g))
     out = {f: getattr(res, f) for f, _ in _OpimResult._fields_}
     out["seeds"] = list(seeds)[:res.nsel]
     return out
@@ -538,7 +549,8 @@ def solve_batch(tasks, stream=None):
     cov = torch.empty(nt, dtype=torch.int64, device=dev)
     st = _BatchStats()
     _call_ws(lib().im_solve_batch, "im_solve_batch",
-             (arr, nt, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov), C.byref(st)), stream)
+             (arr, nt, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov), C.byref(st)), stream,
+             max(_sampling_hint(t[0]) for t in tasks))
     s_h, g_h, n_h, c_h = (seeds.cpu().tolist(), gains.cpu().tolist(), nsel.cpu().tolist(),
                           cov.cpu().tolist())
     out, o = [], 0
@@ -584,7 +596,8 @@ def sample_into(g: Graph, seed: int, stream_tag: int, first: int, count: int,
     Returns the member total, or -total if mem was too small (IM_ERANGE)."""
     gs = g.struct()
     total = C.c_int64()
-    hint = workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=count, total=mem.numel())
+    hint = max(workspace_size(WS_SAMPLE, n=g.n, model=g.model, count=count, total=mem.numel()),
+               _sampling_hint(g))
     st = _call_ws(lib().im_sample_rrr, "im_sample_rrr",
                   (C.byref(gs), seed, stream_tag, first, count, _ptr(off), _ptr(mem),
                    mem.numel(), C.byref(total), None), stream, hint, ok=(IM_OK, IM_ERANGE))
