@@ -85,10 +85,16 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
     }
   } guard{ev};
   // sampling: the sets are staged in the arena, then gathered into a member
-  // buffer of exactly their total
+  // buffer of exactly their total.  The arena is sized from the member total
+  // of this thread's previous batch (a short arena means sampling the batch
+  // again; the total is kept as soon as it is counted, also when the call
+  // then runs short of workspace and is repeated); results do not depend on it
+  static thread_local int64_t last_total = 0;
   ArenaRun R;
   IM_HIP(hipEventRecord(ev[0], s));
-  IM_TRY(sample_to_arena(td.data(), nt, S, max_n, off, 0, 0, true, false, &R, s));
+  const int rc = sample_to_arena(td.data(), nt, S, max_n, off, last_total, 0, true, false, &R, s);
+  if (R.total > 0) last_total = R.total;
+  IM_TRY(rc);
   const int64_t total = R.total;
   void* mp = nullptr;
   IM_TRY(scratch(s, kSlotBatchMem, (size_t)std::max<int64_t>(total, 1) * 4, &mp));

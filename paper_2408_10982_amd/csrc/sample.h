@@ -51,7 +51,9 @@ struct ArenaRun {
 // canonical offsets (off, count_total + 1 entries).  expect: a guess of the
 // member total used to size the arena (0: none).  stop_above > 0: a total
 // above it is only counted (the sets need not be kept: the caller reports
-// IM_ERANGE), so a short arena is not refilled.  Synchronises s.
+// IM_ERANGE), so a short arena is not refilled.  R->total holds the member
+// total once a pass has counted it, also when the call then fails (a short
+// workspace for the larger arena).  Synchronises s.
 int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, int32_t max_n,
                     int64_t* off, int64_t expect, int64_t stop_above, bool sort_all, bool timed,
                     ArenaRun* R, hipStream_t s);

@@ -361,10 +361,13 @@ __device__ __forceinline__ int64_t lt_level_base(int64_t E, int k) {
 // whose last edge is taken are counted in one 64-byte group (the windows
 // entirely inside [a, b) only: the one holding b - 1 is where the search
 // ends if no earlier one is taken); the last group holds the edges
-// themselves, loaded with their sources.  Without the index, a binary search.
+// themselves, loaded with their sources.  Without the index (or with
+// kIndex false, where the registers the descent holds would cost occupancy),
+// a binary search.
+template <bool kIndex = true>
 __device__ __forceinline__ int32_t lt_pick(const GView& G, int32_t a, int32_t b, uint32_t r,
                                            int32_t* src) {
-  if (!G.lt_index) {
+  if (!kIndex || !G.lt_index) {
     int32_t lo = a, hi = b;
     while (lo < hi) {
       const int32_t mid = lo + ((hi - lo) >> 1);
@@ -1257,7 +1260,7 @@ __global__ __launch_bounds__(C::kBlock) IM_BIG_ATTR void k_sample_big(SampleArgs
         s_ex += ceil_log2_plus1(b - a);
         const uint32_t r = draw1(seed, kTagVert, G.stream, i, (uint32_t)v);
         int32_t u = 0;
-        if (lt_pick(G, a, b, r, &u) == b) break;
+        if (lt_pick<false>(G, a, b, r, &u) == b) break;
         ++s_lv;
         const uint32_t bit = 1u << (u & 31);
         if (bm[u >> 5] & bit) break;
@@ -1435,8 +1438,14 @@ __device__ __forceinline__ bool list_has(const int32_t* Ls, int32_t len, int32_t
 }
 
 // One lane per walk.  Lanes take new samples as their walks end (aggregated
-// per wave), so a long walk does not hold up the other 63 lanes.
-__global__ __launch_bounds__(kLtBlock) void k_sample_lt(SampleArgs A, int32_t* lane_list) {
+// per wave), so a long walk does not hold up the other 63 lanes.  Resident
+// wavefronts per SIMD (IM_LT_WAVES): the compiler keeps the registers within
+// what that many need.
+#ifndef IM_LT_WAVES
+#define IM_LT_WAVES 4
+#endif
+__global__ __launch_bounds__(kLtBlock) __attribute__((amdgpu_waves_per_eu(IM_LT_WAVES)))
+void k_sample_lt(SampleArgs A, int32_t* lane_list) {
   const size_t gl = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t* Ls = lane_list + gl * kLtCap;
   const int lane = lane_id();
@@ -1914,6 +1923,7 @@ int sample_to_arena(const TaskDesc* h_tasks, int ntasks, int64_t count_total, in
       if (timed) IM_HIP(hipEventElapsedTime(&ms_large, ev[2], ev[3]));
     }
     R->passes = attempt + 1;
+    R->total = (int64_t)hc[10];  // exact even when the arena was short
     if (hc[1] <= arena_cap) break;
     // more members than the caller can take: the call reports the total and
     // returns IM_ERANGE, so the sets need not be kept
