@@ -57,6 +57,10 @@ class SamplePool:
         n = torch.empty(cap, dtype=t.dtype, device=t.device)
         with torch.cuda.stream(stream):
             n[:t.numel()].copy_(t)
+        # the old tensor may have been allocated on another slot's stream and
+        # is freed as soon as the pool drops it: its block must not be handed
+        # to that stream's next allocation while this copy still reads it
+        t.record_stream(stream)
         return n
 
     def prefix(self, want: int, stream):
