@@ -269,10 +269,15 @@ def workspace_bytes(stream=None) -> int:
     return 0 if t is None else t.numel()
 
 
-def drop_workspaces():
-    """Forgets every cached workspace (their memory returns to torch's allocator)."""
+def drop_workspaces(stream=None):
+    """Forgets the cached workspace of `stream`, or every cached workspace
+    (their memory returns to torch's allocator once the streams' work is
+    done)."""
     with _WS_LOCK:
-        _WS.clear()
+        if stream is None:
+            _WS.clear()
+        else:
+            _WS.pop((stream.device.index, stream.cuda_stream), None)
 
 
 def _dev(t: torch.Tensor, dtype) -> torch.Tensor:
