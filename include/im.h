@@ -188,8 +188,10 @@ int im_workspace_need(size_t* need, size_t* want);
  *                          subsets take the dense form, >= 0 (0: always
  *                          dense; default 256)
  *   IM_TUNE_LT_BLOCKS      workgroups (4 wavefronts, one walk per lane) per CU
- *                          of the LT sampling launch, 1..32 (default 7: at 70
- *                          VGPRs, seven wavefronts per SIMD are resident at once)
+ *                          of the LT sampling launch, 1..32 (default 4: the walk
+ *                          kernel is built for four resident wavefronts per
+ *                          SIMD; more workgroups only wait behind them, and
+ *                          each lane holds 4 KiB of walk list in the workspace)
  *   IM_TUNE_GRAPH          1: a cover's 2k + 2 launches (greedy, RandGreedi local
  *                          step, offline aggregation, batch) are captured into a
  *                          hipGraph once per launch shape and replayed (updated

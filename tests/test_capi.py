@@ -181,7 +181,7 @@ def test_tune_knobs_validate_and_round_trip():
         assert L.im_tune_get(key, ctypes.byref(v)) == 0
         return v.value
 
-    defaults = {0: 5, 1: 0, 2: 1, 3: 256, 4: 7, 5: 16, 6: 0}
+    defaults = {0: 5, 1: 0, 2: 1, 3: 256, 4: 4, 5: 16, 6: 0}
     assert {k: get(k) for k in defaults} == defaults
     for key, bad in ((0, 0), (0, 65), (1, 3), (2, 0), (2, 17), (3, -2), (4, 0), (4, 33), (5, 0),
                      (5, 4097), (6, 2), (6, -2), (7, 1), (-1, 1)):
