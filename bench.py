@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+HW_QUEUES = 16                   # hardware queues per process (one per stream used here)
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # 32-bit integer VALU lane-ops/s (full rate)
 
 
@@ -144,6 +145,16 @@ def main():
               "multi-GPU path (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
               file=sys.stderr)
         sys.exit(2)
+
+    # HIP gives a stream its hardware queue when the stream is first used: a
+    # new queue while fewer than GPU_MAX_HW_QUEUES exist (HIP's default is 4),
+    # else the least used one, ties going to the newest.  Work of streams on
+    # one queue runs one after the other, so with 4 queues two of the four
+    # solve streams (or serving slots) can share one: 18.5 against 14 ms per
+    # solve measured.  This process uses fewer than 16 streams, so with 16
+    # each stream has a queue of its own.  It must be set before HIP starts.
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < HW_QUEUES:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 
     import torch
 
@@ -598,8 +609,8 @@ def concurrent_solves(im, G, w, alpha, steps, n_streams, torch, ref_seeds):
         except BaseException as e:  # noqa: BLE001 -- re-raised below
             errs.append(e)
 
-    # an untimed pass of the same shape first: the first concurrent pass of
-    # a process runs slower (18.4 against 14.0-14.5 ms per solve measured)
+    # an untimed pass of the same shape first: it grows each stream's
+    # workspace and gives each stream its hardware queue
     for timed_run in (False, True):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -663,6 +674,7 @@ def bench_imm(args, w, G, im, W, torch):
         "streamed_solution_chosen": res["global_won"], "final_sum_rrr": res["final_total"],
         "seeds_head": res["seeds"][:8],
         "solves_in_flight": n_conc,
+        "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
         "ms_per_step_one_stream": round(dt1s * 1e3, 3),
         "value_one_stream": round(samples / dt1s, 1),
         "sampling_sets_per_s": round(res["sampled_sets"] /

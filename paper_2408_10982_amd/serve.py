@@ -210,7 +210,13 @@ class Server:
     slots' streams (one per slot, default priority), to be reused across
     servers: the binding keeps a workspace per stream, so a server on
     streams that served before starts with those workspaces in place; None
-    creates new ones."""
+    creates new ones.
+
+    Slots overlap only if their streams sit on different hardware queues.
+    HIP hands a stream its queue on first use, a new one while fewer than
+    GPU_MAX_HW_QUEUES exist (default 4), so the process should set that
+    variable, before HIP starts, above the number of streams it uses; with
+    fewer, two slots can share a queue and run one after the other."""
 
     def __init__(self, graphs: dict, seed: int, slots: int = 4, hbm_budget: int = 64 << 30,
                  streams=None):
