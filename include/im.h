@@ -188,10 +188,11 @@ int im_workspace_need(size_t* need, size_t* want);
  *                          subsets take the dense form, >= 0 (0: always
  *                          dense; default 256)
  *   IM_TUNE_LT_BLOCKS      workgroups (4 wavefronts, one walk per lane) per CU
- *                          of the LT sampling launch, 1..32 (default 4: the walk
- *                          kernel is built for four resident wavefronts per
- *                          SIMD; more workgroups only wait behind them, and
- *                          each lane holds 4 KiB of walk list in the workspace)
+ *                          of the LT sampling launch, 1..32 (default 2: half of
+ *                          the four wavefronts per SIMD the walk kernel is
+ *                          built for, so that work of other streams runs beside
+ *                          it; each lane holds 4 KiB of walk list in the
+ *                          workspace)
  *   IM_TUNE_GRAPH          1: a cover's 2k + 2 launches (greedy, RandGreedi local
  *                          step, offline aggregation, batch) are captured into a
  *                          hipGraph once per launch shape and replayed (updated
@@ -201,6 +202,13 @@ int im_workspace_need(size_t* need, size_t* want);
  *   IM_TUNE_LT_GRAB        sample ids an LT wavefront claims at once, 1..4096
  *                          (default 16: with 256 only ~1,250 wavefronts of a
  *                          320 K-walk launch get work; 16 spreads it over all)
+ *   IM_TUNE_LISTS          1: the RandGreedi local step (partitions of at
+ *                          most 2^18 positions on average) finds each pick
+ *                          from a per-partition list of the highest counts,
+ *                          one workgroup per partition, scanning a partition
+ *                          only when its list can no longer decide; 0: every
+ *                          pick scans all counts over the whole device
+ *                          (default 1)
  * value -1 restores the default.  Returns IM_EINVAL for an unknown key or a
  * value outside its range (nothing changes then).  im_tune_get writes the
  * value in effect.
@@ -212,7 +220,8 @@ typedef enum {
   IM_TUNE_DENSE_RATIO = 3,
   IM_TUNE_LT_BLOCKS = 4,
   IM_TUNE_LT_GRAB = 5,
-  IM_TUNE_GRAPH = 6
+  IM_TUNE_GRAPH = 6,
+  IM_TUNE_LISTS = 7
 } im_tune_key;
 int im_tune_set(int32_t key, int64_t value);
 int im_tune_get(int32_t key, int64_t* value);

@@ -7,7 +7,7 @@ This package is the thin Python face of that library.
 """
 from .binding import (IC, LT, SEL_GREEDIRIS, SEL_GREEDY, SEL_RANDGREEDI, EXPORTS, Forward, Graph,
                       ImError, RRR, TUNE_APPLY_BLOCKS, TUNE_BIG_SHAPE, TUNE_DENSE_RATIO,
-                      TUNE_GRAPH, TUNE_LT_BLOCKS, TUNE_LT_GRAB, TUNE_SAMPLE_BLOCKS,
+                      TUNE_GRAPH, TUNE_LISTS, TUNE_LT_BLOCKS, TUNE_LT_GRAB, TUNE_SAMPLE_BLOCKS,
                       WS_BATCH, WS_FORWARD, WS_GREEDY, WS_INCIDENCE, WS_INFLUENCE, WS_OFFLINE,
                       WS_OPIM, WS_PREPARE_GRAPH, WS_RANDGREEDI, WS_SAMPLE, WS_SOLVE, WS_STREAM,
                       build_incidence, drop_workspaces, greedi_offline, greedy_cover,
@@ -18,7 +18,7 @@ from .binding import (IC, LT, SEL_GREEDIRIS, SEL_GREEDY, SEL_RANDGREEDI, EXPORTS
 
 __all__ = ["IC", "LT", "SEL_GREEDY", "SEL_GREEDIRIS", "SEL_RANDGREEDI", "EXPORTS", "Forward",
            "Graph", "ImError", "RRR", "TUNE_APPLY_BLOCKS", "TUNE_BIG_SHAPE", "TUNE_DENSE_RATIO",
-           "TUNE_GRAPH", "TUNE_LT_BLOCKS", "TUNE_LT_GRAB", "TUNE_SAMPLE_BLOCKS", "WS_BATCH",
+           "TUNE_GRAPH", "TUNE_LISTS", "TUNE_LT_BLOCKS", "TUNE_LT_GRAB", "TUNE_SAMPLE_BLOCKS", "WS_BATCH",
            "WS_FORWARD", "WS_GREEDY", "WS_INCIDENCE", "WS_INFLUENCE", "WS_OFFLINE", "WS_OPIM",
            "WS_PREPARE_GRAPH", "WS_RANDGREEDI", "WS_SAMPLE", "WS_SOLVE", "WS_STREAM",
            "build_incidence", "drop_workspaces", "greedi_offline", "greedy_cover",

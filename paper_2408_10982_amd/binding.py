@@ -25,7 +25,7 @@ IM_OK, IM_EINVAL, IM_ERANGE, IM_ENOMEM, IM_EDEVICE = 0, -1, -2, -3, -4
 IC, LT = 0, 1
 SEL_GREEDY, SEL_GREEDIRIS, SEL_RANDGREEDI = 0, 1, 2
 (TUNE_SAMPLE_BLOCKS, TUNE_BIG_SHAPE, TUNE_APPLY_BLOCKS, TUNE_DENSE_RATIO, TUNE_LT_BLOCKS,
- TUNE_LT_GRAB, TUNE_GRAPH) = 0, 1, 2, 3, 4, 5, 6
+ TUNE_LT_GRAB, TUNE_GRAPH, TUNE_LISTS) = 0, 1, 2, 3, 4, 5, 6, 7
 (WS_PREPARE_GRAPH, WS_SAMPLE, WS_INCIDENCE, WS_GREEDY, WS_RANDGREEDI, WS_STREAM, WS_OFFLINE,
  WS_FORWARD, WS_INFLUENCE, WS_SOLVE, WS_OPIM, WS_BATCH) = range(12)
 

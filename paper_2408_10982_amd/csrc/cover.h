@@ -48,7 +48,19 @@ struct CoverArgs {
   // rebuilds all counts instead of decrementing per member (0: never);
   // set by launch_cover
   int64_t recount_min;
+  // candidate lists of the partition argmax (nullptr: every pick scans all
+  // counts): kListCap positions per partition, their number, and the count
+  // that no position outside the list exceeds
+  int32_t* __restrict__ cand;
+  int32_t* __restrict__ cand_n;          // m
+  uint32_t* __restrict__ tau;            // m
 };
+
+// Positions a partition's candidate list holds.
+constexpr int kListCap = 1024;
+// Candidate lists are used when partitions average at most this many
+// positions (a rebuild scans one partition with one workgroup).
+constexpr int64_t kListMaxPart = (int64_t)1 << 18;
 
 // Destroys the calling thread's captured cover graphs (im_release).
 void release_cover_graphs();

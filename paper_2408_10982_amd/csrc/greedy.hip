@@ -79,6 +79,11 @@ __global__ __launch_bounds__(kGBlock) void k_cover_init(CoverArgs A) {
   const int64_t ncov = A.sbase ? A.count : (int64_t)A.m * A.count;
   for (int64_t j = gtid; j < ncov; j += gthreads) A.covered[j] = 0;
   for (int64_t j = gtid; j < (int64_t)A.m * A.k; j += gthreads) A.gmax[j] = 0ull;
+  if (A.cand)
+    for (int64_t j = gtid; j < A.m; j += gthreads) {
+      A.cand_n[j] = 0;  // an empty list: the first pick scans the partition
+      A.tau[j] = 0u;
+    }
   if (gtid == 0) *A.done = 0;
 }
 
@@ -139,6 +144,117 @@ __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
     }
     best = block_max_u64(best, red);
     if (threadIdx.x == 0 && best && !done) atomicMax(&A.gmax[(int64_t)it * A.m + p], best);
+  }
+}
+
+// Pick `it`, step 1, with candidate lists (RandGreedi): one workgroup per
+// partition.  A partition's list holds every position whose count exceeded
+// tau[p] when the list was built; counts only fall, so a position outside the
+// list stays at or below tau[p], and a list entry above tau[p] with the best
+// key is the partition's argmax (a strictly larger count than any outside).
+// Otherwise the workgroup scans the partition's counts: their argmax is the
+// pick, and the list is rebuilt from a histogram of the counts (the highest
+// bins that together hold at most kListCap positions).  A partition whose
+// counts are all 0 is marked exhausted (tau = ~0).  Same picks as the full
+// argmax pass.
+constexpr int kListBlock = kListCap;
+constexpr int kListBins = kListBlock;  // one histogram bin per thread
+static_assert(kListBins == kListBlock && kListBlock % kWave == 0, "list block shape");
+constexpr uint32_t kListExhausted = 0xFFFFFFFFu;
+constexpr int kListUnroll = 8;
+
+__global__ __launch_bounds__(kListBlock) void k_cover_pick_list(CoverArgs A, int it) {
+  __shared__ unsigned long long red[kListBlock / kWave];
+  __shared__ uint32_t hist[kListBins];
+  __shared__ uint32_t wsum[kListBlock / kWave];
+  __shared__ int32_t s_n;
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const uint32_t tau = A.tau[p];
+  // uniform: the row of gmax stays 0 (no pick)
+  if (*A.done || it >= part_k(A, p) || tau == kListExhausted) return;
+  int32_t* L = A.cand + (int64_t)p * kListCap;
+  const int32_t ln = A.cand_n[p];
+  unsigned long long best = 0ull;
+  if (tid < ln) {
+    const int32_t pos = L[tid];
+    best = argmax_key(A.cnt[pos], (uint32_t)pos);
+  }
+  best = block_max_u64(best, red);
+  if (key_count(best) > tau) {
+    if (tid == 0) A.gmax[(int64_t)it * A.m + p] = best;
+    return;
+  }
+  const int64_t lo = part_lo(A, p), hi = part_hi(A, p);
+  constexpr int64_t kStep = (int64_t)kListBlock * kListUnroll;
+  best = 0ull;
+  for (int64_t b = lo; b < hi; b += kStep) {
+    uint32_t c[kListUnroll];
+#pragma unroll
+    for (int q = 0; q < kListUnroll; ++q) {
+      const int64_t pos = b + tid + (int64_t)q * kListBlock;
+      c[q] = pos < hi ? A.cnt[pos] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kListUnroll; ++q) {
+      const int64_t pos = b + tid + (int64_t)q * kListBlock;
+      const unsigned long long key = pos < hi ? argmax_key(c[q], (uint32_t)pos) : 0ull;
+      best = key > best ? key : best;
+    }
+  }
+  best = block_max_u64(best, red);
+  const uint32_t mx = key_count(best);
+  if (mx == 0) {  // nothing left to gain here, now or later
+    if (tid == 0) {
+      A.cand_n[p] = 0;
+      A.tau[p] = kListExhausted;
+    }
+    return;
+  }
+  hist[tid] = 0u;
+  if (tid == 0) s_n = 0;
+  __syncthreads();
+  // bin of a count c in [1, mx]: floor(c * kListBins / (mx + 1))
+  for (int64_t b = lo; b < hi; b += kStep) {
+    uint32_t c[kListUnroll];
+#pragma unroll
+    for (int q = 0; q < kListUnroll; ++q) {
+      const int64_t pos = b + tid + (int64_t)q * kListBlock;
+      c[q] = pos < hi ? A.cnt[pos] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kListUnroll; ++q)
+      if (c[q] > 0u)
+        atomicAdd(&hist[(uint32_t)(((uint64_t)c[q] * kListBins) / ((uint64_t)mx + 1))], 1u);
+  }
+  __syncthreads();
+  // suffix sums of the bins; cut = number of bins whose suffix exceeds the
+  // cap (a prefix of the bins, as suffixes only fall)
+  const int w = tid / kWave;
+  const uint32_t incl = wave_inclusive_scan(hist[kListBins - 1 - tid]);
+  if (lane_id() == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t suffix = incl;
+  for (int q = 0; q < w; ++q) suffix += wsum[q];
+  const int cut = __syncthreads_count(suffix > (uint32_t)kListCap);
+  // a count is in a bin >= cut exactly when it is at least cmin
+  const uint64_t cmin = ((uint64_t)cut * ((uint64_t)mx + 1) + kListBins - 1) / kListBins;
+  const uint32_t tau2 = cmin > 0 ? (uint32_t)(cmin - 1) : 0u;
+  for (int64_t b = lo; b < hi; b += kStep) {
+    uint32_t c[kListUnroll];
+#pragma unroll
+    for (int q = 0; q < kListUnroll; ++q) {
+      const int64_t pos = b + tid + (int64_t)q * kListBlock;
+      c[q] = pos < hi ? A.cnt[pos] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kListUnroll; ++q)
+      if (c[q] > tau2) L[atomicAdd(&s_n, 1)] = (int32_t)(b + tid + (int64_t)q * kListBlock);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    A.cand_n[p] = s_n;
+    A.tau[p] = tau2;
+    A.gmax[(int64_t)it * A.m + p] = best;
   }
 }
 
@@ -593,13 +709,16 @@ __global__ void k_pos_of(int32_t n, const int32_t* __restrict__ order,
 // per wave).
 struct CoverPlan {
   unsigned init_blocks, arg_blocks, apply_blocks, agg_blocks, recount_blocks, finish_blocks;
-  bool can_recount;
+  bool can_recount, lists;
 };
 
 static void enqueue_cover(const CoverArgs& A, const CoverPlan& P, hipStream_t s) {
   k_cover_init<<<dim3(P.init_blocks), dim3(kGBlock), 0, s>>>(A);
   for (int it = 0; it < A.k; ++it) {
-    k_cover_argmax<<<dim3(P.arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
+    if (P.lists)
+      k_cover_pick_list<<<dim3((unsigned)A.m), dim3(kListBlock), 0, s>>>(A, it);
+    else
+      k_cover_argmax<<<dim3(P.arg_blocks), dim3(kGBlock), 0, s>>>(A, it);
     if (P.can_recount)
       k_cover_apply_one<<<dim3(P.agg_blocks), dim3(kAggBlock), 0, s>>>(A, it);
     else
@@ -620,12 +739,12 @@ namespace {
 struct PlanKey {
   int dev, k, m;
   unsigned init_blocks, arg_blocks, apply_blocks, agg_blocks, recount_blocks, finish_blocks;
-  bool can_recount;
+  bool can_recount, lists;
   bool operator<(const PlanKey& o) const {
     return std::tie(dev, k, m, init_blocks, arg_blocks, apply_blocks, agg_blocks, recount_blocks,
-                    finish_blocks, can_recount) <
+                    finish_blocks, can_recount, lists) <
            std::tie(o.dev, o.k, o.m, o.init_blocks, o.arg_blocks, o.apply_blocks, o.agg_blocks,
-                    o.recount_blocks, o.finish_blocks, o.can_recount);
+                    o.recount_blocks, o.finish_blocks, o.can_recount, o.lists);
   }
 };
 thread_local std::map<PlanKey, hipGraphExec_t>* t_execs = nullptr;
@@ -654,7 +773,7 @@ static int launch_captured(const CoverArgs& A, const CoverPlan& P, int dev, hipS
   }
   if (!t_execs) t_execs = new std::map<PlanKey, hipGraphExec_t>();
   const PlanKey key{dev, A.k, A.m, P.init_blocks, P.arg_blocks, P.apply_blocks, P.agg_blocks,
-                    P.recount_blocks, P.finish_blocks, P.can_recount};
+                    P.recount_blocks, P.finish_blocks, P.can_recount, P.lists};
   auto it = t_execs->find(key);
   if (it != t_execs->end()) {
     hipGraphNode_t err_node = nullptr;
@@ -702,6 +821,7 @@ int launch_cover(CoverArgs& A, hipStream_t s) {
   // over the covering subsets, 0.1 ms); the decision is taken on the device
   // from the pick's gain.  Its other picks use the aggregated apply.
   P.can_recount = A.m == 1 && !A.order && !A.pos_of && !A.sbase && !A.local_ids;
+  P.lists = A.cand != nullptr;
   A.recount_min = P.can_recount ? std::max<int64_t>(1, A.count / 64) : 0;
   bool graph = tune(IM_TUNE_GRAPH) != 0;
   if (graph) {  // a stream the caller is capturing gets the launches themselves
@@ -727,13 +847,16 @@ static size_t greedy_bytes(int32_t n, int64_t count, int32_t k) {
 
 // Scratch of one RandGreedi local step: gmax (k m) | done | pbase (m + 1) |
 // hist (m) | order, pos_of, cnt (n each) | covered (m count) | M, Moff (the
-// partition counts per chunk of kPartChunk vertices and their scan).
+// partition counts per chunk of kPartChunk vertices and their scan) | member
+// positions (total) | candidate lists (m kListCap) and their sizes and
+// thresholds (m each).
 static size_t randgreedi_bytes(int32_t n, int64_t count, int64_t total, int32_t k, int32_t m) {
   const int64_t nch = ((int64_t)n + kPartChunk - 1) / kPartChunk;
   const size_t cells = (size_t)m * (size_t)nch;
   return (size_t)m * k * 8 + 64 + 64 + (size_t)(m + 1) * 8 + (size_t)m * 4 + 64 +
          (size_t)n * 12 + (size_t)m * (size_t)count + 256 + (cells * 4 + 64) / 64 * 64 +
-         (cells + 1) * 8 + 64 + (size_t)total * 4 + 64;
+         (cells + 1) * 8 + 64 + (size_t)total * 4 + 64 + (size_t)m * kListCap * 4 +
+         (size_t)m * 8 + 128;
 }
 
 size_t ws_greedy(int32_t n, int64_t count, int32_t k) {
@@ -833,6 +956,13 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   c += (cells + 1) * 8;
   c = (char*)(((uintptr_t)c + 63) / 64 * 64);
   int32_t* mpos = (int32_t*)c;
+  c += (size_t)total * 4;
+  c = (char*)(((uintptr_t)c + 63) / 64 * 64);
+  int32_t* cand = (int32_t*)c;
+  c += (size_t)m * kListCap * 4;
+  int32_t* cand_n = (int32_t*)c;
+  c += ((size_t)m * 4 + 63) / 64 * 64;
+  uint32_t* tau = (uint32_t*)c;
   IM_HIP(hipMemsetAsync(hist, 0, (size_t)m * 4, s));
   k_part_count<<<dim3((unsigned)nch), dim3(kPartBlock), 0, s>>>(n, m, part, nch, M, hist);
   IM_HIP(hipGetLastError());
@@ -869,6 +999,11 @@ extern "C" int im_randgreedi(int32_t n, int64_t count, const int64_t* off, const
   A.pos_keys = 1;  // the partition scatter keeps each partition in ascending id order
   A.part = part;
   A.mpos = total > 0 ? mpos : nullptr;
+  if (tune(IM_TUNE_LISTS) != 0 && (int64_t)n <= (int64_t)m * kListMaxPart) {
+    A.cand = cand;
+    A.cand_n = cand_n;
+    A.tau = tau;
+  }
   A.pbase = pbase;
   A.cnt = cnt;
   A.covered = covered;

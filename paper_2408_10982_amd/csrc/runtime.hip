@@ -346,11 +346,11 @@ int exclusive_scan_u32_to_i64(const uint32_t* in, int64_t n, int64_t* out, hipSt
 }
 
 namespace {
-constexpr int kTuneKeys = 7;
-constexpr int64_t kTuneDefault[kTuneKeys] = {5, 0, 1, 256, 4, 16, 0};
-constexpr int64_t kTuneMin[kTuneKeys] = {1, 0, 1, 0, 1, 1, 0};
-constexpr int64_t kTuneMax[kTuneKeys] = {64, 2, 16, (int64_t)1 << 40, 32, 4096, 1};
-std::atomic<int64_t> g_tune[kTuneKeys] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+constexpr int kTuneKeys = 8;
+constexpr int64_t kTuneDefault[kTuneKeys] = {5, 0, 1, 256, 2, 16, 0, 1};
+constexpr int64_t kTuneMin[kTuneKeys] = {1, 0, 1, 0, 1, 1, 0, 0};
+constexpr int64_t kTuneMax[kTuneKeys] = {64, 2, 16, (int64_t)1 << 40, 32, 4096, 1, 1};
+std::atomic<int64_t> g_tune[kTuneKeys] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 }  // namespace
 
 int64_t tune(im_tune_key key) {

@@ -181,15 +181,15 @@ def test_tune_knobs_validate_and_round_trip():
         assert L.im_tune_get(key, ctypes.byref(v)) == 0
         return v.value
 
-    defaults = {0: 5, 1: 0, 2: 1, 3: 256, 4: 4, 5: 16, 6: 0}
+    defaults = {0: 5, 1: 0, 2: 1, 3: 256, 4: 2, 5: 16, 6: 0, 7: 1}
     assert {k: get(k) for k in defaults} == defaults
     for key, bad in ((0, 0), (0, 65), (1, 3), (2, 0), (2, 17), (3, -2), (4, 0), (4, 33), (5, 0),
-                     (5, 4097), (6, 2), (6, -2), (7, 1), (-1, 1)):
+                     (5, 4097), (6, 2), (6, -2), (7, 2), (7, -2), (8, 1), (-1, 1)):
         assert L.im_tune_set(key, bad) == -1, (key, bad)
     assert {k: get(k) for k in defaults} == defaults
     assert L.im_tune_get(9, ctypes.byref(v)) == -1
     assert L.im_tune_get(0, None) == -1
-    for key, good in ((0, 12), (1, 2), (2, 4), (3, 0), (4, 2), (5, 64), (6, 1)):
+    for key, good in ((0, 12), (1, 2), (2, 4), (3, 0), (4, 7), (5, 64), (6, 1), (7, 0)):
         assert L.im_tune_set(key, good) == 0
         assert get(key) == good
         assert L.im_tune_set(key, -1) == 0

@@ -350,6 +350,32 @@ def test_randgreedi(im, name, count, k, m):
     assert np.array_equal(_np(lg), olg)
 
 
+@pytest.mark.parametrize("name,count,k,m", [("rmat14_wc", 20000, 300, 2), ("rmat12", 300, 400, 3)])
+def test_randgreedi_candidate_lists(im, name, count, k, m):
+    """Partitions far larger than a candidate list (1024 positions), picks
+    deep enough that the lists are rebuilt many times and counts tie at small
+    values, and (rmat12, k = 400) partitions whose counts all reach 0: the
+    picks equal the oracle's, with the lists and with the full argmax pass."""
+    _say("randgreedi lists", name, count, k, m)
+    g = GRAPHS[name]()
+    G, r, io, imem, o, oio, oim = _pipeline(im, g, count, 61)
+    opart = O.partition(g.n, m, 5003)
+    ols, olg, olc, olv = O.local_greedy(g.n, count, oio, oim, opart, m, k)
+    try:
+        for lists in (1, 0):
+            im.tune_set(im.TUNE_LISTS, lists)
+            part, ls, lg, lc, lv = im.randgreedi(g.n, r, io, imem, k, m, part_seed=5003)
+            assert np.array_equal(_np(part), opart)
+            assert np.array_equal(_np(lc), olc), lists
+            assert np.array_equal(_np(lv), olv), lists
+            assert np.array_equal(_np(ls), ols), lists
+            assert np.array_equal(_np(lg), olg), lists
+    finally:
+        im.tune_set(im.TUNE_LISTS, -1)
+    if name == "rmat12":
+        assert (olc < k).all()  # every partition ran out of gain
+
+
 @pytest.mark.parametrize("name,count,k,m,delta,alpha", [
     ("ic_dense", 2000, 10, 4, 0.077, 1.0), ("lt_small", 6000, 20, 8, 0.1, 0.25),
     ("rmat12", 16384, 16, 64, 0.077, 1.0), ("rmat12", 16384, 16, 64, 0.077, 0.125),
