@@ -261,7 +261,10 @@ __global__ __launch_bounds__(kListBlock) void k_cover_pick_list(CoverArgs A, int
 // Pick `it`, step 2: record the picks, cover their covering subsets, and
 // decrement the counts of the members of every newly covered sample.  Each
 // wavefront takes kApplyEntries consecutive entries of the picks' subsets; a
-// newly covered sample is then walked by the whole wavefront.
+// newly covered sample is then walked by the whole wavefront (one sample
+// after another: walking the fresh samples of a chunk together, each lane
+// finding its sample by a search over the prefix sums of their sizes,
+// measured slower).
 // One of the first kRecountPicks picks whose gain reaches recount_min
 // (one-partition covers only): mark its samples covered and zero every count;
 // k_cover_recount, launched for exactly those picks, then rebuilds them.
@@ -270,11 +273,14 @@ __device__ __forceinline__ bool recount_pick(const CoverArgs& A, int it) {
          (int64_t)key_count(A.gmax[it]) >= A.recount_min;
 }
 
+
 __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it) {
   __shared__ unsigned long long pbest[kMaxParts];
   __shared__ int64_t pre[kMaxParts + 1];
   __shared__ int64_t part_scan[kApplyBlock / kWave + 1];
-  __shared__ int64_t ppos[kMaxParts];  // count position of each partition's pick
+  __shared__ int64_t ppos[kMaxParts];    // count position of each partition's pick
+  __shared__ int64_t pstart[kMaxParts];  // where its covering subset starts
+  __shared__ int64_t plo[kMaxParts], phi[kMaxParts];  // the partition's positions
   __shared__ uint32_t pvert[kMaxParts];  // its vertex
   const int tid = threadIdx.x, lane = lane_id();
   const int m = A.m;
@@ -285,13 +291,18 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   int64_t sz = 0;
   if (tid < m) {
     const unsigned long long b = it < part_k(A, tid) ? gm[tid] : 0ull;
+    plo[tid] = part_lo(A, tid);
+    phi[tid] = part_hi(A, tid);
     pbest[tid] = b;
     ppos[tid] = -1;
+    pstart[tid] = 0;
     pvert[tid] = 0u;
     if (key_count(b) > 0) {
       const uint32_t x = key_vertex(b);
       const uint32_t v = A.pos_keys ? (uint32_t)A.order[x] : x;
-      sz = A.inc_off[v + 1] - A.inc_off[v];
+      const int64_t s0 = A.inc_off[v];
+      sz = A.inc_off[v + 1] - s0;
+      pstart[tid] = s0;
       ppos[tid] = A.pos_keys ? (int64_t)x : (A.pos_of ? (int64_t)A.pos_of[v] : (int64_t)v);
       pvert[tid] = v;
     }
@@ -326,7 +337,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
       const unsigned long long b = pbest[p];
       if (key_count(b) > 0) {
         const int64_t v = pvert[p];
-        A.seeds[part_out(A, p) + it] = (int32_t)(A.local_ids ? v - part_lo(A, p) : v);
+        A.seeds[part_out(A, p) + it] = (int32_t)(A.local_ids ? v - plo[p] : v);
         A.gains[part_out(A, p) + it] = (int64_t)key_count(b);
         // every sample of S(v*) ends up covered, so the pick's own count
         // becomes 0; it is stored once here and skipped in the member walks
@@ -338,12 +349,11 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
   const int64_t gtid = (int64_t)blockIdx.x * kApplyBlock + tid;
   if (!decrement)
     for (int64_t pos = gtid; pos < A.n; pos += (int64_t)gridDim.x * kApplyBlock) A.cnt[pos] = 0u;
-  const int64_t nchunks = (tot + kApplyEntries - 1) / kApplyEntries;
   const int64_t wid = gtid / kWave, nw = (int64_t)gridDim.x * kApplyBlock / kWave;
+  const int64_t nchunks = (tot + kApplyEntries - 1) / kApplyEntries;
   for (int64_t c = wid; c < nchunks; c += nw) {
     const int64_t f = c * kApplyEntries + lane;
     int p = 0;
-    int32_t smp = -1;
     bool fresh = false;
     int64_t ma = 0, mb = 0;  // the sample's member range, loaded with its flag
     if (lane < kApplyEntries && f < tot) {
@@ -356,8 +366,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
           hi = mid - 1;
       }
       p = lo;
-      const uint32_t v = pvert[p];
-      smp = A.inc_mem[A.inc_off[v] + (f - pre[p])];
+      const int32_t smp = A.inc_mem[pstart[p] + (f - pre[p])];
       // flag index: a global sample position when each partition owns its
       // own samples, else one flag array per partition over all samples
       const int64_t fi = A.sbase ? A.sbase[p] + smp : (int64_t)p * A.count + smp;
@@ -377,22 +386,20 @@ __global__ __launch_bounds__(kApplyBlock) void k_cover_apply(CoverArgs A, int it
     while (todo) {
       const int src = __ffsll(todo) - 1;
       todo &= todo - 1;
-      const int s_p = __shfl(p, src, kWave);
-      const int64_t lo_p = part_lo(A, s_p), hi_p = part_hi(A, s_p);
-      const int64_t skip = ppos[s_p];
+      const int q = __shfl(p, src, kWave);
       const int64_t a = __shfl(ma, src, kWave), b = __shfl(mb, src, kWave);
       for (int64_t t = a + lane; t < b; t += kWave) {
         // RandGreedi: only members of the covering partition lose a count;
         // their count positions, stored beside the members, say which
         if (A.mpos) {
           const int64_t pos = A.mpos[t];
-          if (pos >= lo_p && pos < hi_p && pos != skip) atomicSub(&A.cnt[pos], 1u);
+          if (pos >= plo[q] && pos < phi[q] && pos != ppos[q]) atomicSub(&A.cnt[pos], 1u);
           continue;
         }
         const int32_t u = A.mem[t];
-        if (A.part && A.part[u] != (uint8_t)s_p) continue;
-        const int64_t pos = A.local_ids ? lo_p + u : (A.pos_of ? A.pos_of[u] : u);
-        if (pos >= lo_p && pos < hi_p && pos != skip) atomicSub(&A.cnt[pos], 1u);
+        if (A.part && A.part[u] != (uint8_t)q) continue;
+        const int64_t pos = A.local_ids ? plo[q] + u : (A.pos_of ? A.pos_of[u] : u);
+        if (pos >= plo[q] && pos < phi[q] && pos != ppos[q]) atomicSub(&A.cnt[pos], 1u);
       }
     }
   }
