@@ -1437,17 +1437,36 @@ __device__ __forceinline__ bool list_has(const int32_t* Ls, int32_t len, int32_t
   return hit;
 }
 
+// Second membership filter of a walk, 32 words per lane in LDS, hashed with
+// another multiplier than the register filter: it is read only when the
+// register filter has the bit, and a clear bit again proves the vertex new.
+#ifndef IM_LT_BLOOM2
+#define IM_LT_BLOOM2 1
+#endif
+#ifndef IM_LT_BLOOM2_BITS
+#define IM_LT_BLOOM2_BITS 10
+#endif
+constexpr int kLtBloom2Words = (1 << IM_LT_BLOOM2_BITS) / 32;
+
+__device__ __forceinline__ uint32_t bloom2_bit(int32_t u) {
+  return ((uint32_t)u * 0x85EBCA6Bu) >> (32 - IM_LT_BLOOM2_BITS);
+}
+
 // One lane per walk.  Lanes take new samples as their walks end (aggregated
 // per wave), so a long walk does not hold up the other 63 lanes.  Resident
 // wavefronts per SIMD (IM_LT_WAVES): the compiler keeps the registers within
 // what that many need.
 #ifndef IM_LT_WAVES
-#define IM_LT_WAVES 4
+#define IM_LT_WAVES 3
 #endif
 __global__ __launch_bounds__(kLtBlock) __attribute__((amdgpu_waves_per_eu(IM_LT_WAVES)))
 void k_sample_lt(SampleArgs A, int32_t* lane_list) {
   const size_t gl = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t* Ls = lane_list + gl * kLtCap;
+#if IM_LT_BLOOM2
+  __shared__ uint32_t s_f2[kLtBlock * kLtBloom2Words];
+  uint32_t* F2 = s_f2 + (size_t)threadIdx.x * kLtBloom2Words;  // this lane's
+#endif
   const int lane = lane_id();
   const uint64_t below = (1ull << lane) - 1ull;
   bool have = false, done = false;
@@ -1486,6 +1505,15 @@ void k_sample_lt(SampleArgs A, int32_t* lane_list) {
           v = (int32_t)scale_draw(draw1(seed, kTagRoot, G.stream, 0u, i), G.n);
           bl = Bloom{0ull, 0ull, 0ull, 0ull};
           bloom_add(bl, bloom_bit(v));
+#if IM_LT_BLOOM2
+#pragma unroll
+          for (int q = 0; q < kLtBloom2Words / 4; ++q)
+            reinterpret_cast<uint4*>(F2)[q] = make_uint4(0u, 0u, 0u, 0u);
+          {
+            const uint32_t h2 = bloom2_bit(v);
+            F2[h2 >> 5] |= 1u << (h2 & 31u);
+          }
+#endif
           Ls[0] = v;
           len = 1;
           s_ex = s_lv = 0;
@@ -1513,7 +1541,12 @@ void k_sample_lt(SampleArgs A, int32_t* lane_list) {
           ++s_lv;
           h = bloom_bit(u);
           cand = true;
+#if IM_LT_BLOOM2
+          const uint32_t h2 = bloom2_bit(u);
+          if (bloom_has(bl, h) && ((F2[h2 >> 5] >> (h2 & 31u)) & 1u)) {
+#else
           if (bloom_has(bl, h)) {
+#endif
             if (len <= kLtOwnScan)
               seen = list_has(Ls, len, u);
             else
@@ -1557,6 +1590,12 @@ void k_sample_lt(SampleArgs A, int32_t* lane_list) {
         over = true;
       } else {
         bloom_add(bl, h);
+#if IM_LT_BLOOM2
+        {
+          const uint32_t h2 = bloom2_bit(u);
+          F2[h2 >> 5] |= 1u << (h2 & 31u);
+        }
+#endif
         Ls[len++] = u;
         v = u;
       }
