@@ -1401,21 +1401,23 @@ __device__ __forceinline__ uint32_t bloom_bit(int32_t u) {
   return ((uint32_t)u * 0x9E3779B1u) >> 24;
 }
 
+// Masked updates of all four words, so that the filter stays in registers
+// (a selected word becomes an indexed private array in scratch memory).
 __device__ __forceinline__ bool bloom_has(const Bloom& b, uint32_t h) {
-  const uint64_t w = h < 128u ? (h < 64u ? b.w0 : b.w1) : (h < 192u ? b.w2 : b.w3);
-  return ((w >> (h & 63u)) & 1ull) != 0ull;
+  const uint64_t m = 1ull << (h & 63u);
+  const uint32_t q = h >> 6;
+  const uint64_t hit = (b.w0 & (q == 0u ? m : 0ull)) | (b.w1 & (q == 1u ? m : 0ull)) |
+                       (b.w2 & (q == 2u ? m : 0ull)) | (b.w3 & (q == 3u ? m : 0ull));
+  return hit != 0ull;
 }
 
 __device__ __forceinline__ void bloom_add(Bloom& b, uint32_t h) {
   const uint64_t m = 1ull << (h & 63u);
-  if (h < 64u)
-    b.w0 |= m;
-  else if (h < 128u)
-    b.w1 |= m;
-  else if (h < 192u)
-    b.w2 |= m;
-  else
-    b.w3 |= m;
+  const uint32_t q = h >> 6;
+  b.w0 |= q == 0u ? m : 0ull;
+  b.w1 |= q == 1u ? m : 0ull;
+  b.w2 |= q == 2u ? m : 0ull;
+  b.w3 |= q == 3u ? m : 0ull;
 }
 
 // Is u among the first len (<= kLtOwnScan) entries of the lane's list
