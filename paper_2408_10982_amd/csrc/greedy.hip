@@ -162,9 +162,17 @@ __global__ __launch_bounds__(kGBlock) void k_cover_argmax(CoverArgs A, int it) {
 // bins that together hold at most kListCap positions).  A partition whose
 // counts are all 0 is marked exhausted (tau = ~0).  Same picks as the full
 // argmax pass.
-constexpr int kListBlock = kListCap;
-constexpr int kListBins = kListBlock;  // one histogram bin per thread
-static_assert(kListBins == kListBlock && kListBlock % kWave == 0, "list block shape");
+// Threads of a list workgroup (each holds kListCap / kListBlock entries):
+// 256, 512 and 1024 measured within noise with four solves in flight, 512
+// fastest on one stream (local greedy 7.66 against 7.84-7.86 ms).
+#ifndef IM_LIST_BLOCK
+#define IM_LIST_BLOCK 512
+#endif
+constexpr int kListBlock = IM_LIST_BLOCK;
+constexpr int kListBins = kListCap;  // histogram bins of a rebuild
+constexpr int kListPer = kListCap / kListBlock;  // list entries per thread
+constexpr int kBinsPer = kListBins / kListBlock;  // bins per thread
+static_assert(kListCap % kListBlock == 0 && kListBlock % kWave == 0, "list block shape");
 constexpr uint32_t kListExhausted = 0xFFFFFFFFu;
 constexpr int kListUnroll = 8;
 
@@ -172,6 +180,7 @@ __global__ __launch_bounds__(kListBlock) void k_cover_pick_list(CoverArgs A, int
   __shared__ unsigned long long red[kListBlock / kWave];
   __shared__ uint32_t hist[kListBins];
   __shared__ uint32_t wsum[kListBlock / kWave];
+  __shared__ int32_t csum[kListBlock / kWave];
   __shared__ int32_t s_n;
   const int p = blockIdx.x, tid = threadIdx.x;
   const uint32_t tau = A.tau[p];
@@ -180,9 +189,21 @@ __global__ __launch_bounds__(kListBlock) void k_cover_pick_list(CoverArgs A, int
   int32_t* L = A.cand + (int64_t)p * kListCap;
   const int32_t ln = A.cand_n[p];
   unsigned long long best = 0ull;
-  if (tid < ln) {
-    const int32_t pos = L[tid];
-    best = argmax_key(A.cnt[pos], (uint32_t)pos);
+  {
+    int32_t pos[kListPer];
+    uint32_t cv[kListPer];
+#pragma unroll
+    for (int r = 0; r < kListPer; ++r) {
+      const int j = tid + r * kListBlock;
+      pos[r] = j < ln ? L[j] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < kListPer; ++r) cv[r] = pos[r] >= 0 ? A.cnt[pos[r]] : 0u;
+#pragma unroll
+    for (int r = 0; r < kListPer; ++r) {
+      const unsigned long long key = pos[r] >= 0 ? argmax_key(cv[r], (uint32_t)pos[r]) : 0ull;
+      best = key > best ? key : best;
+    }
   }
   best = block_max_u64(best, red);
   if (key_count(best) > tau) {
@@ -215,7 +236,8 @@ __global__ __launch_bounds__(kListBlock) void k_cover_pick_list(CoverArgs A, int
     }
     return;
   }
-  hist[tid] = 0u;
+#pragma unroll
+  for (int r = 0; r < kBinsPer; ++r) hist[tid + r * kListBlock] = 0u;
   if (tid == 0) s_n = 0;
   __syncthreads();
   // bin of a count c in [1, mx]: floor(c * kListBins / (mx + 1))
@@ -232,16 +254,36 @@ __global__ __launch_bounds__(kListBlock) void k_cover_pick_list(CoverArgs A, int
         atomicAdd(&hist[(uint32_t)(((uint64_t)c[q] * kListBins) / ((uint64_t)mx + 1))], 1u);
   }
   __syncthreads();
-  // suffix sums of the bins; cut = number of bins whose suffix exceeds the
-  // cap (a prefix of the bins, as suffixes only fall)
+  // suffix sums of the bins (the sum over a bin and all above it), highest
+  // bin first, thread t holding kBinsPer consecutive ones; cut = number of
+  // bins whose suffix exceeds the cap
   const int w = tid / kWave;
-  const uint32_t incl = wave_inclusive_scan(hist[kListBins - 1 - tid]);
+  uint32_t hv[kBinsPer];
+  uint32_t tsum = 0;
+#pragma unroll
+  for (int r = 0; r < kBinsPer; ++r) {
+    hv[r] = hist[kListBins - 1 - (kBinsPer * tid + r)];
+    tsum += hv[r];
+  }
+  const uint32_t incl = wave_inclusive_scan(tsum);
   if (lane_id() == kWave - 1) wsum[w] = incl;
   __syncthreads();
-  uint32_t suffix = incl;
-  for (int q = 0; q < w; ++q) suffix += wsum[q];
-  const int cut = __syncthreads_count(suffix > (uint32_t)kListCap);
-  // a count is in a bin >= cut exactly when it is at least cmin
+  uint32_t run = incl - tsum;
+  for (int q = 0; q < w; ++q) run += wsum[q];
+  int32_t over = 0;
+#pragma unroll
+  for (int r = 0; r < kBinsPer; ++r) {
+    run += hv[r];
+    over += run > (uint32_t)kListCap ? 1 : 0;
+  }
+  over = wave_sum(over);
+  if (lane_id() == 0) csum[w] = over;
+  __syncthreads();
+  int cut = 0;
+  for (int q = 0; q < kListBlock / kWave; ++q) cut += csum[q];
+  // the bins whose suffix exceeds the cap are bins 0 .. cut-1; the list
+  // keeps bins >= cut, and a count is in a bin >= cut exactly when it is at
+  // least cmin
   const uint64_t cmin = ((uint64_t)cut * ((uint64_t)mx + 1) + kListBins - 1) / kListBins;
   const uint32_t tau2 = cmin > 0 ? (uint32_t)(cmin - 1) : 0u;
   for (int64_t b = lo; b < hi; b += kStep) {
