@@ -36,7 +36,7 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   std::vector<int64_t> sb(nt + 1), vb(nt + 1), ko(nt);
   std::vector<int32_t> kp(nt);
   int64_t S = 0, V = 0, K = out_base;
-  int32_t max_n = 1, max_k = 1;
+  int32_t max_n = 1, max_k = 1, model = IM_IC;
   for (int t = 0; t < nt; ++t) {
     const im_task& q = tasks[t];
     sb[t] = S;
@@ -49,6 +49,7 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
     K += q.k;
     max_n = std::max(max_n, q.graph.n);
     max_k = std::max(max_k, q.k);
+    if (q.graph.model == IM_LT) model = IM_LT;
   }
   sb[nt] = S;
   vb[nt] = V;
@@ -93,7 +94,13 @@ static int batch_chunk(const im_task* tasks, int32_t nt, int64_t out_base, int32
   ArenaRun R;
   IM_HIP(hipEventRecord(ev[0], s));
   const int rc = sample_to_arena(td.data(), nt, S, max_n, off, last_total, 0, true, false, &R, s);
-  if (R.total > 0) last_total = R.total;
+  if (R.total > 0) {
+    last_total = R.total;
+    // with the member total known, a workspace too small for the rest of the
+    // call is reported with the size of the whole call, so that the caller
+    // grows it once instead of once per stage (each growth repeats the call)
+    scratch_need_whole(ws_batch(di.num_cus, nt, S, V, R.total, max_n, max_k, model, false));
+  }
   IM_TRY(rc);
   const int64_t total = R.total;
   void* mp = nullptr;

@@ -215,6 +215,11 @@ void scratch_need(size_t more) {
   if (c) t_need = std::max(t_need, std::max(c->peak, c->top + more));
 }
 
+void scratch_need_whole(size_t bytes) {
+  const WsCtx* c = t_ws;
+  if (c && c->cap < bytes) t_need = std::max(t_need, bytes);
+}
+
 void scratch_wish(size_t more) {
   const WsCtx* c = t_ws;
   if (c) t_want = std::max(t_want, std::max(c->peak, c->top + more));
