@@ -20,6 +20,10 @@
 
 namespace im {
 
+// Records that the whole call needs `bytes`, if the workspace is smaller
+// (defined with the other workspace bookkeeping in runtime.hip).
+void scratch_need_whole(size_t bytes);
+
 // tables | off | inc_off | cnt | covered | gmax | done
 static size_t batch_bytes(int32_t nt, int64_t S, int64_t V, int32_t max_k) {
   const size_t tab = (size_t)(nt + 1) * 16 + (size_t)nt * 12 + 256;

@@ -252,8 +252,6 @@ size_t scratch_room();
 size_t scratch_largest();
 // Records that the call needs `more` bytes beyond its highest region.
 void scratch_need(size_t more);
-// Records that the whole call needs `bytes`, if the workspace is smaller.
-void scratch_need_whole(size_t bytes);
 // Records that `more` bytes beyond the highest region would have let the
 // call take a faster launch shape (reported by im_workspace_need).
 void scratch_wish(size_t more);
