@@ -36,7 +36,12 @@
  *    returned before any device work is enqueued or any output is written.
  *  - Calls that share one stream run in order.  Calls on different streams
  *    may overlap when they are given different workspaces; they must not
- *    write the same caller buffers.
+ *    write the same caller buffers.  Their kernels run side by side only if
+ *    the streams sit on different hardware queues: HIP gives a stream its
+ *    queue on first use, and past GPU_MAX_HW_QUEUES queues (HIP's default 4)
+ *    streams share them and run one after the other, so a process that
+ *    overlaps solves sets that variable above its stream count before HIP
+ *    starts.
  *  - All arithmetic on the device is integer.  The only floating-point steps
  *    (IMM sample-size bounds, streaming bucket thresholds) run on the host in
  *    fp64 with a fixed operation order.
