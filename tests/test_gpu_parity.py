@@ -6,6 +6,8 @@ partitions, local solutions, streamed solutions and IMM sample counts.
 Both sides run on the same seeded synthetic inputs; neither sees the other's
 outputs.
 """
+import threading
+
 import numpy as np
 import pytest
 import torch
@@ -598,6 +600,74 @@ def test_workspace_minimum_and_short(im):
     assert rc == B.IM_OK and tries >= 2
     assert list(seeds)[:res.nsel] == exp["seeds"].tolist()
     assert res.coverage == exp["coverage"] and res.theta == exp["theta"]
+
+
+def test_batch_workspace_grows_once(im):
+    """A batched call through the C ABI, started with a 1 MiB workspace and
+    grown to what im_workspace_need reports after each IM_ENOMEM: the first
+    report is the call's minimum, and once sampling knows the member total
+    the next one is the size of the whole call, so at most two growths are
+    needed; the seeds, gains and coverage equal the oracle's per task."""
+    import ctypes as C
+    from paper_2408_10982_amd import binding as B
+    L = B.lib()
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    specs = [(W.random_small_graph(3000, 12000, seed=21, p_hi=0.5), 901, 12, 1500),
+             (GRAPHS["lt_small"](), 902, 20, 3000),
+             (W.random_small_graph(5000, 15000, seed=22, p_hi=0.3), 903, 8, 2500),
+             (GRAPHS["ic_dense"](), 904, 10, 1200)]
+    _say("batch workspace growth", len(specs))
+    preps = [_prep(im, g) for g, *_ in specs]
+    nt = len(specs)
+    arr = (B._Task * nt)()
+    for j, ((g, seed, k, theta), G) in enumerate(zip(specs, preps)):
+        arr[j] = B._Task(G.struct(), seed, 0, k, theta)
+    K = sum(k for _, _, k, _ in specs)
+    seeds = torch.empty(K, dtype=torch.int32, device="cuda")
+    gains = torch.empty(K, dtype=torch.int64, device="cuda")
+    nsel = torch.empty(nt, dtype=torch.int32, device="cuda")
+    cov = torch.empty(nt, dtype=torch.int64, device="cuda")
+    st = B._BatchStats()
+    out = {}
+
+    def calls():  # a fresh thread: no member total remembered from earlier batches
+        try:
+            ws_bytes, grown, rc = 1 << 20, [], None
+            for _ in range(4):
+                ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+                rc = L.im_solve_batch(arr, nt, _ptr(seeds), _ptr(gains), _ptr(nsel), _ptr(cov),
+                                      C.byref(st), _ptr(ws), ws_bytes, s)
+                torch.cuda.synchronize()
+                if rc != B.IM_ENOMEM:
+                    break
+                need = B.workspace_need()[0]
+                grown.append((ws_bytes, need))
+                if need <= ws_bytes:
+                    break
+                ws_bytes = need
+                del ws
+            out["rc"], out["grown"] = rc, grown
+        except BaseException as e:  # noqa: BLE001 -- re-raised below
+            out["err"] = e
+
+    th = threading.Thread(target=calls)
+    th.start()
+    th.join()
+    if "err" in out:
+        raise out["err"]
+    assert out["rc"] == B.IM_OK and 1 <= len(out["grown"]) <= 2, out
+    assert all(need > have for have, need in out["grown"]), out
+    s_h, g_h, n_h, c_h = _np(seeds), _np(gains), _np(nsel), _np(cov)
+    o = 0
+    for j, (g, seed, k, theta) in enumerate(specs):
+        r = O.sample(g.model, g.in_off, g.in_src, _oracle_thr(g), seed, 0, 0, theta)
+        io, imem = O.incidence(g.n, r)
+        es, eg, ec = O.greedy(g.n, theta, io, imem, k, lazy=True)
+        n = int(n_h[j])
+        assert n == len(es) and np.array_equal(s_h[o:o + n], es), j
+        assert np.array_equal(g_h[o:o + n], np.asarray(eg)[:n]), j
+        assert int(c_h[j]) == ec, j
+        o += k
 
 
 @pytest.mark.parametrize("name,k,eps,selector,cap", [
