@@ -50,3 +50,16 @@ def test_admission_counts_resident_bytes():
     assert A.pop(held=60) is None          # 60 + 30 + 30 > 100
     assert A.pop(held=30)[0] == 1          # 30 + 30 + 30 <= 100
     assert A.pop(held=30) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more it exits with status 2 and
+    says so, before any GPU work."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "single MI355X" in r.stderr and "--gpus 2" in r.stderr
